@@ -1,0 +1,192 @@
+/*
+ * sgn.h -- C ABI of libsgn, the MI355X (gfx950) hot path of Sparse
+ * Gauss-Newton sensitivity analysis (Zehnder, Coros, Thomaszewski,
+ * "Sparse Gauss-Newton for Accelerated Sensitivity Analysis", ACM TOG 2021).
+ *
+ * Problem (Sec. 3, eq. optProb): min_{x,p} f(x, p) s.t. c(x, p) = 0 with
+ * n_c = n_x and dc/dx of full rank.  Here c is static force balance of a
+ * linear-simplex neo-Hookean mesh, c = dPi/dx, Pi = sum_e E_e(x, p) - f_ext^T x,
+ * and f is the least-squares objective of eq. leastSquaresObjective plus a
+ * Tikhonov term:  f = w/2 sum_{i in T} ((x_i - t_i)/ell)^2 + mu/2 |p - p_ref|^2,
+ * so A = (w/ell^2) I_T, B = 0, C = mu I in eq. reducedGN.
+ *
+ * Each Gauss-Newton iteration solves the sparse symmetric indefinite system
+ * of eq. sparseSystemGN,
+ *     [ A  B^T  Kx^T ] [dx  ]   [  0 ]
+ *     [ B  C    Kp^T ] [dp  ] = [ -g ]      Kx = dc/dx, Kp = dc/dp,
+ *     [ Kx Kp   0    ] [dlam]   [  0 ]      g = df/dp^T + Kp^T lam_adj,
+ * whose dp equals the dense Gauss-Newton step H dp = -g exactly (Sec. 4,
+ * Appendix A Theorem 1).  x(p) comes from a forward Newton solve with
+ * monotone backtracking (Sec. 5, "Computing Equilibrium States").
+ *
+ * Conventions
+ *  - Ownership: the library never allocates device memory.  sgn_create does
+ *    host work only (it copies the problem and runs the symbolic analysis);
+ *    the caller allocates sgn_workspace_size() bytes of device memory and
+ *    hands it over with sgn_set_workspace(), which uploads the symbolic
+ *    tables.  Every other device buffer is caller-owned and must stay valid
+ *    until the call returns (calls that fill an *_info struct or a host
+ *    scalar synchronise the context's stream before returning).
+ *  - Pointers named d_* are device pointers, h_* host pointers.
+ *  - Layouts at the boundary are FP64 whatever the internal precision:
+ *      x    [n_x]  free nodes in ascending node id, dim components each;
+ *      p    [n_p]  log-modulus: element order; rest positions / nodal
+ *                  forces: same layout as x;
+ *      sol  [N]    N = 2 n_x + n_p, block order [dx; dp; dlam] (eq.
+ *                  sparseSystemGN).
+ *  - Errors: every call returns an sgn_status; nothing is thrown across the
+ *    ABI and nothing aborts.  A non-OK status is sticky on the context
+ *    (later calls return SGN_E_STATE) and sgn_last_error() gives a message.
+ *    HIP runtime failures map to SGN_E_HIP.
+ *  - Streams: all device work of a context runs on the stream given at
+ *    create (a hipStream_t passed as void*; NULL = the null stream).  One
+ *    context per stream; distinct contexts are independent.
+ */
+#ifndef SGN_H
+#define SGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgn_ctx_s* sgn_ctx;
+
+typedef enum {
+  SGN_OK = 0,
+  SGN_E_ARG = 1,        /* invalid argument or problem data */
+  SGN_E_STATE = 2,      /* call out of order, or an earlier error is pending */
+  SGN_E_NOMEM = 3,      /* host allocation failed, or workspace too small */
+  SGN_E_HIP = 4,        /* a HIP runtime call failed */
+  SGN_E_NEWTON = 5,     /* equilibrium did not converge in max_newton steps */
+  SGN_E_INVERTED = 6,   /* the given state has an inverted element (J <= 0) */
+  SGN_E_PIVOT = 7,      /* factorisation met a zero pivot or wrong inertia */
+  SGN_E_REFINE = 8,     /* refinement did not reach solve_rtol in max_ir sweeps */
+  SGN_E_LINESEARCH = 9  /* outer line search failed after max_halvings */
+} sgn_status;
+
+/* parameter kinds */
+enum { SGN_P_LOGE = 0, SGN_P_REST_POS = 1, SGN_P_NODAL_FORCE = 2 };
+/* internal factor precision of the saddle-point system */
+enum { SGN_FP64 = 0, SGN_FP32_IR = 1 };
+/* linear solver of the saddle-point system */
+enum { SGN_LDLT = 0, SGN_MINRES_LEARNED = 1 };
+/* right-hand side of the step: [0; -g; 0] (eq. sparseSystemGN) or the KKT
+ * form [-df/dx^T; -df/dp^T; 0] (Appendix A), which gives the same dp and a
+ * multiplier block shifted by the adjoint multiplier */
+enum { SGN_RHS_ADJOINT = 0, SGN_RHS_KKT = 1 };
+/* which system sgn_get_symbolic / sgn_get_sizes describe */
+enum { SGN_SYS_SGN = 0, SGN_SYS_KX = 1 };
+
+/* Problem data (host pointers; copied by sgn_create, caller keeps ownership). */
+typedef struct {
+  int dim;                      /* 2 (plane strain, unit thickness) or 3 */
+  int n_nodes, n_elems;
+  const double* rest_pos;       /* [n_nodes*dim] */
+  const int32_t* elems;         /* [n_elems*(dim+1)] positively oriented simplices */
+  const int32_t* node_grid;     /* [n_nodes*dim] integer grid coordinates (ordering) */
+  const uint8_t* fixed;         /* [n_nodes] 1 = Dirichlet on all components */
+  const double* f_ext;          /* [n_nodes*dim] dead nodal loads */
+  double E0, nu;                /* neo-Hookean: E_e = E0 exp(p_e) for SGN_P_LOGE */
+  int param_kind;               /* SGN_P_* */
+  int n_targets;
+  const int32_t* target_dof;    /* [n_targets] indices into x */
+  const double* target_val;     /* [n_targets] (may be NULL until sgn_set_targets) */
+  double target_w, length_scale, reg_mu;
+  const double* p_ref;          /* [n_p] Tikhonov reference */
+} sgn_problem;
+
+typedef struct {
+  int precision;                /* SGN_FP64 | SGN_FP32_IR */
+  int solver;                   /* SGN_LDLT | SGN_MINRES_LEARNED */
+  int rhs_kind;                 /* SGN_RHS_ADJOINT | SGN_RHS_KKT */
+  double newton_rtol;           /* |c|_2 <= newton_rtol |f_ext|_2 (+ newton_atol) */
+  double newton_atol;
+  double solve_rtol;            /* equilibrated residual |S(b - K z)|_2 / |S b|_2 */
+  double eps_x, eps_lambda;     /* optional diagonal stabilisation (Sec. 5), default 0 */
+  int max_newton, max_ir, max_minres, max_halvings;
+} sgn_options;
+
+typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;
+typedef struct {
+  int64_t n_pos, n_neg, n_zero; /* inertia counted from D */
+  int64_t n_perturbed;          /* tiny pivots replaced */
+  double min_abs_pivot;
+  double flops;                 /* dense front work executed */
+  double ms;                    /* wall time of the call */
+} sgn_factor_info;
+typedef struct {
+  int sweeps;                   /* refinement sweeps or MINRES iterations */
+  int fallback;                 /* MINRES fell back to the exact LDL^T */
+  double rel_res;               /* equilibrated relative residual (solve_rtol measure) */
+  double raw_rel_res;           /* |b - K z|_2 / |b|_2 on the unscaled matrix */
+  double ms;
+} sgn_solve_info;
+typedef struct {
+  double alpha, f0, f1, grad_norm, gtdp;
+  int halvings, newton_iters;
+  double ms_rhs, ms_assemble, ms_factor, ms_solve, ms_linesearch;
+  sgn_solve_info solve;
+} sgn_step_info;
+
+/* Validate the problem, copy it, run the host symbolic analysis of both the
+ * saddle-point system and the Kx system (nested-dissection order, permuted
+ * lower CSR, elimination tree, supernodes, slot maps).  No device work. */
+sgn_status sgn_create(const sgn_problem* prob, const sgn_options* opt, void* stream, sgn_ctx* out);
+/* Fill *opt with the defaults. */
+void sgn_default_options(sgn_options* opt);
+/* Device bytes the context needs (fronts, CSR values, element buffers, vectors). */
+sgn_status sgn_workspace_size(sgn_ctx ctx, size_t* bytes);
+/* Hand over caller-owned device memory (256-byte aligned, >= workspace size)
+ * and upload the symbolic tables.  Synchronises the stream. */
+sgn_status sgn_set_workspace(sgn_ctx ctx, void* d_ws, size_t bytes);
+/* Replace target values and the frozen length scale ell (host arrays). */
+sgn_status sgn_set_targets(sgn_ctx ctx, const double* h_target_val, double length_scale);
+/* Forward simulation x(p): Newton on c(x, p) = 0 with backtracking on Pi and
+ * an inversion guard (Sec. 5).  d_x is the initial guess on entry and x(p) on
+ * exit.  Leaves a factorisation of Kx(x(p)) for the adjoint right-hand side. */
+sgn_status sgn_equilibrium(sgn_ctx ctx, const double* d_p, double* d_x, sgn_eq_info* info);
+/* Assemble K_SGN (eq. sparseSystemGN) at (x, p) from per-element blocks and,
+ * when d_rhs != NULL, the right-hand side [N] in block order (adjoint form:
+ * g from one solve with the Kx factor, eq. totalGradient; KKT form: no solve).
+ * d_grad [n_p] (optional) receives g (adjoint form only); h_obj (optional)
+ * receives f(x, p).  (x, p) must be an equilibrium for the adjoint form. */
+sgn_status sgn_assemble(sgn_ctx ctx, const double* d_x, const double* d_p,
+                        double* d_rhs, double* d_grad, double* h_obj);
+/* Supernodal LDL^T of the assembled K_SGN (Bunch-Kaufman pivots restricted
+ * to each mesh node's variable group).  Checks the inertia (n_x+n_p, n_x, 0). */
+sgn_status sgn_factor(sgn_ctx ctx, sgn_factor_info* info);
+/* Solve K_SGN sol = rhs with the current factor plus FP64 iterative
+ * refinement to solve_rtol (both device arrays, [N], block order). */
+sgn_status sgn_solve(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_info* info);
+/* One outer iteration: assemble + factor + solve for the step, then
+ * backtracking p + alpha dp with one equilibrium per trial and Armijo
+ * acceptance f(alpha) <= f(0) + 1e-4 alpha g^T dp.  (d_p, d_x) must be an
+ * equilibrium on entry and are updated in place. */
+sgn_status sgn_step(sgn_ctx ctx, double* d_p, double* d_x, sgn_step_info* info);
+/* Sizes of a system: N, nnz of the lower CSR, number of supernodes, factor
+ * entries sum(m*s) and dense front flops of one factorisation. */
+sgn_status sgn_get_sizes(sgn_ctx ctx, int which, int64_t* n, int64_t* nnz, int64_t* n_supernodes,
+                         int64_t* factor_entries, double* factor_flops);
+/* Symbolic tables of a system (host arrays sized from sgn_get_sizes):
+ * perm[new] = old [n], etree [n] (-1 = root), rowptr [n+1], colind [nnz]. */
+sgn_status sgn_get_symbolic(sgn_ctx ctx, int which, int32_t* h_perm, int32_t* h_etree,
+                            int64_t* h_rowptr, int32_t* h_colind);
+/* Read back the assembled lower CSR values (host [nnz], new numbering). */
+sgn_status sgn_get_values(sgn_ctx ctx, int which, double* h_vals);
+/* Self test of the matrix-core lane layout the factorisation kernels rely on:
+ * d_out (16x16, row-major) = A (16x4, row-major d_a) * B (4x16, row-major d_b)
+ * computed by one 16x16x4 MFMA in FP64 (prec 0) or FP32 (prec 1).  Device
+ * pointers owned by the caller; synchronises the stream. */
+sgn_status sgn_selftest_mfma(int prec, const double* d_a, const double* d_b, double* d_out, void* stream);
+/* Last error message of the context (never NULL). */
+const char* sgn_last_error(sgn_ctx ctx);
+/* Release host state (the workspace stays owned by the caller). */
+void sgn_destroy(sgn_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGN_H */

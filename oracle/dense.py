@@ -11,6 +11,10 @@ parameters outnumber residuals):
     f = w/2 sum_{i in T} ((x_i - t_i) / ell)^2 + mu/2 |p - p_ref|^2,
 
 so in the notation of eq. reducedGN, A = (w / ell^2) I_T, B = 0, C = mu I.
+For rest-position parameters (lengths, like x) the regulariser is measured
+in the same normalised units as the misfit, mu/2 |(p - p_ref)/ell|^2, i.e.
+C = (mu / ell^2) I (a reading; with mu on raw metres the reduced Hessian of
+the small cantilevers has condition numbers near 1e9).
 
 Every vector over states uses the free-DOF layout (free nodes ascending, dim
 components each).  Parameters: one log-modulus per element, the rest
@@ -135,10 +139,17 @@ def param_jacobian(prob: Problem, x: np.ndarray, p: np.ndarray) -> sp.csr_matrix
 
 # ----------------------------------------------------------------------------- objective
 
+def reg_weight(prob: Problem) -> float:
+    """Diagonal C of the regulariser (mu, or mu / ell^2 for rest-position parameters)."""
+    if prob.param_kind == P_REST_POS:
+        return prob.reg_mu / prob.length_scale ** 2
+    return prob.reg_mu
+
+
 def objective(prob: Problem, x: np.ndarray, p: np.ndarray) -> float:
     r = (x[prob.target_dof] - prob.target_val) / prob.length_scale
     dp = p - prob.p_ref
-    return float(0.5 * prob.target_w * r @ r + 0.5 * prob.reg_mu * dp @ dp)
+    return float(0.5 * prob.target_w * r @ r + 0.5 * reg_weight(prob) * dp @ dp)
 
 
 def objective_blocks(prob: Problem, x: np.ndarray, p: np.ndarray):
@@ -146,12 +157,13 @@ def objective_blocks(prob: Problem, x: np.ndarray, p: np.ndarray):
     ell2 = prob.length_scale ** 2
     fx = np.zeros(prob.n_x)
     fx[prob.target_dof] = prob.target_w * (x[prob.target_dof] - prob.target_val) / ell2
-    fp = prob.reg_mu * (p - prob.p_ref)
+    mu = reg_weight(prob)
+    fp = mu * (p - prob.p_ref)
     a = np.zeros(prob.n_x)
     a[prob.target_dof] = prob.target_w / ell2
     A = sp.diags(a, format="csr")
     B = sp.csr_matrix((prob.n_p, prob.n_x))
-    C = sp.diags(np.full(prob.n_p, prob.reg_mu), format="csr")
+    C = sp.diags(np.full(prob.n_p, mu), format="csr")
     return fx, fp, A, B, C
 
 

@@ -1,0 +1,1082 @@
+// C ABI of libsgn (declared in include/sgn.h): context, workspace layout and
+// the host drivers of the hot path -- Newton equilibrium (Sec. 5), SGN
+// assembly and right-hand side (Sec. 4, eq. sparseSystemGN; adjoint gradient
+// of eq. totalGradient), supernodal LDL^T, refined solves, and the outer
+// iteration with backtracking.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sgn.h"
+#include "kernels.h"
+#include "symbolic.h"
+
+using namespace sgn;
+
+namespace {
+
+struct DevSys {
+  int64_t* rowptr = nullptr;
+  int32_t* colind = nullptr;
+  int32_t* slot_row = nullptr;
+  int64_t* csr_front_pos = nullptr;
+  int64_t* slot_ptr = nullptr;
+  int32_t* slot_src = nullptr;
+  int32_t* diag_kind = nullptr;
+  int64_t* frowptr = nullptr;
+  int32_t* fcol = nullptr;
+  int32_t* fslot = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* sn_begin = nullptr;
+  int32_t* sn_m = nullptr;
+  int64_t* sn_front_off = nullptr;
+  int64_t* sn_vec_off = nullptr;
+  int64_t* sn_rows_ptr = nullptr;
+  int32_t* sn_rows = nullptr;
+  int64_t* relmap_off = nullptr;
+  int32_t* relmap = nullptr;
+  int32_t* child_ptr = nullptr;
+  int32_t* child_list = nullptr;
+  int32_t* var_group_end = nullptr;
+  int32_t* level_sn = nullptr;
+  int32_t* panel_ptr = nullptr;
+  int32_t* panel_col = nullptr;
+  int64_t* panel_tasks = nullptr;
+  int64_t* upd_tasks = nullptr;
+  int64_t* ea_tasks = nullptr;
+  int64_t* vec_ptr = nullptr;
+  int32_t* vec_src = nullptr;
+  int64_t* const_slots = nullptr;
+  int64_t n_const = 0;
+  double* vals = nullptr;
+  double* scale = nullptr;
+  double* dpiv = nullptr;
+  double* epiv = nullptr;
+  int32_t* pivtype = nullptr;
+  int32_t* lperm = nullptr;
+  void* front = nullptr;
+  double* tv = nullptr;
+  double* tp = nullptr;
+  double* b = nullptr;     // caller-facing work vectors of the drivers
+  double* z = nullptr;
+  double* r = nullptr;
+  double* t = nullptr;
+  double* sv = nullptr;    // internal to solve_once: scaled right-hand side
+  double* ir_r = nullptr;  // internal to refined_solve: residual
+  double* ir_d = nullptr;  // internal to refined_solve: correction
+  double* ir_s = nullptr;  // internal to refined_solve: scaled residual
+  int prec = 0;  // 0: FP64 fronts, 1: FP32 fronts
+  bool factored = false;
+  int64_t inertia[3] = {0, 0, 0};
+};
+
+struct Layout {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct sgn_ctx_s {
+  Analysis A;
+  sgn_options opt{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool sticky = false;
+  bool has_ws = false;
+  std::vector<int32_t> target_dof;
+  std::vector<double> target_val, p_ref, fext_free;
+  std::vector<int32_t> efdof;
+  double target_w = 1, ell = 1, mu_in = 0, mu_reg = 0, mu0 = 0, lam0 = 0, fext_norm = 0;
+  DevSys sys[2];
+  int32_t* d_elems = nullptr;
+  int32_t* d_efdof = nullptr;
+  double* d_rest = nullptr;
+  double* d_fext = nullptr;
+  int32_t* d_tdof = nullptr;
+  double* d_tval = nullptr;
+  double* d_pref = nullptr;
+  double* d_ebuf = nullptr;
+  double* d_x = nullptr;
+  double* d_xt = nullptr;
+  double* d_p = nullptr;
+  double* d_pt = nullptr;
+  double* d_c = nullptr;
+  double* d_dx = nullptr;
+  double* d_fx = nullptr;
+  double* d_fp = nullptr;
+  double* d_lam = nullptr;
+  double* d_g = nullptr;
+  double* d_old = nullptr;
+  double* d_old2 = nullptr;
+  double* d_rt = nullptr;
+  double* d_srhs = nullptr;  // [N] step right-hand side (boundary order)
+  double* d_ssol = nullptr;  // [N] step solution (boundary order)
+  double* d_part = nullptr;
+  double* d_scal = nullptr;
+  int* d_cnt = nullptr;
+  unsigned long long* d_ull = nullptr;
+  bool kx_valid = false;
+  bool sgn_assembled = false;
+};
+
+namespace {
+
+sgn_status fail(sgn_ctx c, sgn_status s, const std::string& msg) {
+  if (c && s != SGN_OK) {
+    c->err = msg;
+    c->sticky = true;
+  }
+  return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(c, SGN_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)                    \
+  do {                               \
+    sgn_status s_ = (expr);          \
+    if (s_ != SGN_OK) return s_;     \
+  } while (0)
+
+template <typename T>
+size_t bytes_of(const std::vector<T>& v) {
+  return v.size() * sizeof(T);
+}
+
+size_t layout(sgn_ctx c, char* base) {
+  Layout L{base};
+  const Analysis& A = c->A;
+  const int64_t nx = A.mesh.n_x, np = A.mesh.n_p, ne = A.mesh.n_elems, nv = A.mesh.dim + 1;
+  const size_t nt = c->target_dof.size();
+  for (int si = 0; si < 2; ++si) {
+    const System& S = si == 0 ? A.sgn : A.kx;
+    DevSys& D = c->sys[si];
+    D.rowptr = L.take<int64_t>(S.rowptr.size());
+    D.colind = L.take<int32_t>(S.colind.size());
+    D.slot_row = L.take<int32_t>(S.slot_row.size());
+    D.csr_front_pos = L.take<int64_t>(S.csr_front_pos.size());
+    D.slot_ptr = L.take<int64_t>(S.slot_ptr.size());
+    D.slot_src = L.take<int32_t>(S.slot_src.size());
+    D.diag_kind = L.take<int32_t>(S.diag_kind.size());
+    D.frowptr = L.take<int64_t>(S.frowptr.size());
+    D.fcol = L.take<int32_t>(S.fcol.size());
+    D.fslot = L.take<int32_t>(S.fslot.size());
+    D.perm = L.take<int32_t>(S.perm.size());
+    D.sn_begin = L.take<int32_t>(S.sn_begin.size());
+    D.sn_m = L.take<int32_t>(S.sn_m.size());
+    D.sn_front_off = L.take<int64_t>(S.sn_front_off.size());
+    D.sn_vec_off = L.take<int64_t>(S.sn_vec_off.size());
+    D.sn_rows_ptr = L.take<int64_t>(S.sn_rows_ptr.size());
+    D.sn_rows = L.take<int32_t>(S.sn_rows.size());
+    D.relmap_off = L.take<int64_t>(S.relmap_off.size());
+    D.relmap = L.take<int32_t>(S.relmap.size());
+    D.child_ptr = L.take<int32_t>(S.child_ptr.size());
+    D.child_list = L.take<int32_t>(S.child_list.size());
+    D.var_group_end = L.take<int32_t>(S.var_group_end.size());
+    D.level_sn = L.take<int32_t>(S.level_sn.size());
+    D.panel_ptr = L.take<int32_t>(S.panel_ptr.size());
+    D.panel_col = L.take<int32_t>(S.panel_col.size());
+    D.panel_tasks = L.take<int64_t>(S.panel_tasks.size());
+    D.upd_tasks = L.take<int64_t>(S.upd_tasks.size());
+    D.ea_tasks = L.take<int64_t>(S.ea_tasks.size());
+    D.vec_ptr = L.take<int64_t>(S.vec_ptr.size());
+    D.vec_src = L.take<int32_t>(S.vec_src.size());
+    D.n_const = (si == 0 && A.mesh.param_kind == 2) ? nx : 0;
+    D.const_slots = L.take<int64_t>(D.n_const);
+    D.vals = L.take<double>(S.colind.size());
+    D.scale = L.take<double>(S.N);
+    D.dpiv = L.take<double>(S.N);
+    D.epiv = L.take<double>(S.N);
+    D.pivtype = L.take<int32_t>(S.N);
+    D.lperm = L.take<int32_t>(S.N);
+    D.prec = (si == 0 && c->opt.precision == SGN_FP32_IR) ? 1 : 0;
+    const size_t esz = D.prec ? sizeof(float) : sizeof(double);
+    D.front = L.take<char>(S.front_total * esz + 64);
+    D.tv = L.take<double>(S.vec_total);
+    D.tp = L.take<double>(S.vec_total);
+    D.b = L.take<double>(S.N);
+    D.z = L.take<double>(S.N);
+    D.r = L.take<double>(S.N);
+    D.t = L.take<double>(S.N);
+    D.sv = L.take<double>(S.N);
+    D.ir_r = L.take<double>(S.N);
+    D.ir_d = L.take<double>(S.N);
+    D.ir_s = L.take<double>(S.N);
+  }
+  c->d_elems = L.take<int32_t>(ne * nv);
+  c->d_efdof = L.take<int32_t>(ne * nv);
+  c->d_rest = L.take<double>(A.mesh.rest.size());
+  c->d_fext = L.take<double>(nx);
+  c->d_tdof = L.take<int32_t>(nt);
+  c->d_tval = L.take<double>(nt);
+  c->d_pref = L.take<double>(np);
+  c->d_ebuf = L.take<double>(ne * (int64_t)A.stride);
+  c->d_x = L.take<double>(nx);
+  c->d_xt = L.take<double>(nx);
+  c->d_p = L.take<double>(np);
+  c->d_pt = L.take<double>(np);
+  c->d_c = L.take<double>(nx);
+  c->d_dx = L.take<double>(nx);
+  c->d_fx = L.take<double>(nx);
+  c->d_fp = L.take<double>(np);
+  c->d_lam = L.take<double>(nx);
+  c->d_g = L.take<double>(np);
+  c->d_old = L.take<double>(A.sgn.N);
+  c->d_old2 = L.take<double>(A.sgn.N);
+  c->d_rt = L.take<double>(nt);
+  c->d_srhs = L.take<double>(A.sgn.N);
+  c->d_ssol = L.take<double>(A.sgn.N);
+  c->d_part = L.take<double>(4 * kRedBlocks);
+  c->d_scal = L.take<double>(64);
+  c->d_cnt = L.take<int>(64);
+  c->d_ull = L.take<unsigned long long>(16);
+  return L.off + 256;
+}
+
+template <typename T>
+hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, src.data(), bytes_of(src), hipMemcpyHostToDevice, s);
+}
+
+// ------------------------------------------------------------------ reductions
+sgn_status read_scalars(sgn_ctx c, int first, int n, double* out) {
+  HIPCHK(hipMemcpyAsync(out, c->d_scal + first, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+void dev_dot(sgn_ctx c, int64_t n, const double* a, const double* b, int slot, int64_t stride = 1,
+             int absval = 0) {
+  launch_dot_partials(n, a, b, stride, absval, c->d_part, c->stream);
+  launch_final_sum(c->d_part, kRedBlocks, c->d_scal + slot, c->stream);
+}
+
+// ------------------------------------------------------------------ element + assembly
+sgn_status run_element(sgn_ctx c, const double* x, const double* p, int mode, int* inverted) {
+  const Analysis& A = c->A;
+  HIPCHK(hipMemsetAsync(c->d_cnt + 8, 0, sizeof(int), c->stream));
+  ElemArgs ea;
+  ea.dim = A.mesh.dim;
+  ea.ne = A.mesh.n_elems;
+  ea.param_kind = A.mesh.param_kind;
+  ea.mode = mode;
+  ea.elems = c->d_elems;
+  ea.efdof = c->d_efdof;
+  ea.rest = c->d_rest;
+  ea.x = x;
+  ea.p = p;
+  ea.mu0 = c->mu0;
+  ea.lam0 = c->lam0;
+  ea.ebuf = c->d_ebuf;
+  ea.stride = A.stride;
+  ea.off_grad = A.off_grad;
+  ea.off_kp = A.off_kp;
+  ea.off_energy = A.off_energy;
+  ea.inverted = c->d_cnt + 8;
+  launch_element(ea, c->stream);
+  HIPCHK(hipGetLastError());
+  int inv = 0;
+  HIPCHK(hipMemcpyAsync(&inv, c->d_cnt + 8, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *inverted = inv;
+  return SGN_OK;
+}
+
+// Kx values (+ shift tau on the diagonal) from the element buffer
+void assemble_kx(sgn_ctx c, double tau) {
+  const System& S = c->A.kx;
+  DevSys& D = c->sys[1];
+  launch_gather_slots((int64_t)S.colind.size(), D.slot_ptr, D.slot_src, c->d_ebuf, D.vals, c->stream);
+  if (tau != 0.0) launch_diag_add(S.N, D.rowptr, D.diag_kind, 0.0, 0.0, tau, 0.0, D.vals, c->stream);
+}
+
+void assemble_sgn(sgn_ctx c) {
+  const System& S = c->A.sgn;
+  DevSys& D = c->sys[0];
+  launch_gather_slots((int64_t)S.colind.size(), D.slot_ptr, D.slot_src, c->d_ebuf, D.vals, c->stream);
+  const double a_t = c->target_w / (c->ell * c->ell);
+  launch_diag_add(S.N, D.rowptr, D.diag_kind, a_t, c->mu_reg, c->opt.eps_x, c->opt.eps_lambda, D.vals, c->stream);
+  if (D.n_const) launch_const_slots(D.n_const, D.const_slots, -1.0, D.vals, c->stream);
+}
+
+// residual c = sum g_e - f_ext (- p)
+void residual_vec(sgn_ctx c, const double* p, double* out) {
+  const System& S = c->A.kx;
+  DevSys& D = c->sys[1];
+  launch_gather_vec(S.N, D.vec_ptr, D.vec_src, c->d_ebuf, c->d_fext, c->A.mesh.param_kind == 2 ? p : nullptr, out,
+                    c->stream);
+}
+
+// ------------------------------------------------------------------ factorisation
+template <typename T>
+sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
+  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+  DevSys& D = c->sys[si];
+  hipStream_t st = c->stream;
+  T* front = reinterpret_cast<T*>(D.front);
+  launch_row_scaling(S.N, D.frowptr, D.fslot, D.vals, D.scale, st);
+  launch_fill_bytes(((int64_t)(S.front_total * sizeof(T)) + 15) / 16 * 16, front, st);
+  launch_csr_to_fronts<T>((int64_t)S.colind.size(), D.slot_row, D.colind, D.csr_front_pos, D.vals, D.scale, front,
+                          st);
+  HIPCHK(hipMemsetAsync(c->d_cnt, 0, 4 * sizeof(int), st));
+  FrontArgs f;
+  f.sn_begin = D.sn_begin;
+  f.sn_m = D.sn_m;
+  f.sn_front_off = D.sn_front_off;
+  f.sn_rows_ptr = D.sn_rows_ptr;
+  f.sn_rows = D.sn_rows;
+  f.relmap_off = D.relmap_off;
+  f.relmap = D.relmap;
+  f.var_group_end = D.var_group_end;
+  f.dpiv = D.dpiv;
+  f.epiv = D.epiv;
+  f.pivtype = D.pivtype;
+  f.lperm = D.lperm;
+  f.counters = c->d_cnt;
+  f.piv_tol = piv_tol;
+  for (int L = 0; L < S.nlevels; ++L) {
+    const LevelPlan& P = S.levels[L];
+    for (size_t r = 0; r < P.ea_begin.size(); ++r) {
+      const int64_t nt = P.ea_end[r] - P.ea_begin[r];
+      launch_extend_add<T>(nt, P.ea_work[r], D.ea_tasks + P.ea_begin[r] * 3, f, front, st);
+    }
+    for (const PanelStep& ps : P.steps) {
+      const int64_t nt = ps.task_end - ps.task_begin;
+      launch_panel_diag<T>(nt, D.panel_tasks + ps.task_begin * 3, f, front, st);
+      launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
+      launch_update<T>(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, f, front, st);
+      launch_update<T>(ps.outer_end - ps.outer_begin, ps.outer_tiles, D.upd_tasks + ps.outer_begin * 6, f, front,
+                       st);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemsetAsync(c->d_ull, 0, 4 * sizeof(unsigned long long), st));
+  launch_inertia(S.N, D.dpiv, D.epiv, D.pivtype, c->d_ull, c->d_part, st);
+  HIPCHK(hipGetLastError());
+  D.factored = true;
+  return SGN_OK;
+}
+
+sgn_status factor_dispatch(sgn_ctx c, int si, double piv_tol, sgn_factor_info* info) {
+  const double t0 = now_ms();
+  DevSys& D = c->sys[si];
+  if (D.prec) TRY(factor_system<float>(c, si, piv_tol));
+  else TRY(factor_system<double>(c, si, piv_tol));
+  unsigned long long cnt[3] = {0, 0, 0};
+  int pert = 0;
+  std::vector<double> part(kRedBlocks);
+  HIPCHK(hipMemcpyAsync(cnt, c->d_ull, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(&pert, c->d_cnt, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(part.data(), c->d_part, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double mn = INFINITY;
+  for (double v : part) mn = std::min(mn, v);
+  D.inertia[0] = (int64_t)cnt[0];
+  D.inertia[1] = (int64_t)cnt[1];
+  D.inertia[2] = (int64_t)cnt[2];
+  if (info) {
+    const System& S = si == 0 ? c->A.sgn : c->A.kx;
+    info->n_pos = (int64_t)cnt[0];
+    info->n_neg = (int64_t)cnt[1];
+    info->n_zero = (int64_t)cnt[2];
+    info->n_perturbed = pert;
+    info->min_abs_pivot = mn;
+    info->flops = S.flops;
+    info->ms = now_ms() - t0;
+  }
+  return SGN_OK;
+}
+
+// solve in the system's (new, scaled) space: x = K^-1 b with b, x in new order, unscaled
+template <typename T>
+void solve_once_t(sgn_ctx c, int si, const double* b_new, double* x_new) {
+  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+  DevSys& D = c->sys[si];
+  hipStream_t st = c->stream;
+  SolveArgs a;
+  a.f.sn_begin = D.sn_begin;
+  a.f.sn_m = D.sn_m;
+  a.f.sn_front_off = D.sn_front_off;
+  a.f.sn_rows_ptr = D.sn_rows_ptr;
+  a.f.sn_rows = D.sn_rows;
+  a.f.relmap_off = D.relmap_off;
+  a.f.relmap = D.relmap;
+  a.f.var_group_end = D.var_group_end;
+  a.f.dpiv = D.dpiv;
+  a.f.epiv = D.epiv;
+  a.f.pivtype = D.pivtype;
+  a.f.lperm = D.lperm;
+  a.f.counters = c->d_cnt;
+  a.f.piv_tol = 0;
+  a.child_ptr = D.child_ptr;
+  a.child_list = D.child_list;
+  a.sn_vec_off = D.sn_vec_off;
+  a.panel_ptr = D.panel_ptr;
+  a.panel_col = D.panel_col;
+  a.tv = D.tv;
+  a.tp = D.tp;
+  const T* front = reinterpret_cast<const T*>(D.front);
+  for (int L = 0; L < S.nlevels; ++L) {
+    const LevelPlan& P = S.levels[L];
+    launch_fwd_level<T>(P.sn_end - P.sn_begin, D.level_sn + P.sn_begin, a, front, b_new, st);
+  }
+  for (int L = S.nlevels - 1; L >= 0; --L) {
+    const LevelPlan& P = S.levels[L];
+    launch_bwd_level<T>(P.sn_end - P.sn_begin, D.level_sn + P.sn_begin, a, front, x_new, st);
+  }
+}
+
+void scale_vec(sgn_ctx c, int64_t n, const double* s, const double* in, double* out);
+
+// x_new = K^-1 b_new with the current factor (x_new may alias b_new; uses D.sv)
+void solve_once(sgn_ctx c, int si, const double* b_new, double* x_new) {
+  DevSys& D = c->sys[si];
+  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+  scale_vec(c, S.N, D.scale, b_new, D.sv);
+  if (D.prec) solve_once_t<float>(c, si, D.sv, x_new);
+  else solve_once_t<double>(c, si, D.sv, x_new);
+  scale_vec(c, S.N, D.scale, x_new, x_new);
+}
+
+void scale_vec(sgn_ctx c, int64_t n, const double* s, const double* in, double* out) {
+  launch_scale(n, s, in, out, c->stream);
+}
+
+// Refined solve in new order: K z = b (unscaled), FP64 residuals on the assembled
+// matrix.  b_new and z_new are caller buffers (distinct from the internal ones).
+sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, sgn_solve_info* info) {
+  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+  DevSys& D = c->sys[si];
+  const double t0 = now_ms();
+  solve_once(c, si, b_new, z_new);
+  scale_vec(c, S.N, D.scale, b_new, D.ir_s);
+  dev_dot(c, S.N, D.ir_s, D.ir_s, 1);
+  dev_dot(c, S.N, b_new, b_new, 2);
+  double bn[2];
+  TRY(read_scalars(c, 1, 2, bn));
+  const double sb = std::sqrt(bn[0]), rb = std::sqrt(bn[1]);
+  int sweeps = 0;
+  double rel = 0, raw = 0, prev = INFINITY;
+  const int max_ir = std::max(0, c->opt.max_ir);
+  for (;;) {
+    launch_residual(S.N, D.frowptr, D.fcol, D.fslot, D.vals, z_new, b_new, D.ir_r, c->stream);
+    scale_vec(c, S.N, D.scale, D.ir_r, D.ir_s);
+    dev_dot(c, S.N, D.ir_s, D.ir_s, 1);
+    dev_dot(c, S.N, D.ir_r, D.ir_r, 2);
+    double rn[2];
+    TRY(read_scalars(c, 1, 2, rn));
+    rel = sb > 0 ? std::sqrt(rn[0]) / sb : 0.0;
+    raw = rb > 0 ? std::sqrt(rn[1]) / rb : 0.0;
+    if (rel <= c->opt.solve_rtol || sweeps >= max_ir || !(rel < prev)) break;
+    prev = rel;
+    solve_once(c, si, D.ir_r, D.ir_d);
+    launch_axpby(S.N, 1.0, z_new, 1.0, D.ir_d, z_new, c->stream);
+    ++sweeps;
+  }
+  if (info) {
+    info->sweeps = sweeps;
+    info->fallback = 0;
+    info->rel_res = rel;
+    info->raw_rel_res = raw;
+    info->ms = now_ms() - t0;
+  }
+  if (!(rel <= c->opt.solve_rtol)) {
+    c->err = "refinement stopped at equilibrated relative residual " + std::to_string(rel);
+    return SGN_E_REFINE;
+  }
+  return SGN_OK;
+}
+
+// ------------------------------------------------------------------ equilibrium
+sgn_status potential(sgn_ctx c, const double* x, const double* p, double* pi, double* scale, bool* inverted) {
+  int inv = 0;
+  TRY(run_element(c, x, p, 0, &inv));
+  *inverted = inv > 0;
+  if (inv) {
+    *pi = INFINITY;
+    return SGN_OK;
+  }
+  const Analysis& A = c->A;
+  dev_dot(c, A.mesh.n_elems, c->d_ebuf + A.off_energy, nullptr, 4, A.stride, 0);
+  dev_dot(c, A.mesh.n_elems, c->d_ebuf + A.off_energy, nullptr, 5, A.stride, 1);
+  dev_dot(c, A.mesh.n_x, c->d_fext, x, 6);
+  int ns = 3;
+  if (A.mesh.param_kind == 2) {
+    dev_dot(c, A.mesh.n_x, p, x, 7);
+    ns = 4;
+  }
+  double v[4] = {0, 0, 0, 0};
+  TRY(read_scalars(c, 4, ns, v));
+  const double fx = v[2] + v[3];
+  *pi = v[0] - fx;
+  *scale = v[1] + std::fabs(fx);
+  return SGN_OK;
+}
+
+// Newton with backtracking; on success the Kx factor is valid at the returned x.
+sgn_status equilibrium_impl(sgn_ctx c, const double* p, double* x, sgn_eq_info* info) {
+  const Analysis& A = c->A;
+  const int64_t nx = A.mesh.n_x;
+  const double tol = c->opt.newton_rtol * c->fext_norm + c->opt.newton_atol;
+  int halvings = 0;
+  c->kx_valid = false;
+  for (int it = 0; it <= c->opt.max_newton; ++it) {
+    int inv = 0;
+    TRY(run_element(c, x, p, 2, &inv));
+    if (inv) {
+      c->err = "inverted element at the Newton iterate";
+      return SGN_E_INVERTED;
+    }
+    residual_vec(c, p, c->d_c);
+    dev_dot(c, nx, c->d_c, c->d_c, 3);
+    double rn2;
+    TRY(read_scalars(c, 3, 1, &rn2));
+    const double rn = std::sqrt(rn2);
+    // factorise Kx at this iterate (also needed at convergence for the adjoint)
+    double tau = 0.0;
+    double dmax = 0.0;
+    for (int attempt = 0;; ++attempt) {
+      assemble_kx(c, tau);
+      TRY(factor_dispatch(c, 1, 1e-300, nullptr));
+      if (c->sys[1].inertia[0] == nx) break;
+      if (attempt >= 20) {
+        c->err = "Kx stayed indefinite after diagonal shifts";
+        return SGN_E_NEWTON;
+      }
+      if (tau == 0.0) {
+        launch_max_abs_partials((int64_t)A.kx.colind.size(), c->sys[1].vals, c->d_part, c->stream);
+        launch_final_max(c->d_part, kRedBlocks, c->d_scal + 8, c->stream);
+        TRY(read_scalars(c, 8, 1, &dmax));
+        tau = 1e-8 * dmax;
+      } else {
+        tau *= 10.0;
+      }
+    }
+    if (rn <= tol) {
+      c->kx_valid = (tau == 0.0);
+      if (info) {
+        info->iters = it;
+        info->halvings = halvings;
+        info->res_norm = rn;
+        info->f_ext_norm = c->fext_norm;
+        info->converged = 1;
+      }
+      return SGN_OK;
+    }
+    if (it == c->opt.max_newton) break;
+    // dx = -Kx^-1 c, in the Kx ordering
+    DevSys& D = c->sys[1];
+    launch_gather_perm(nx, D.perm, nullptr, c->d_c, D.b, c->stream);
+    launch_axpby(nx, -1.0, D.b, 0.0, nullptr, D.b, c->stream);
+    sgn_solve_info si{};
+    const double keep = c->opt.solve_rtol;
+    c->opt.solve_rtol = 1e-14;
+    sgn_status s = refined_solve(c, 1, D.b, D.z, &si);
+    c->opt.solve_rtol = keep;
+    if (s != SGN_OK && s != SGN_E_REFINE) return s;
+    launch_scatter_perm(nx, D.perm, nullptr, D.z, c->d_dx, c->stream);
+    // backtracking on Pi
+    double pi0, sc0;
+    bool inv0;
+    TRY(potential(c, x, p, &pi0, &sc0, &inv0));
+    dev_dot(c, nx, c->d_c, c->d_dx, 9);
+    double slope;
+    TRY(read_scalars(c, 9, 1, &slope));
+    double alpha = 1.0;
+    bool ok = false;
+    for (int h = 0; h <= c->opt.max_halvings + 10; ++h) {
+      launch_axpby(nx, 1.0, x, alpha, c->d_dx, c->d_xt, c->stream);
+      double pi1, sc1;
+      bool inv1;
+      TRY(potential(c, c->d_xt, p, &pi1, &sc1, &inv1));
+      if (!inv1 && pi1 <= pi0 + 1e-4 * alpha * slope + 1e-12 * sc0) {
+        ok = true;
+        break;
+      }
+      alpha *= 0.5;
+      ++halvings;
+    }
+    if (!ok) {
+      c->err = "Newton line search failed";
+      return SGN_E_NEWTON;
+    }
+    HIPCHK(hipMemcpyAsync(x, c->d_xt, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (info) {
+    info->iters = c->opt.max_newton;
+    info->halvings = halvings;
+    info->res_norm = -1;
+    info->f_ext_norm = c->fext_norm;
+    info->converged = 0;
+  }
+  c->err = "Newton did not converge";
+  return SGN_E_NEWTON;
+}
+
+// f(x, p) on device pointers (sync)
+sgn_status objective_value(sgn_ctx c, const double* x, const double* p, double* f) {
+  const Analysis& A = c->A;
+  const int64_t nt = (int64_t)c->target_dof.size();
+  launch_fill(A.mesh.n_x, 0.0, c->d_fx, c->stream);
+  launch_objective_fx(nt, c->d_tdof, c->d_tval, x, 1.0, c->d_fx, c->stream);  // x_T - t
+  dev_dot(c, A.mesh.n_x, c->d_fx, c->d_fx, 10);
+  launch_axpby(A.mesh.n_p, 1.0, p, -1.0, c->d_pref, c->d_fp, c->stream);
+  dev_dot(c, A.mesh.n_p, c->d_fp, c->d_fp, 11);
+  double v[2];
+  TRY(read_scalars(c, 10, 2, v));
+  *f = 0.5 * c->target_w * v[0] / (c->ell * c->ell) + 0.5 * c->mu_reg * v[1];
+  return SGN_OK;
+}
+
+// Assemble K_SGN at (x, p) and the rhs in boundary order into rhs_old (device).
+sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rhs_old, double* grad, double* obj) {
+  const Analysis& A = c->A;
+  const int64_t nx = A.mesh.n_x, np = A.mesh.n_p, N = A.sgn.N;
+  int inv = 0;
+  TRY(run_element(c, x, p, 2, &inv));
+  if (inv) {
+    c->err = "inverted element in the given state";
+    return SGN_E_INVERTED;
+  }
+  assemble_sgn(c);
+  c->sgn_assembled = true;
+  c->sys[0].factored = false;
+  if (obj) TRY(objective_value(c, x, p, obj));
+  if (rhs_old || grad) {
+    const int64_t nt = (int64_t)c->target_dof.size();
+    launch_fill(nx, 0.0, c->d_fx, c->stream);
+    launch_objective_fx(nt, c->d_tdof, c->d_tval, x, c->target_w / (c->ell * c->ell), c->d_fx, c->stream);
+    launch_axpby(np, c->mu_reg, p, -c->mu_reg, c->d_pref, c->d_fp, c->stream);
+    if (c->opt.rhs_kind == SGN_RHS_KKT) {
+      if (grad) {
+        c->err = "the KKT right-hand side does not form the gradient";
+        return SGN_E_ARG;
+      }
+      launch_axpby(nx, -1.0, c->d_fx, 0.0, nullptr, rhs_old, c->stream);
+      launch_axpby(np, -1.0, c->d_fp, 0.0, nullptr, rhs_old + nx, c->stream);
+      launch_fill(nx, 0.0, rhs_old + nx + np, c->stream);
+      return SGN_OK;
+    }
+    if (!c->kx_valid) {
+      c->err = "adjoint right-hand side needs the Kx factor of sgn_equilibrium at this state";
+      return SGN_E_STATE;
+    }
+    // lam: Kx lam = -fx
+    DevSys& K = c->sys[1];
+    launch_gather_perm(nx, K.perm, nullptr, c->d_fx, K.b, c->stream);
+    launch_axpby(nx, -1.0, K.b, 0.0, nullptr, K.b, c->stream);
+    const double keep = c->opt.solve_rtol;
+    c->opt.solve_rtol = 1e-14;
+    sgn_solve_info si{};
+    sgn_status s = refined_solve(c, 1, K.b, K.z, &si);
+    c->opt.solve_rtol = keep;
+    if (s != SGN_OK && s != SGN_E_REFINE) return s;
+    launch_scatter_perm(nx, K.perm, nullptr, K.z, c->d_lam, c->stream);
+    // Kp^T lam through the assembled K_SGN: w = K [0; 0; lam], g = fp + w_p
+    DevSys& D = c->sys[0];
+    launch_fill(N, 0.0, c->d_old, c->stream);
+    HIPCHK(hipMemcpyAsync(c->d_old + nx + np, c->d_lam, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    launch_gather_perm(N, D.perm, nullptr, c->d_old, D.t, c->stream);
+    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, D.t, D.r, c->stream);
+    launch_scatter_perm(N, D.perm, nullptr, D.r, c->d_old2, c->stream);
+    launch_axpby(np, 1.0, c->d_fp, 1.0, c->d_old2 + nx, c->d_g, c->stream);
+    if (grad && grad != c->d_g)
+      HIPCHK(hipMemcpyAsync(grad, c->d_g, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (rhs_old) {
+      launch_fill(N, 0.0, rhs_old, c->stream);
+      launch_axpby(np, -1.0, c->d_g, 0.0, nullptr, rhs_old + nx, c->stream);
+    }
+  }
+  return SGN_OK;
+}
+
+sgn_status check_ready(sgn_ctx c) {
+  if (!c) return SGN_E_ARG;
+  if (c->sticky) return SGN_E_STATE;
+  if (!c->has_ws) return fail(c, SGN_E_STATE, "no workspace set");
+  return SGN_OK;
+}
+
+sgn_status sgn_factor_impl(sgn_ctx c, sgn_factor_info* info) {
+  if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "sgn_factor before sgn_assemble");
+  sgn_factor_info fi{};
+  const double tol = c->sys[0].prec ? 1e-12 : 1e-14;
+  TRY(factor_dispatch(c, 0, tol, &fi));
+  if (info) *info = fi;
+  const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p;
+  if (c->sys[0].prec == 0 && (fi.n_pos != nx + np || fi.n_neg != nx || fi.n_zero != 0)) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "inertia (%lld, %lld, %lld), expected (%lld, %lld, 0)", (long long)fi.n_pos,
+             (long long)fi.n_neg, (long long)fi.n_zero, (long long)(nx + np), (long long)nx);
+    return fail(c, SGN_E_PIVOT, buf);
+  }
+  return SGN_OK;
+}
+
+sgn_status sgn_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_info* info) {
+  DevSys& D = c->sys[0];
+  if (!D.factored) return fail(c, SGN_E_STATE, "sgn_solve before sgn_factor");
+  const int64_t N = c->A.sgn.N;
+  launch_gather_perm(N, D.perm, nullptr, rhs, c->d_old2, c->stream);
+  double* zn = c->d_old;  // new-order solution
+  sgn_status s = refined_solve(c, 0, c->d_old2, zn, info);
+  launch_scatter_perm(N, D.perm, nullptr, zn, sol, c->stream);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (s != SGN_OK) return fail(c, s, c->err);
+  return SGN_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void sgn_default_options(sgn_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SGN_FP64;
+  o->solver = SGN_LDLT;
+  o->rhs_kind = SGN_RHS_ADJOINT;
+  o->newton_rtol = 1e-10;
+  o->newton_atol = 0.0;
+  o->solve_rtol = 1e-10;
+  o->eps_x = 0.0;
+  o->eps_lambda = 0.0;
+  o->max_newton = 50;
+  o->max_ir = 10;
+  o->max_minres = 500;
+  o->max_halvings = 30;
+}
+
+sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* stream, sgn_ctx* out) {
+  if (!out) return SGN_E_ARG;
+  *out = nullptr;
+  if (!pr || !pr->rest_pos || !pr->elems || !pr->node_grid || !pr->fixed || !pr->f_ext) return SGN_E_ARG;
+  if (pr->dim != 2 && pr->dim != 3) return SGN_E_ARG;
+  if (pr->n_nodes <= 0 || pr->n_elems <= 0) return SGN_E_ARG;
+  if (pr->param_kind < 0 || pr->param_kind > 2) return SGN_E_ARG;
+  sgn_ctx c = new (std::nothrow) sgn_ctx_s();
+  if (!c) return SGN_E_NOMEM;
+  *out = c;
+  if (opt) c->opt = *opt;
+  else sgn_default_options(&c->opt);
+  c->stream = (hipStream_t)stream;
+  const int d = pr->dim, nv = d + 1;
+  Mesh& m = c->A.mesh;
+  m.dim = d;
+  m.n_nodes = pr->n_nodes;
+  m.n_elems = pr->n_elems;
+  m.param_kind = pr->param_kind;
+  m.rest.assign(pr->rest_pos, pr->rest_pos + (size_t)pr->n_nodes * d);
+  m.elems.assign(pr->elems, pr->elems + (size_t)pr->n_elems * nv);
+  m.grid.assign(pr->node_grid, pr->node_grid + (size_t)pr->n_nodes * d);
+  m.fixed.assign(pr->fixed, pr->fixed + pr->n_nodes);
+  m.fext.assign(pr->f_ext, pr->f_ext + (size_t)pr->n_nodes * d);
+  for (int32_t v : m.elems)
+    if (v < 0 || v >= pr->n_nodes) return fail(c, SGN_E_ARG, "element references a node out of range");
+  for (int32_t g : m.grid)
+    if (g < 0 || g > 1000000) return fail(c, SGN_E_ARG, "grid coordinate out of range");
+  if (!(pr->E0 > 0) || !(pr->nu > -1.0 && pr->nu < 0.5)) return fail(c, SGN_E_ARG, "invalid material");
+  std::string err = analyse(c->A);
+  if (!err.empty()) return fail(c, SGN_E_ARG, "symbolic analysis: " + err);
+  const int64_t nx = m.n_x, np = m.n_p;
+  if (pr->n_targets < 0 || (pr->n_targets > 0 && !pr->target_dof)) return fail(c, SGN_E_ARG, "targets");
+  c->target_dof.assign(pr->target_dof, pr->target_dof + pr->n_targets);
+  for (int32_t t : c->target_dof)
+    if (t < 0 || t >= nx) return fail(c, SGN_E_ARG, "target DOF out of range");
+  c->target_val.assign(pr->n_targets, 0.0);
+  if (pr->target_val) c->target_val.assign(pr->target_val, pr->target_val + pr->n_targets);
+  c->target_w = pr->target_w;
+  c->ell = pr->length_scale > 0 ? pr->length_scale : 1.0;
+  c->mu_in = pr->reg_mu;
+  // rest-position parameters: the regulariser is measured in units of ell, like the misfit
+  c->mu_reg = pr->param_kind == SGN_P_REST_POS ? c->mu_in / (c->ell * c->ell) : c->mu_in;
+  c->p_ref.assign(np, 0.0);
+  if (pr->p_ref) c->p_ref.assign(pr->p_ref, pr->p_ref + np);
+  c->mu0 = pr->E0 / (2.0 * (1.0 + pr->nu));
+  c->lam0 = pr->E0 * pr->nu / ((1.0 + pr->nu) * (1.0 - 2.0 * pr->nu));
+  c->fext_free.assign(nx, 0.0);
+  for (int v = 0; v < m.n_nodes; ++v)
+    if (m.fdof[v] >= 0)
+      for (int k = 0; k < d; ++k) c->fext_free[m.fdof[v] + k] = m.fext[(size_t)v * d + k];
+  double fn = 0;
+  for (double v : c->fext_free) fn += v * v;
+  c->fext_norm = std::sqrt(fn);
+  c->efdof.resize((size_t)m.n_elems * nv);
+  for (size_t k = 0; k < c->efdof.size(); ++k) c->efdof[k] = m.fdof[m.elems[k]];
+  // target flags on the SGN diagonal
+  {
+    System& S = c->A.sgn;
+    for (int32_t t : c->target_dof) S.diag_kind[S.iperm[t]] = 1;
+  }
+  return SGN_OK;
+}
+
+sgn_status sgn_workspace_size(sgn_ctx c, size_t* bytes) {
+  if (!c || !bytes) return SGN_E_ARG;
+  if (c->sticky) return SGN_E_STATE;
+  *bytes = layout(c, nullptr);
+  return SGN_OK;
+}
+
+sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
+  if (!c || !d_ws) return SGN_E_ARG;
+  if (c->sticky) return SGN_E_STATE;
+  if (((uintptr_t)d_ws & 255) != 0) return fail(c, SGN_E_ARG, "workspace must be 256-byte aligned");
+  const size_t need = layout(c, nullptr);
+  if (bytes < need) return fail(c, SGN_E_NOMEM, "workspace too small");
+  layout(c, reinterpret_cast<char*>(d_ws));
+  const Analysis& A = c->A;
+  hipStream_t st = c->stream;
+  for (int si = 0; si < 2; ++si) {
+    const System& S = si == 0 ? A.sgn : A.kx;
+    DevSys& D = c->sys[si];
+    HIPCHK(up(D.rowptr, S.rowptr, st));
+    HIPCHK(up(D.colind, S.colind, st));
+    HIPCHK(up(D.slot_row, S.slot_row, st));
+    HIPCHK(up(D.csr_front_pos, S.csr_front_pos, st));
+    HIPCHK(up(D.slot_ptr, S.slot_ptr, st));
+    HIPCHK(up(D.slot_src, S.slot_src, st));
+    HIPCHK(up(D.diag_kind, S.diag_kind, st));
+    HIPCHK(up(D.frowptr, S.frowptr, st));
+    HIPCHK(up(D.fcol, S.fcol, st));
+    HIPCHK(up(D.fslot, S.fslot, st));
+    HIPCHK(up(D.perm, S.perm, st));
+    HIPCHK(up(D.sn_begin, S.sn_begin, st));
+    HIPCHK(up(D.sn_m, S.sn_m, st));
+    HIPCHK(up(D.sn_front_off, S.sn_front_off, st));
+    HIPCHK(up(D.sn_vec_off, S.sn_vec_off, st));
+    HIPCHK(up(D.sn_rows_ptr, S.sn_rows_ptr, st));
+    HIPCHK(up(D.sn_rows, S.sn_rows, st));
+    HIPCHK(up(D.relmap_off, S.relmap_off, st));
+    HIPCHK(up(D.relmap, S.relmap, st));
+    HIPCHK(up(D.child_ptr, S.child_ptr, st));
+    HIPCHK(up(D.child_list, S.child_list, st));
+    HIPCHK(up(D.var_group_end, S.var_group_end, st));
+    HIPCHK(up(D.level_sn, S.level_sn, st));
+    HIPCHK(up(D.panel_ptr, S.panel_ptr, st));
+    HIPCHK(up(D.panel_col, S.panel_col, st));
+    HIPCHK(up(D.panel_tasks, S.panel_tasks, st));
+    HIPCHK(up(D.upd_tasks, S.upd_tasks, st));
+    HIPCHK(up(D.ea_tasks, S.ea_tasks, st));
+    HIPCHK(up(D.vec_ptr, S.vec_ptr, st));
+    HIPCHK(up(D.vec_src, S.vec_src, st));
+    if (D.n_const) {
+      std::vector<int64_t> cs(D.n_const);
+      for (int64_t i = 0; i < D.n_const; ++i) {
+        const int64_t r = S.iperm[A.mesh.n_x + A.mesh.n_p + i], q = S.iperm[A.mesh.n_x + i];
+        const int64_t hi = std::max(r, q), lo = std::min(r, q);
+        auto b = S.colind.begin() + S.rowptr[hi], e = S.colind.begin() + S.rowptr[hi + 1];
+        cs[i] = std::lower_bound(b, e, (int32_t)lo) - S.colind.begin();
+      }
+      HIPCHK(hipMemcpyAsync(D.const_slots, cs.data(), cs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  }
+  HIPCHK(up(c->d_elems, A.mesh.elems, st));
+  HIPCHK(up(c->d_efdof, c->efdof, st));
+  HIPCHK(up(c->d_rest, A.mesh.rest, st));
+  HIPCHK(up(c->d_fext, c->fext_free, st));
+  HIPCHK(up(c->d_tdof, c->target_dof, st));
+  HIPCHK(up(c->d_tval, c->target_val, st));
+  HIPCHK(up(c->d_pref, c->p_ref, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->has_ws = true;
+  return SGN_OK;
+}
+
+sgn_status sgn_set_targets(sgn_ctx c, const double* h_tval, double ell) {
+  TRY(check_ready(c));
+  if (!h_tval || !(ell > 0)) return fail(c, SGN_E_ARG, "targets");
+  c->target_val.assign(h_tval, h_tval + c->target_dof.size());
+  c->ell = ell;
+  c->mu_reg = c->A.mesh.param_kind == SGN_P_REST_POS ? c->mu_in / (ell * ell) : c->mu_in;
+  HIPCHK(up(c->d_tval, c->target_val, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+sgn_status sgn_equilibrium(sgn_ctx c, const double* d_p, double* d_x, sgn_eq_info* info) {
+  TRY(check_ready(c));
+  if (!d_p || !d_x) return fail(c, SGN_E_ARG, "null state");
+  sgn_status s = equilibrium_impl(c, d_p, d_x, info);
+  if (s != SGN_OK) return fail(c, s, c->err);
+  return SGN_OK;
+}
+
+sgn_status sgn_assemble(sgn_ctx c, const double* d_x, const double* d_p, double* d_rhs, double* d_grad,
+                        double* h_obj) {
+  TRY(check_ready(c));
+  if (!d_x || !d_p) return fail(c, SGN_E_ARG, "null state");
+  sgn_status s = assemble_impl(c, d_x, d_p, d_rhs, d_grad, h_obj);
+  if (s != SGN_OK) return fail(c, s, c->err);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, SGN_E_HIP, hipGetErrorString(e));
+  return SGN_OK;
+}
+
+sgn_status sgn_factor(sgn_ctx c, sgn_factor_info* info) {
+  TRY(check_ready(c));
+  return sgn_factor_impl(c, info);
+}
+
+sgn_status sgn_solve(sgn_ctx c, const double* d_rhs, double* d_sol, sgn_solve_info* info) {
+  TRY(check_ready(c));
+  if (!d_rhs || !d_sol) return fail(c, SGN_E_ARG, "null vector");
+  return sgn_solve_impl(c, d_rhs, d_sol, info);
+}
+
+sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
+  TRY(check_ready(c));
+  if (!d_p || !d_x) return fail(c, SGN_E_ARG, "null state");
+  const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p;
+  sgn_step_info si{};
+  double t0 = now_ms();
+  if (c->opt.rhs_kind != SGN_RHS_ADJOINT) return fail(c, SGN_E_ARG, "sgn_step uses the adjoint right-hand side");
+  if (!c->kx_valid) {
+    sgn_status s = equilibrium_impl(c, d_p, d_x, nullptr);
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  double f0 = 0;
+  double* rhs = c->d_srhs;
+  double* sol = c->d_ssol;
+  {
+    sgn_status s = assemble_impl(c, d_x, d_p, rhs, c->d_g, &f0);
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double t1 = now_ms();
+  si.ms_rhs = 0;
+  si.ms_assemble = t1 - t0;
+  {
+    sgn_factor_info fi{};
+    sgn_status s = sgn_factor_impl(c, &fi);
+    if (s != SGN_OK) return s;
+  }
+  double t2 = now_ms();
+  si.ms_factor = t2 - t1;
+  {
+    sgn_status s = sgn_solve_impl(c, rhs, sol, &si.solve);
+    if (s != SGN_OK) return s;
+  }
+  double t3 = now_ms();
+  si.ms_solve = t3 - t2;
+  // dp = sol[nx : nx+np]; g^T dp and |g|
+  dev_dot(c, np, c->d_g, sol + nx, 12);
+  dev_dot(c, np, c->d_g, c->d_g, 13);
+  double v[2];
+  {
+    sgn_status s = read_scalars(c, 12, 2, v);
+    if (s != SGN_OK) return s;
+  }
+  const double gtdp = v[0];
+  si.grad_norm = std::sqrt(v[1]);
+  si.gtdp = gtdp;
+  si.f0 = f0;
+  // backtracking with one equilibrium per trial
+  double alpha = 1.0;
+  bool ok = false;
+  int nt_iters = 0;
+  for (int h = 0; h <= c->opt.max_halvings; ++h) {
+    launch_axpby(np, 1.0, d_p, alpha, sol + nx, c->d_pt, c->stream);
+    HIPCHK(hipMemcpyAsync(c->d_xt, d_x, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    sgn_eq_info ei{};
+    sgn_status s = equilibrium_impl(c, c->d_pt, c->d_xt, &ei);
+    if (s == SGN_OK) {
+      nt_iters += ei.iters;
+      double f1;
+      TRY(objective_value(c, c->d_xt, c->d_pt, &f1));
+      if (f1 <= f0 + 1e-4 * alpha * gtdp) {
+        si.f1 = f1;
+        ok = true;
+        break;
+      }
+    } else if (s == SGN_E_HIP) {
+      return fail(c, s, c->err);
+    }
+    alpha *= 0.5;
+    ++si.halvings;
+  }
+  si.ms_linesearch = now_ms() - t3;
+  si.alpha = alpha;
+  si.newton_iters = nt_iters;
+  if (info) *info = si;
+  if (!ok) {
+    c->kx_valid = false;
+    return fail(c, SGN_E_LINESEARCH, "line search failed");
+  }
+  HIPCHK(hipMemcpyAsync(d_p, c->d_pt, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d_x, c->d_xt, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+sgn_status sgn_get_sizes(sgn_ctx c, int which, int64_t* n, int64_t* nnz, int64_t* nsn, int64_t* fe, double* fl) {
+  if (!c || (which != 0 && which != 1)) return SGN_E_ARG;
+  const System& S = which == 0 ? c->A.sgn : c->A.kx;
+  if (n) *n = S.N;
+  if (nnz) *nnz = (int64_t)S.colind.size();
+  if (nsn) *nsn = S.nsn;
+  if (fe) *fe = S.factor_entries;
+  if (fl) *fl = S.flops;
+  return SGN_OK;
+}
+
+sgn_status sgn_get_symbolic(sgn_ctx c, int which, int32_t* perm, int32_t* etree, int64_t* rowptr, int32_t* colind) {
+  if (!c || (which != 0 && which != 1)) return SGN_E_ARG;
+  const System& S = which == 0 ? c->A.sgn : c->A.kx;
+  if (perm) std::memcpy(perm, S.perm.data(), bytes_of(S.perm));
+  if (etree) std::memcpy(etree, S.etree.data(), bytes_of(S.etree));
+  if (rowptr) std::memcpy(rowptr, S.rowptr.data(), bytes_of(S.rowptr));
+  if (colind) std::memcpy(colind, S.colind.data(), bytes_of(S.colind));
+  return SGN_OK;
+}
+
+sgn_status sgn_get_values(sgn_ctx c, int which, double* h_vals) {
+  TRY(check_ready(c));
+  if (!h_vals || (which != 0 && which != 1)) return fail(c, SGN_E_ARG, "values");
+  const System& S = which == 0 ? c->A.sgn : c->A.kx;
+  HIPCHK(hipMemcpyAsync(h_vals, c->sys[which].vals, S.colind.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+sgn_status sgn_selftest_mfma(int prec, const double* d_a, const double* d_b, double* d_out, void* stream) {
+  if (!d_a || !d_b || !d_out || (prec != 0 && prec != 1)) return SGN_E_ARG;
+  launch_mfma_probe(prec, d_a, d_b, d_out, (hipStream_t)stream);
+  if (hipGetLastError() != hipSuccess) return SGN_E_HIP;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SGN_E_HIP;
+  return SGN_OK;
+}
+
+const char* sgn_last_error(sgn_ctx c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+void sgn_destroy(sgn_ctx c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,498 @@
+// Element derivative kernels and deterministic assembly (gfx950).
+//
+// Per element e with linear shape functions (the paper's inverse elastic
+// design example, Sec. 5.1, uses linear tetrahedra with a neo-Hookean
+// material): F = Ds Dm^-1, J = det F,
+//   Psi = mu/2 (|F|^2 - d) - mu ln J + lam/2 (ln J)^2,
+//   P   = mu (F - F^-T) + lam ln J F^-T,
+//   dP  = mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam tr(F^-1 dF) F^-T,
+// energy V0 Psi, gradient V0 P Dm^-T (node 0 takes minus the column sum) and
+// the Hessian (dc/dx of Sec. 3.1) column by column from dP along each nodal
+// DOF direction, where dF = e_c w^T is rank one.  For log-modulus
+// parameters E_e = E0 exp(p_e) the constraint Jacobian column dc/dp_e equals
+// the element gradient itself.
+//
+// Assembly never uses floating-point atomics: every element writes its block
+// to an element buffer, and each CSR slot sums its sources in a fixed order
+// (ascending element), so the assembled values are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sgn {
+
+namespace {
+
+template <int D>
+__device__ inline double det(const double (&M)[D][D]) {
+  if constexpr (D == 2) {
+    return M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  } else {
+    return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+           M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  }
+}
+
+template <int D>
+__device__ inline void inverse(const double (&M)[D][D], double dt, double (&R)[D][D]) {
+  double id = 1.0 / dt;
+  if constexpr (D == 2) {
+    R[0][0] = M[1][1] * id;
+    R[0][1] = -M[0][1] * id;
+    R[1][0] = -M[1][0] * id;
+    R[1][1] = M[0][0] * id;
+  } else {
+    R[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) * id;
+    R[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) * id;
+    R[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) * id;
+    R[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) * id;
+    R[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) * id;
+    R[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) * id;
+    R[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) * id;
+    R[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) * id;
+    R[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) * id;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(128) k_element(ElemArgs a) {
+  constexpr int NV = D + 1;
+  constexpr int ND = NV * D;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.ne) return;
+  double xe[NV][D], Xe[NV][D];
+  for (int v = 0; v < NV; ++v) {
+    const int node = a.elems[(int64_t)e * NV + v];
+    const int f = a.efdof[(int64_t)e * NV + v];
+    for (int c = 0; c < D; ++c) {
+      const double r = a.rest[(int64_t)node * D + c];
+      Xe[v][c] = (a.param_kind == 1 && f >= 0) ? a.p[f + c] : r;
+      xe[v][c] = f >= 0 ? a.x[f + c] : r;
+    }
+  }
+  double Dm[D][D], Ds[D][D], Dmi[D][D];
+  for (int c = 0; c < D; ++c)
+    for (int k = 0; k < D; ++k) {
+      Dm[c][k] = Xe[k + 1][c] - Xe[0][c];
+      Ds[c][k] = xe[k + 1][c] - xe[0][c];
+    }
+  const double dm = det<D>(Dm);
+  inverse<D>(Dm, dm, Dmi);
+  const double V0 = dm / (D == 2 ? 2.0 : 6.0);
+  double mu = a.mu0, lam = a.lam0;
+  if (a.param_kind == 0) {
+    const double s = exp(a.p[e]);
+    mu *= s;
+    lam *= s;
+  }
+  double F[D][D];
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < D; ++k) acc += Ds[i][k] * Dmi[k][j];
+      F[i][j] = acc;
+    }
+  const double J = det<D>(F);
+  double* out = a.ebuf + (int64_t)e * a.stride;
+  if (!(J > 0.0)) {
+    atomicAdd(a.inverted, 1);
+    out[a.off_energy] = __builtin_inf();
+    return;
+  }
+  double Fi[D][D];
+  inverse<D>(F, J, Fi);
+  const double lnJ = log(J);
+  double trC = 0.0;
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) trC += F[i][j] * F[i][j];
+  out[a.off_energy] = V0 * (0.5 * mu * (trC - D) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+  if (a.mode == 0) return;
+  // F^-T[i][j] = Fi[j][i]
+  double P[D][D];
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) P[i][j] = mu * (F[i][j] - Fi[j][i]) + lam * lnJ * Fi[j][i];
+  // G = V0 P Dm^-T : G[c][k] = V0 sum_j P[c][j] Dmi[k][j]
+  {
+    double g0[D];
+    for (int c = 0; c < D; ++c) g0[c] = 0.0;
+    for (int k = 0; k < D; ++k)
+      for (int c = 0; c < D; ++c) {
+        double acc = 0.0;
+        for (int j = 0; j < D; ++j) acc += P[c][j] * Dmi[k][j];
+        acc *= V0;
+        out[a.off_grad + (k + 1) * D + c] = acc;
+        g0[c] -= acc;
+      }
+    for (int c = 0; c < D; ++c) out[a.off_grad + c] = g0[c];
+  }
+  if (a.mode == 1) return;
+  const double cA = mu - lam * lnJ;
+  for (int b = 0; b < NV; ++b) {
+    // w = d(Dm^-1 row) for node b: dF = e_cb w^T
+    double w[D];
+    for (int j = 0; j < D; ++j) {
+      if (b > 0) {
+        w[j] = Dmi[b - 1][j];
+      } else {
+        double acc = 0.0;
+        for (int k = 0; k < D; ++k) acc -= Dmi[k][j];
+        w[j] = acc;
+      }
+    }
+    // FinvT w : (F^-T w)_i = sum_a Fi[a][i] w[a]
+    double Fw[D];
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int q = 0; q < D; ++q) acc += Fi[q][i] * w[q];
+      Fw[i] = acc;
+    }
+    for (int cb = 0; cb < D; ++cb) {
+      // tr(F^-1 dF) = sum_i Fi[i][cb] w[i]
+      double tr = 0.0;
+      for (int i = 0; i < D; ++i) tr += Fi[i][cb] * w[i];
+      double dP[D][D];
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j)
+          dP[i][j] = (i == cb ? mu * w[j] : 0.0) + cA * Fw[i] * Fi[j][cb] + lam * tr * Fi[j][i];
+      const int col = b * D + cb;
+      double h0[D];
+      for (int c = 0; c < D; ++c) h0[c] = 0.0;
+      for (int k = 0; k < D; ++k)
+        for (int c = 0; c < D; ++c) {
+          double acc = 0.0;
+          for (int j = 0; j < D; ++j) acc += dP[c][j] * Dmi[k][j];
+          acc *= V0;
+          out[((k + 1) * D + c) * ND + col] = acc;
+          h0[c] -= acc;
+        }
+      for (int c = 0; c < D; ++c) out[c * ND + col] = h0[c];
+    }
+  }
+  if (a.param_kind == 1) {
+    // d(grad)/dX along each rest DOF: Dm moves, so dDm^-1 = -Dm^-1 dDm Dm^-1,
+    // dF = -F dDm Dm^-1, dV0 = V0 tr(Dm^-1 dDm), dG = dV0 P Dm^-T + V0 dP Dm^-T + V0 P d(Dm^-T)
+    for (int b = 0; b < NV; ++b) {
+      for (int cb = 0; cb < D; ++cb) {
+        // dDm = e_cb u^T with u[k] = (b > 0 ? delta(k, b-1) : -1)
+        double u[D];
+        for (int k = 0; k < D; ++k) u[k] = b > 0 ? (k == b - 1 ? 1.0 : 0.0) : -1.0;
+        // (u^T Dm^-1)[j] = sum_k u[k] Dmi[k][j]
+        double uD[D];
+        for (int j = 0; j < D; ++j) {
+          double acc = 0.0;
+          for (int k = 0; k < D; ++k) acc += u[k] * Dmi[k][j];
+          uD[j] = acc;
+        }
+        // dDmi = -Dmi e_cb uD^T : dDmi[i][j] = -Dmi[i][cb] uD[j]
+        // dF = Ds dDmi = -(Ds Dmi[:, cb]) uD^T = -(F e_cb) uD^T -> column cb of F
+        double fc[D];
+        for (int i = 0; i < D; ++i) fc[i] = F[i][cb];
+        const double dV0 = V0 * uD[cb];  // tr(Dmi dDm) = sum_i Dmi[i][cb] u... = (u^T Dmi)[cb]
+        double dF[D][D];
+        for (int i = 0; i < D; ++i)
+          for (int j = 0; j < D; ++j) dF[i][j] = -fc[i] * uD[j];
+        // dP = mu dF + cA F^-T dF^T F^-T + lam tr(F^-1 dF) F^-T
+        double trq = 0.0;
+        for (int i = 0; i < D; ++i)
+          for (int j = 0; j < D; ++j) trq += Fi[i][j] * dF[j][i];
+        double T1[D][D];  // dF^T F^-T : T1[q][j] = sum_r dF[r][q] Fi[j][r]
+        for (int q = 0; q < D; ++q)
+          for (int j = 0; j < D; ++j) {
+            double acc = 0.0;
+            for (int r = 0; r < D; ++r) acc += dF[r][q] * Fi[j][r];
+            T1[q][j] = acc;
+          }
+        double dP[D][D];
+        for (int i = 0; i < D; ++i)
+          for (int j = 0; j < D; ++j) {
+            double acc = 0.0;
+            for (int q = 0; q < D; ++q) acc += Fi[q][i] * T1[q][j];
+            dP[i][j] = mu * dF[i][j] + cA * acc + lam * trq * Fi[j][i];
+          }
+        const int col = b * D + cb;
+        double h0[D];
+        for (int c = 0; c < D; ++c) h0[c] = 0.0;
+        for (int k = 0; k < D; ++k)
+          for (int c = 0; c < D; ++c) {
+            // G[c][k] = V0 sum_j P[c][j] Dmi[k][j]
+            double acc = 0.0;
+            for (int j = 0; j < D; ++j)
+              acc += dV0 * P[c][j] * Dmi[k][j] + V0 * dP[c][j] * Dmi[k][j] - V0 * P[c][j] * Dmi[k][cb] * uD[j];
+            out[a.off_kp + ((k + 1) * D + c) * ND + col] = acc;
+            h0[c] -= acc;
+          }
+        for (int c = 0; c < D; ++c) out[a.off_kp + c * ND + col] = h0[c];
+      }
+    }
+  }
+}
+
+__global__ void k_gather_slots(int64_t nnz, const int64_t* __restrict__ ptr, const int32_t* __restrict__ src,
+                               const double* __restrict__ ebuf, double* __restrict__ vals) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int64_t q = ptr[t]; q < ptr[t + 1]; ++q) acc += ebuf[src[q]];
+    vals[t] = acc;
+  }
+}
+
+__global__ void k_diag_add(int64_t N, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ kind,
+                           double a_target, double c_param, double eps_x, double eps_lambda, double* vals) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = kind[i];
+    double v = 0.0;
+    if (k == 1) v = a_target + eps_x;
+    else if (k == 2) v = c_param;
+    else if (k == 3) v = eps_x;
+    else if (k == 4) v = -eps_lambda;
+    vals[rowptr[i + 1] - 1] += v;
+  }
+}
+
+__global__ void k_const_slots(int64_t n, const int64_t* slots, double value, double* vals) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    vals[slots[i]] += value;
+}
+
+__global__ void k_gather_vec(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ src,
+                             const double* __restrict__ ebuf, const double* __restrict__ fext,
+                             const double* __restrict__ pforce, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) acc += ebuf[src[q]];
+    acc -= fext[i];
+    if (pforce) acc -= pforce[i];
+    out[i] = acc;
+  }
+}
+
+// Fixed-shape block reduction: 256 threads, pairwise tree in LDS.
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(256) k_dot_partials(int64_t n, const double* __restrict__ a,
+                                                      const double* __restrict__ b, int64_t sa, int absval,
+                                                      double* __restrict__ partials) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double x = absval ? fabs(a[i * sa]) : a[i * sa];
+    acc += b ? x * b[i] : x;
+  }
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256) k_final_sum(const double* partials, int np, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += partials[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = r;
+}
+
+__global__ void __launch_bounds__(256) k_max_abs_partials(int64_t n, const double* __restrict__ a,
+                                                          double* __restrict__ partials) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) acc = fmax(acc, fabs(a[i]));
+  const double r = block_max(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256) k_final_max(const double* partials, int np, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc = fmax(acc, partials[i]);
+  const double r = block_max(acc, sh);
+  if (threadIdx.x == 0) *out = r;
+}
+
+__global__ void k_gather_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const double v = in[perm[k]];
+    out[k] = scale ? scale[k] * v : v;
+  }
+}
+
+__global__ void k_scatter_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const double v = in[k];
+    out[perm[k]] = scale ? scale[k] * v : v;
+  }
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = a * x[k] + (y ? b * y[k] : 0.0);
+}
+
+__global__ void k_scale(int64_t n, const double* sc, const double* in, double* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = sc[k] * in[k];
+}
+
+__global__ void k_fill(int64_t n, double v, double* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = v;
+}
+
+__global__ void k_fill_bytes(int64_t n16, uint4* out) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n16; k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = z;
+}
+
+// one wave (64 lanes) per row: lanes stride the row, then a fixed butterfly
+__global__ void __launch_bounds__(256) k_spmv(int64_t N, const int64_t* __restrict__ frp,
+                                              const int32_t* __restrict__ fcol, const int32_t* __restrict__ fslot,
+                                              const double* __restrict__ vals, const double* __restrict__ x,
+                                              const double* __restrict__ b, double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  double acc = 0.0;
+  for (int64_t t = frp[row] + lane; t < frp[row + 1]; t += 64) acc += vals[fslot[t]] * x[fcol[t]];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[row] = b ? b[row] - acc : acc;
+}
+
+__global__ void __launch_bounds__(256) k_row_scaling(int64_t N, const int64_t* __restrict__ frp,
+                                                     const int32_t* __restrict__ fslot,
+                                                     const double* __restrict__ vals, double* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  double m = 0.0;
+  for (int64_t t = frp[row] + lane; t < frp[row + 1]; t += 64) m = fmax(m, fabs(vals[fslot[t]]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if (lane == 0) scale[row] = m > 0.0 ? 1.0 / sqrt(m) : 1.0;
+}
+
+__global__ void k_objective_fx(int64_t nt, const int32_t* tdof, const double* tval, const double* x, double c,
+                               double* fx) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nt; k += (int64_t)gridDim.x * blockDim.x)
+    fx[tdof[k]] = c * (x[tdof[k]] - tval[k]);
+}
+
+inline unsigned grid_for(int64_t n, int bs, int64_t cap = 65536) {
+  int64_t g = (n + bs - 1) / bs;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+void launch_element(const ElemArgs& a, hipStream_t s) {
+  if (a.ne <= 0) return;
+  const unsigned g = (unsigned)((a.ne + 127) / 128);
+  if (a.dim == 2) k_element<2><<<g, 128, 0, s>>>(a);
+  else k_element<3><<<g, 128, 0, s>>>(a);
+}
+
+void launch_gather_slots(int64_t nnz, const int64_t* ptr, const int32_t* src, const double* ebuf, double* vals,
+                         hipStream_t s) {
+  if (nnz > 0) k_gather_slots<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, ptr, src, ebuf, vals);
+}
+
+void launch_diag_add(int64_t N, const int64_t* rowptr, const int32_t* kind, double a_target, double c_param,
+                     double eps_x, double eps_lambda, double* vals, hipStream_t s) {
+  if (N > 0) k_diag_add<<<grid_for(N, 256), 256, 0, s>>>(N, rowptr, kind, a_target, c_param, eps_x, eps_lambda, vals);
+}
+
+void launch_const_slots(int64_t n, const int64_t* slots, double value, double* vals, hipStream_t s) {
+  if (n > 0) k_const_slots<<<grid_for(n, 256), 256, 0, s>>>(n, slots, value, vals);
+}
+
+void launch_gather_vec(int64_t n, const int64_t* ptr, const int32_t* src, const double* ebuf, const double* fext,
+                       const double* pforce, double* out, hipStream_t s) {
+  if (n > 0) k_gather_vec<<<grid_for(n, 256), 256, 0, s>>>(n, ptr, src, ebuf, fext, pforce, out);
+}
+
+void launch_dot_partials(int64_t n, const double* a, const double* b, int64_t stride_a, int absval, double* partials,
+                         hipStream_t s) {
+  k_dot_partials<<<kRedBlocks, 256, 0, s>>>(n, a, b, stride_a, absval, partials);
+}
+
+void launch_final_sum(const double* partials, int np, double* out, hipStream_t s) {
+  k_final_sum<<<1, 256, 0, s>>>(partials, np, out);
+}
+
+void launch_max_abs_partials(int64_t n, const double* a, double* partials, hipStream_t s) {
+  k_max_abs_partials<<<kRedBlocks, 256, 0, s>>>(n, a, partials);
+}
+
+void launch_final_max(const double* partials, int np, double* out, hipStream_t s) {
+  k_final_max<<<1, 256, 0, s>>>(partials, np, out);
+}
+
+void launch_gather_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out,
+                        hipStream_t s) {
+  if (n > 0) k_gather_perm<<<grid_for(n, 256), 256, 0, s>>>(n, perm, scale, in, out);
+}
+
+void launch_scatter_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out,
+                         hipStream_t s) {
+  if (n > 0) k_scatter_perm<<<grid_for(n, 256), 256, 0, s>>>(n, perm, scale, in, out);
+}
+
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t s) {
+  if (n > 0) k_axpby<<<grid_for(n, 256), 256, 0, s>>>(n, a, x, b, y, out);
+}
+
+void launch_scale(int64_t n, const double* sc, const double* in, double* out, hipStream_t s) {
+  if (n > 0) k_scale<<<grid_for(n, 256), 256, 0, s>>>(n, sc, in, out);
+}
+
+void launch_fill(int64_t n, double v, double* out, hipStream_t s) {
+  if (n > 0) k_fill<<<grid_for(n, 256), 256, 0, s>>>(n, v, out);
+}
+
+void launch_fill_bytes(int64_t nbytes, void* out, hipStream_t s) {
+  const int64_t n16 = nbytes / 16;  // callers pass 16-byte multiples
+  if (n16 > 0) k_fill_bytes<<<grid_for(n16, 256, 1 << 20), 256, 0, s>>>(n16, (uint4*)out);
+}
+
+void launch_spmv(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot, const double* vals,
+                 const double* x, double* y, hipStream_t s) {
+  if (N > 0) k_spmv<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, nullptr, y);
+}
+
+void launch_residual(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+                     const double* vals, const double* x, const double* b, double* out, hipStream_t s) {
+  if (N > 0) k_spmv<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, b, out);
+}
+
+void launch_row_scaling(int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals, double* scale,
+                        hipStream_t s) {
+  if (N > 0) k_row_scaling<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(N, frowptr, fslot, vals, scale);
+}
+
+void launch_objective_fx(int64_t nt, const int32_t* tdof, const double* tval, const double* x, double w_over_ell2,
+                         double* fx, hipStream_t s) {
+  if (nt > 0) k_objective_fx<<<grid_for(nt, 256), 256, 0, s>>>(nt, tdof, tval, x, w_over_ell2, fx);
+}
+
+}  // namespace sgn

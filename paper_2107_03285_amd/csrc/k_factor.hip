@@ -1,0 +1,513 @@
+// Multifrontal supernodal LDL^T of the SGN saddle-point matrix (gfx950).
+//
+// The paper factorises eq. sparseSystemGN with a sparse direct solver on a
+// CPU (Sec. 5, "Solving the saddle point problem"); here every front is a
+// dense m x m column-major block (pivot columns first) held in HBM for the
+// whole factorisation, processed level by level of the supernode tree:
+//   1. original entries of the scaled matrix are scattered into the fronts;
+//   2. children's Schur complements are added in a fixed child order
+//      (extend-add, one launch per child rank, so sums are deterministic);
+//   3. per panel of <= 64 pivot columns (whole node groups):
+//        - the panel's diagonal block is factorised in LDS in FP64 with
+//          Bunch-Kaufman 1x1/2x2 pivots restricted to one node's group;
+//        - rows below are solved against it (TRSM, one thread per row);
+//        - trailing columns are updated with MFMA tiles; updates of columns
+//          beyond the current block of 4 panels are delayed and applied
+//          with k = 256 (one rank-256 update instead of four rank-64 ones).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sgn {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+constexpr double kAlphaBK = 0.6403882032022076;  // (1 + sqrt(17)) / 8
+
+// Output row (M index) held by accumulator register `reg` of `lane` for the
+// 16x16x4 matrix-core products; the operand layouts are A[lane%16][lane/16]
+// and B[lane/16][lane%16] for both types, the column is lane%16.  Measured on
+// gfx950 (the self-test entry point checks it): the FP64 product interleaves
+// rows across registers, the FP32 one keeps four consecutive rows per lane.
+template <typename T>
+__device__ inline int mfma_row(int lane, int reg) {
+  return sizeof(T) == 8 ? (lane >> 4) + 4 * reg : 4 * (lane >> 4) + reg;
+}
+
+template <typename T>
+__global__ void k_csr_to_fronts(int64_t nnz, const int32_t* __restrict__ slot_row, const int32_t* __restrict__ colind,
+                                const int64_t* __restrict__ pos, const double* __restrict__ vals,
+                                const double* __restrict__ scale, T* __restrict__ front) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = slot_row[t], j = colind[t];
+    front[pos[t]] = (T)(scale[i] * vals[t] * scale[j]);
+  }
+}
+
+// One block per child column: adds the child's Schur complement column
+// (rows >= column) into the parent front through the child's relative map.
+template <typename T>
+__global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, const int64_t* __restrict__ tasks, FrontArgs f,
+                                                    T* __restrict__ front) {
+  const int64_t b = blockIdx.x;
+  int64_t lo = 0, hi = ntasks - 1;
+  while (lo < hi) {  // last task with prefix <= b
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (tasks[mid * 3 + 2] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int C = (int)tasks[lo * 3], P = (int)tasks[lo * 3 + 1];
+  const int64_t c = b - tasks[lo * 3 + 2];
+  const int64_t sC = f.sn_begin[C + 1] - f.sn_begin[C], mC = f.sn_m[C], uC = mC - sC;
+  if (c >= uC) return;
+  const int64_t mP = f.sn_m[P];
+  const T* src = front + f.sn_front_off[C] + sC + (sC + c) * mC;
+  T* dst = front + f.sn_front_off[P];
+  const int32_t* rel = f.relmap + f.relmap_off[C];
+  const int64_t Cc = rel[c];
+  for (int64_t r = c + threadIdx.x; r < uC; r += 256) dst[rel[r] + Cc * mP] += src[r];
+}
+
+// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
+                                                    T* __restrict__ front) {
+  __shared__ double A[64][65];
+  __shared__ int pos[64];
+  __shared__ int s_kind, s_p, s_q, s_perm;
+  const int tid = threadIdx.x;
+  const int sn = (int)tasks[blockIdx.x * 3];
+  const int c0 = (int)tasks[blockIdx.x * 3 + 1], c1 = (int)tasks[blockIdx.x * 3 + 2];
+  const int w = c1 - c0;
+  const int64_t m = f.sn_m[sn];
+  const int64_t gbase = f.sn_begin[sn] + c0;  // global var index of panel column 0
+  T* F = front + f.sn_front_off[sn];
+  for (int idx = tid; idx < w * w; idx += 256) {
+    const int i = idx % w, j = idx / w;
+    if (i >= j) {
+      const double v = (double)F[(c0 + i) + (int64_t)(c0 + j) * m];
+      A[i][j] = v;
+      A[j][i] = v;
+    }
+  }
+  if (tid < 64) pos[tid] = tid;
+  if (tid == 0) s_perm = 0;
+  __syncthreads();
+  int k = 0;
+  while (k < w) {
+    if (tid == 0) {
+      const int gend = (int)(f.var_group_end[gbase + k] - gbase);
+      const double absakk = fabs(A[k][k]);
+      double colmax = 0.0;
+      int imax = k;
+      for (int i = k + 1; i < gend; ++i)
+        if (fabs(A[i][k]) > colmax) {
+          colmax = fabs(A[i][k]);
+          imax = i;
+        }
+      int kind = 1, p = -1, q = -1;
+      if (fmax(absakk, colmax) <= f.piv_tol) {
+        A[k][k] = A[k][k] >= 0.0 ? f.piv_tol : -f.piv_tol;
+        atomicAdd(&f.counters[0], 1);
+      } else if (absakk >= kAlphaBK * colmax) {
+        kind = 1;
+      } else {
+        double rowmax = 0.0;
+        for (int j = k; j < gend; ++j)
+          if (j != imax) rowmax = fmax(rowmax, fabs(A[imax][j]));
+        if (absakk * rowmax >= kAlphaBK * colmax * colmax) {
+          kind = 1;
+        } else if (fabs(A[imax][imax]) >= kAlphaBK * rowmax) {
+          kind = 1;
+          p = k;
+          q = imax;
+        } else {
+          kind = 2;
+          p = k + 1;
+          q = imax;
+        }
+      }
+      s_kind = kind;
+      s_p = p;
+      s_q = q;
+      if (p >= 0 && p != q) s_perm = 1;
+    }
+    __syncthreads();
+    const int kind = s_kind, p = s_p, q = s_q;
+    if (p >= 0 && p != q) {
+      // symmetric swap of indices p and q in the full square block
+      for (int j = tid; j < w; j += 256) {
+        const double t = A[p][j];
+        A[p][j] = A[q][j];
+        A[q][j] = t;
+      }
+      __syncthreads();
+      for (int i = tid; i < w; i += 256) {
+        const double t = A[i][p];
+        A[i][p] = A[i][q];
+        A[i][q] = t;
+      }
+      if (tid == 0) {
+        const int t = pos[p];
+        pos[p] = pos[q];
+        pos[q] = t;
+      }
+      __syncthreads();
+    }
+    if (kind == 1) {
+      double d = A[k][k];
+      if (fabs(d) < f.piv_tol) {
+        __syncthreads();
+        if (tid == 0) {
+          A[k][k] = d >= 0.0 ? f.piv_tol : -f.piv_tol;
+          atomicAdd(&f.counters[0], 1);
+        }
+        __syncthreads();
+        d = A[k][k];
+      }
+      const double id = 1.0 / d;
+      const int n = w - k - 1;
+      for (int idx = tid; idx < n * n; idx += 256) {
+        const int i = k + 1 + idx % n, j = k + 1 + idx / n;
+        A[i][j] -= A[i][k] * A[j][k] * id;
+      }
+      __syncthreads();
+      for (int i = k + 1 + tid; i < w; i += 256) A[i][k] *= id;
+      if (tid == 0) {
+        f.dpiv[gbase + k] = d;
+        f.epiv[gbase + k] = 0.0;
+        f.pivtype[gbase + k] = 0;
+      }
+      __syncthreads();
+      k += 1;
+    } else {
+      const double a = A[k][k], b = A[k + 1][k], c = A[k + 1][k + 1];
+      const double det = a * c - b * b;
+      const double i00 = c / det, i01 = -b / det, i11 = a / det;
+      const int n = w - k - 2;
+      for (int idx = tid; idx < n * n; idx += 256) {
+        const int i = k + 2 + idx % n, j = k + 2 + idx / n;
+        const double ui0 = A[i][k], ui1 = A[i][k + 1], uj0 = A[j][k], uj1 = A[j][k + 1];
+        A[i][j] -= ui0 * (i00 * uj0 + i01 * uj1) + ui1 * (i01 * uj0 + i11 * uj1);
+      }
+      __syncthreads();
+      for (int i = k + 2 + tid; i < w; i += 256) {
+        const double u0 = A[i][k], u1 = A[i][k + 1];
+        A[i][k] = u0 * i00 + u1 * i01;
+        A[i][k + 1] = u0 * i01 + u1 * i11;
+      }
+      if (tid == 0) {
+        f.dpiv[gbase + k] = a;
+        f.dpiv[gbase + k + 1] = c;
+        f.epiv[gbase + k] = b;
+        f.epiv[gbase + k + 1] = 0.0;
+        f.pivtype[gbase + k] = 1;
+        f.pivtype[gbase + k + 1] = 2;
+      }
+      __syncthreads();
+      k += 2;
+    }
+  }
+  // write back L11 (unit lower; zero inside 2x2 blocks) and the pivot order
+  for (int idx = tid; idx < w * w; idx += 256) {
+    const int i = idx % w, j = idx / w;
+    if (i < j) continue;
+    double v;
+    if (i == j) v = 1.0;
+    else if (i == j + 1 && f.pivtype[gbase + j] == 1) v = 0.0;
+    else v = A[i][j];
+    F[(c0 + i) + (int64_t)(c0 + j) * m] = (T)v;
+  }
+  if (tid < w) f.lperm[gbase + tid] = c0 + pos[tid];
+  if (s_perm && c0 > 0) {
+    // apply the row interchanges to the already factorised columns [0, c0)
+    const int kk = tid & 63, jj = tid >> 6;
+    for (int j0 = 0; j0 < c0; j0 += 4) {
+      const int j = j0 + jj;
+      T v = (T)0;
+      if (kk < w && j < c0) v = F[(c0 + pos[kk]) + (int64_t)j * m];
+      __syncthreads();
+      if (kk < w && j < c0) F[(c0 + kk) + (int64_t)j * m] = v;
+      __syncthreads();
+    }
+  }
+}
+
+// Rows [c1, m) of a panel: L21 = F21 P^T L11^-T D^-1, one thread per row, FP64 arithmetic.
+template <typename T>
+__global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ tasks, FrontArgs f,
+                                                    T* __restrict__ front) {
+  __shared__ double L[64][65];
+  __shared__ double dd[64], ee[64];
+  __shared__ int ty[64], ps[64];
+  const int tid = threadIdx.x;
+  const int64_t task = blockIdx.x;
+  const int sn = (int)tasks[task * 3];
+  const int c0 = (int)tasks[task * 3 + 1], c1 = (int)tasks[task * 3 + 2];
+  const int w = c1 - c0;
+  const int64_t m = f.sn_m[sn];
+  const int64_t r = c1 + (int64_t)blockIdx.y * 256 + tid;
+  if (c1 + (int64_t)blockIdx.y * 256 >= m) return;
+  const int64_t gbase = f.sn_begin[sn] + c0;
+  T* F = front + f.sn_front_off[sn];
+  for (int idx = tid; idx < w * w; idx += 256) {
+    const int i = idx % w, j = idx / w;
+    L[i][j] = i > j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
+  }
+  if (tid < w) {
+    dd[tid] = f.dpiv[gbase + tid];
+    ee[tid] = f.epiv[gbase + tid];
+    ty[tid] = f.pivtype[gbase + tid];
+    ps[tid] = f.lperm[gbase + tid] - c0;
+  }
+  __syncthreads();
+  if (r >= m) return;
+  double v[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) v[k] = k < w ? (double)F[r + (int64_t)(c0 + ps[k]) * m] : 0.0;
+#pragma unroll
+  for (int k = 1; k < 64; ++k) {
+    if (k < w) {
+      double acc = v[k];
+#pragma unroll
+      for (int j = 0; j < k; ++j) acc -= v[j] * L[k][j];
+      v[k] = acc;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    if (k < w) {
+      if (ty[k] == 0) {
+        v[k] = v[k] / dd[k];
+      } else if (ty[k] == 1 && k + 1 < 64) {
+        const double a = dd[k], b = ee[k], c = dd[k + 1];
+        const double det = a * c - b * b;
+        const double x0 = v[k], x1 = v[k + 1];
+        v[k] = (c * x0 - b * x1) / det;
+        v[k + 1] = (a * x1 - b * x0) / det;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 64; ++k)
+    if (k < w) F[r + (int64_t)(c0 + k) * m] = (T)v[k];
+}
+
+template <typename T>
+__device__ inline T ld_value(const T* F, int64_t m, int64_t c, int64_t k, int64_t g, const FrontArgs& f) {
+  const int t = f.pivtype[g];
+  double v;
+  if (t == 0) v = (double)F[c + k * m] * f.dpiv[g];
+  else if (t == 1) v = (double)F[c + k * m] * f.dpiv[g] + (double)F[c + (k + 1) * m] * f.epiv[g];
+  else v = (double)F[c + (k - 1) * m] * f.epiv[g - 1] + (double)F[c + k * m] * f.dpiv[g];
+  return (T)v;
+}
+
+// C[r, c] -= sum_{k in [k0,k1)} L[r,k] (L D)[c,k] on one 64 x 64 tile, MFMA 16x16x4.
+template <typename T>
+__global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* __restrict__ tasks, FrontArgs f,
+                                                T* __restrict__ front) {
+  __shared__ T sL[16][68];
+  __shared__ T sW[16][68];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t b = blockIdx.x;
+  int64_t lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (tasks[mid * 6 + 5] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t* tk = tasks + lo * 6;
+  const int sn = (int)tk[0];
+  const int64_t k0 = tk[1], k1 = tk[2], cb = tk[3], ce = tk[4];
+  const int64_t m = f.sn_m[sn];
+  int64_t lt = b - tk[5];
+  const int64_t R = (m - cb + 63) / 64;
+  const int64_t ct = (ce - cb + 63) / 64;
+  int64_t j = 0;
+  while (j < ct && lt >= R - j) {
+    lt -= R - j;
+    ++j;
+  }
+  if (j >= ct) return;  // beyond the task's tiles (never for a consistent schedule)
+  const int64_t i = j + lt;
+  const int64_t r0 = cb + 64 * i, cc0 = cb + 64 * j;
+  const int64_t gsn = f.sn_begin[sn];
+  T* F = front + f.sn_front_off[sn];
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  dbl4 accd[2][2];
+  flt4 accf[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      accd[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+      accf[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
+    }
+  const int64_t cmax = ce < m ? ce : m;
+  for (int64_t kb = k0; kb < k1; kb += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int rr = idx & 63, kk = idx >> 6;
+      const int64_t k = kb + kk;
+      const int64_t r = r0 + rr, c = cc0 + rr;
+      sL[kk][rr] = (k < k1 && r < m) ? F[r + k * m] : (T)0;
+      sW[kk][rr] = (k < k1 && c < cmax) ? ld_value<T>(F, m, c, k, gsn + k, f) : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          const T av = sW[kr][wc + bj * 16 + (lane & 15)];
+          const T bv = sL[kr][wr + bi * 16 + (lane & 15)];
+          if constexpr (sizeof(T) == 8) {
+            accd[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accd[bi][bj], 0, 0, 0);
+          } else {
+            accf[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, accf[bi][bj], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) {
+        const int64_t r = r0 + wr + bi * 16 + (lane & 15);
+        const int64_t c = cc0 + wc + bj * 16 + mfma_row<T>(lane, reg);
+        if (r < m && c < cmax) {
+          const double a = sizeof(T) == 8 ? (double)accd[bi][bj][reg] : (double)accf[bi][bj][reg];
+          F[r + c * m] -= (T)a;
+        }
+      }
+}
+
+__global__ void k_inertia(int64_t N, const double* dpiv, const double* epiv, const int32_t* pivtype,
+                          unsigned long long* counts, double* minabs_partials) {
+  __shared__ double sh[256];
+  unsigned long long np = 0, nn = 0, nz = 0;
+  double mn = __builtin_inf();
+  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
+    const int t = pivtype[k];
+    if (t == 0) {
+      const double d = dpiv[k];
+      if (d > 0) ++np;
+      else if (d < 0) ++nn;
+      else ++nz;
+      mn = fmin(mn, fabs(d));
+    } else if (t == 1) {
+      const double a = dpiv[k], c = dpiv[k + 1], b = epiv[k];
+      const double det = a * c - b * b, tr = a + c;
+      if (det < 0) {
+        ++np;
+        ++nn;
+      } else if (det > 0) {
+        if (tr > 0) np += 2;
+        else nn += 2;
+      } else {
+        nz += 2;
+      }
+      const double h = 0.5 * tr, r = sqrt(0.25 * (a - c) * (a - c) + b * b);
+      mn = fmin(mn, fmin(fabs(h - r), fabs(h + r)));
+    }
+  }
+  if (np) atomicAdd(&counts[0], np);
+  if (nn) atomicAdd(&counts[1], nn);
+  if (nz) atomicAdd(&counts[2], nz);
+  sh[threadIdx.x] = mn;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) minabs_partials[blockIdx.x] = sh[0];
+}
+
+__global__ void k_mfma_probe_f64(const double* a, const double* b, double* out) {
+  const int lane = threadIdx.x;
+  const double av = a[(lane & 15) * 4 + (lane >> 4)];  // A[i][k], i = lane % 16, k = lane / 16
+  const double bv = b[(lane >> 4) * 16 + (lane & 15)]; // B[k][j], k = lane / 16, j = lane % 16
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) out[mfma_row<double>(lane, r) * 16 + (lane & 15)] = acc[r];
+}
+
+__global__ void k_mfma_probe_f32(const double* a, const double* b, double* out) {
+  const int lane = threadIdx.x;
+  const float av = (float)a[(lane & 15) * 4 + (lane >> 4)];
+  const float bv = (float)b[(lane >> 4) * 16 + (lane & 15)];
+  flt4 acc = {0.f, 0.f, 0.f, 0.f};
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) out[mfma_row<float>(lane, r) * 16 + (lane & 15)] = (double)acc[r];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* colind, const int64_t* pos,
+                          const double* vals, const double* scale, T* front, hipStream_t s) {
+  if (nnz <= 0) return;
+  int64_t g = (nnz + 255) / 256;
+  if (g > 65536) g = 65536;
+  k_csr_to_fronts<T><<<(unsigned)g, 256, 0, s>>>(nnz, slot_row, colind, pos, vals, scale, front);
+}
+
+template <typename T>
+void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const FrontArgs& f, T* front,
+                       hipStream_t s) {
+  if (ntasks > 0 && nblocks > 0) k_extend_add<T><<<(unsigned)nblocks, 256, 0, s>>>(ntasks, tasks, f, front);
+}
+
+template <typename T>
+void launch_panel_diag(int64_t ntasks, const int64_t* tasks, const FrontArgs& f, T* front, hipStream_t s) {
+  if (ntasks > 0) k_panel_diag<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, f, front);
+}
+
+template <typename T>
+void launch_panel_trsm(int64_t ntasks, int64_t max_rows, const int64_t* tasks, const FrontArgs& f, T* front,
+                       hipStream_t s) {
+  if (ntasks <= 0 || max_rows <= 0) return;
+  dim3 g((unsigned)ntasks, (unsigned)((max_rows + 255) / 256));
+  k_panel_trsm<T><<<g, 256, 0, s>>>(tasks, f, front);
+}
+
+template <typename T>
+void launch_update(int64_t ntasks, int64_t ntiles, const int64_t* tasks, const FrontArgs& f, T* front,
+                   hipStream_t s) {
+  if (ntasks > 0 && ntiles > 0) k_update<T><<<(unsigned)ntiles, 256, 0, s>>>(ntasks, tasks, f, front);
+}
+
+void launch_inertia(int64_t N, const double* dpiv, const double* epiv, const int32_t* pivtype,
+                    unsigned long long* counts, double* minabs_partials, hipStream_t s) {
+  k_inertia<<<kRedBlocks, 256, 0, s>>>(N, dpiv, epiv, pivtype, counts, minabs_partials);
+}
+
+void launch_mfma_probe(int prec, const double* a, const double* b, double* out, hipStream_t s) {
+  if (prec == 0) k_mfma_probe_f64<<<1, 64, 0, s>>>(a, b, out);
+  else k_mfma_probe_f32<<<1, 64, 0, s>>>(a, b, out);
+}
+
+template void launch_csr_to_fronts<double>(int64_t, const int32_t*, const int32_t*, const int64_t*, const double*,
+                                           const double*, double*, hipStream_t);
+template void launch_csr_to_fronts<float>(int64_t, const int32_t*, const int32_t*, const int64_t*, const double*,
+                                          const double*, float*, hipStream_t);
+template void launch_extend_add<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
+template void launch_extend_add<float>(int64_t, int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+template void launch_panel_diag<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
+template void launch_panel_diag<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+template void launch_panel_trsm<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
+template void launch_panel_trsm<float>(int64_t, int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+template void launch_update<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
+template void launch_update<float>(int64_t, int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+
+}  // namespace sgn

@@ -1,0 +1,125 @@
+// Launchers of the gfx950 kernels (all asynchronous on the given stream).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sgn {
+
+constexpr int kRedBlocks = 1024;  // fixed partition of deterministic reductions
+
+// ---------------------------------------------------------------- element + assembly
+struct ElemArgs {
+  int dim, ne, param_kind, mode;  // mode 0 energy, 1 energy+gradient, 2 + Hessian (+ Kp)
+  const int32_t* elems;           // [ne*(dim+1)]
+  const int32_t* efdof;           // [ne*(dim+1)] free DOF of each element node, -1 fixed
+  const double* rest;             // [n_nodes*dim]
+  const double* x;                // [n_x]
+  const double* p;                // [n_p]
+  double mu0, lam0;
+  double* ebuf;
+  int stride, off_grad, off_kp, off_energy;
+  int* inverted;                  // counter of elements with J <= 0
+};
+void launch_element(const ElemArgs& a, hipStream_t s);
+// vals[t] = sum of ebuf[src] over the slot's sources (fixed order)
+void launch_gather_slots(int64_t nnz, const int64_t* ptr, const int32_t* src, const double* ebuf,
+                         double* vals, hipStream_t s);
+// vals[diag(i)] += diag value of var kind; plus constant slots (nodal-force Kp)
+void launch_diag_add(int64_t N, const int64_t* rowptr, const int32_t* kind, double a_target, double c_param,
+                     double eps_x, double eps_lambda, double* vals, hipStream_t s);
+void launch_const_slots(int64_t n, const int64_t* slots, double value, double* vals, hipStream_t s);
+// c[i] = sum(ebuf[src]) - fext[i] - (pforce ? p[i] : 0)
+void launch_gather_vec(int64_t n, const int64_t* ptr, const int32_t* src, const double* ebuf,
+                       const double* fext, const double* pforce, double* out, hipStream_t s);
+// deterministic reductions: partials[kRedBlocks], then a single-block final sum
+void launch_dot_partials(int64_t n, const double* a, const double* b, int64_t stride_a, int absval, double* partials,
+                         hipStream_t s);
+void launch_final_sum(const double* partials, int np, double* out, hipStream_t s);
+void launch_max_abs_partials(int64_t n, const double* a, double* partials, hipStream_t s);
+void launch_final_max(const double* partials, int np, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- vectors / permutations
+// out[k] = scale[k] * in[perm[k]] (scale may be null)
+void launch_gather_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out,
+                        hipStream_t s);
+// out[perm[k]] = scale[k] * in[k] (scale may be null)
+void launch_scatter_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out,
+                         hipStream_t s);
+void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t s);
+void launch_fill(int64_t n, double v, double* out, hipStream_t s);
+// out = s .* in (elementwise; out may alias in)
+void launch_scale(int64_t n, const double* s, const double* in, double* out, hipStream_t st);
+void launch_fill_bytes(int64_t nbytes, void* out, hipStream_t s);
+// y = K x with the symmetric matrix stored as lower slots and addressed through the full CSR
+void launch_spmv(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+                 const double* vals, const double* x, double* y, hipStream_t s);
+// out = b - K x
+void launch_residual(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+                     const double* vals, const double* x, const double* b, double* out, hipStream_t s);
+// scale[i] = 1 / sqrt(max_j |K_ij|) over the full row (1 when the row is empty)
+void launch_row_scaling(int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals,
+                        double* scale, hipStream_t s);
+// objective pieces on free DOFs: fx = w (x_T - t)/ell^2 on targets (else 0)
+void launch_objective_fx(int64_t nt, const int32_t* tdof, const double* tval, const double* x, double w_over_ell2,
+                         double* fx, hipStream_t s);
+
+// ---------------------------------------------------------------- factorisation
+struct FrontArgs {
+  const int32_t* sn_begin;
+  const int32_t* sn_m;
+  const int64_t* sn_front_off;
+  const int64_t* sn_rows_ptr;
+  const int32_t* sn_rows;
+  const int64_t* relmap_off;
+  const int32_t* relmap;
+  const int32_t* var_group_end;
+  double* dpiv;      // [N] diagonal of D
+  double* epiv;      // [N] off-diagonal of a 2x2 block (stored at its first index)
+  int32_t* pivtype;  // [N] 0 = 1x1, 1 = first of 2x2, 2 = second of 2x2
+  int32_t* lperm;    // [N] local pivot order: position -> original local index
+  int* counters;     // [0] perturbed pivots
+  double piv_tol;
+};
+template <typename T>
+void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* colind, const int64_t* pos,
+                          const double* vals, const double* scale, T* front, hipStream_t s);
+template <typename T>
+void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const FrontArgs& f, T* front,
+                       hipStream_t s);
+template <typename T>
+void launch_panel_diag(int64_t ntasks, const int64_t* tasks, const FrontArgs& f, T* front, hipStream_t s);
+template <typename T>
+void launch_panel_trsm(int64_t ntasks, int64_t max_rows, const int64_t* tasks, const FrontArgs& f, T* front,
+                       hipStream_t s);
+template <typename T>
+void launch_update(int64_t ntasks, int64_t ntiles, const int64_t* tasks, const FrontArgs& f, T* front,
+                   hipStream_t s);
+// inertia: counts[0..2] += (pos, neg, zero); minabs via partial mins
+void launch_inertia(int64_t N, const double* dpiv, const double* epiv, const int32_t* pivtype,
+                    unsigned long long* counts, double* minabs_partials, hipStream_t s);
+
+// ---------------------------------------------------------------- solves
+struct SolveArgs {
+  FrontArgs f;
+  const int32_t* child_ptr;
+  const int32_t* child_list;
+  const int64_t* sn_vec_off;
+  const int32_t* panel_ptr;
+  const int32_t* panel_col;
+  double* tv;  // per-front accumulation vectors
+  double* tp;  // per-front permuted working vectors
+};
+template <typename T>
+void launch_fwd_level(int64_t nsn, const int32_t* level_sn, const SolveArgs& a, const T* front, const double* b,
+                      hipStream_t s);
+template <typename T>
+void launch_bwd_level(int64_t nsn, const int32_t* level_sn, const SolveArgs& a, const T* front, double* x,
+                      hipStream_t s);
+
+// ---------------------------------------------------------------- self test
+// C(16x16) = A(16x4) B(4x16) on one MFMA; out holds D row-major (double or float)
+void launch_mfma_probe(int prec, const double* a, const double* b, double* out, hipStream_t s);
+
+}  // namespace sgn

@@ -1,0 +1,115 @@
+// Host-side symbolic analysis of the SGN saddle-point system and of the
+// Kx system used by the Newton equilibrium solve.  Plain C++17, no HIP: it
+// runs once per mesh (the sparsity pattern is fixed) and produces the tables
+// the device kernels consume.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sgn {
+
+constexpr int kPanel = 64;        // panel width of the blocked front factorisation
+constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
+constexpr int kTile = 64;         // update tile edge
+
+enum SystemKind { SYS_SGN = 0, SYS_KX = 1 };
+
+struct Mesh {
+  int dim = 0, n_nodes = 0, n_elems = 0;
+  std::vector<double> rest;       // [n_nodes*dim]
+  std::vector<int32_t> elems;     // [n_elems*(dim+1)]
+  std::vector<int32_t> grid;      // [n_nodes*dim]
+  std::vector<uint8_t> fixed;     // [n_nodes]
+  std::vector<double> fext;       // [n_nodes*dim]
+  int param_kind = 0;
+  // derived
+  std::vector<int32_t> fdof;      // node -> first free DOF (-1 fixed)
+  int64_t n_x = 0, n_p = 0;
+};
+
+// One launch of the blocked front factorisation: all fronts of one tree level
+// that have a panel with index `panel`.
+struct PanelStep {
+  int64_t task_begin, task_end;    // range in the panel task table
+  int64_t upd_begin, upd_end;      // range in the update task table (inner, k = one panel)
+  int64_t outer_begin, outer_end;  // range in the update task table (outer, k = block)
+  int64_t upd_tiles, outer_tiles;  // tiles of each update launch
+  int64_t trsm_rows;               // max rows below the panel over the step's tasks
+};
+
+struct LevelPlan {
+  int64_t sn_begin, sn_end;            // range in level_sn (supernodes of this level)
+  int max_children;                    // extend-add rounds
+  std::vector<int64_t> ea_begin, ea_end, ea_work;  // per round: range in ea task table, total entries
+  std::vector<PanelStep> steps;
+  int64_t max_m = 0;
+};
+
+struct System {
+  int kind = SYS_SGN;
+  int64_t N = 0;
+  std::vector<int32_t> perm, iperm;      // perm[new] = old
+  std::vector<int64_t> rowptr;           // lower CSR, new numbering
+  std::vector<int32_t> colind;
+  std::vector<int32_t> slot_row;         // row of every lower CSR entry
+  std::vector<int32_t> etree;
+  // full (both triangles) CSR for the symmetric SpMV: column and lower slot
+  std::vector<int64_t> frowptr;
+  std::vector<int32_t> fcol, fslot;
+  // pivot groups (BK pivoting is restricted to a group), new numbering
+  std::vector<int32_t> var_group_end;    // per var: end (exclusive) of its group
+  // supernodes (contiguous pivot ranges)
+  int nsn = 0;
+  std::vector<int32_t> sn_begin;         // [nsn+1]
+  std::vector<int64_t> sn_rows_ptr;      // [nsn+1]
+  std::vector<int32_t> sn_rows;          // struct rows, ascending
+  std::vector<int32_t> sn_parent, sn_level;
+  std::vector<int32_t> sn_m;
+  std::vector<int64_t> sn_front_off;     // element offset of the m x m column-major front
+  std::vector<int64_t> sn_vec_off;       // element offset of the length-m solve vector
+  std::vector<int64_t> relmap_off;       // [nsn+1] into relmap
+  std::vector<int32_t> relmap;           // struct row r of child -> index in parent front
+  std::vector<int32_t> child_ptr, child_list;
+  std::vector<int32_t> var_sn;           // supernode of each var
+  std::vector<int64_t> csr_front_pos;    // per lower CSR entry: element offset in its front
+  int64_t front_total = 0, vec_total = 0;
+  // panels: per supernode a list of local column starts (last = s)
+  std::vector<int32_t> panel_ptr;        // [nsn+1]
+  std::vector<int32_t> panel_col;        // local starts, with a terminating s per sn
+  // schedule
+  int nlevels = 0;
+  std::vector<int32_t> level_sn;         // supernodes grouped by level
+  std::vector<LevelPlan> levels;
+  // task tables (flattened int64 quintuples, see kernels)
+  std::vector<int64_t> panel_tasks;      // (sn, c0, c1) per task: 3 entries
+  std::vector<int64_t> upd_tasks;        // (sn, k0, k1, cb, ce, tile_prefix): 6 entries
+  std::vector<int64_t> ea_tasks;         // (child, parent, work_prefix): 3 entries
+  // element -> lower CSR slot contributions and their inverse (gather) map
+  int elem_stride = 0;                   // values per element in the element buffer
+  std::vector<int64_t> slot_ptr;         // [nnz+1]
+  std::vector<int32_t> slot_src;         // element-buffer index e*stride + k
+  std::vector<int32_t> diag_kind;        // per var (new): 0 none, 1 target x, 2 param, 3 x, 4 lambda
+  // vector gather of the residual c (KX only): per x dof, element-buffer sources
+  std::vector<int64_t> vec_ptr;
+  std::vector<int32_t> vec_src;
+  double flops = 0;                      // dense front work of one factorisation
+  int64_t factor_entries = 0;            // sum m*s
+  int max_front = 0;
+};
+
+struct Analysis {
+  Mesh mesh;
+  std::vector<int64_t> node_order;  // free nodes in ND order
+  System sgn, kx;
+  // element buffer layout
+  int nd = 0;              // dofs per element (d+1)*d
+  int off_hess = 0, off_grad = 0, off_kp = 0, off_energy = 0, stride = 0;
+};
+
+// Runs the whole host analysis.  Returns an empty string on success, else an
+// error message.
+std::string analyse(Analysis& A);
+
+}  // namespace sgn

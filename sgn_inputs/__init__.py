@@ -98,6 +98,16 @@ class Problem:
         m[fn] = np.arange(fn.size, dtype=np.int64) * self.dim
         return m
 
+    def node_grid(self) -> np.ndarray:
+        """[n_nodes, dim] integer grid coordinates of every node (axis 0 fastest in the node id)."""
+        ids = np.arange(self.n_nodes)
+        if self.dim == 2:
+            n = self.grid[0]
+            return np.stack([ids % n, ids // n], axis=1).astype(np.int32)
+        nx, ny, _ = self.grid
+        Nx, Ny = nx + 1, ny + 1
+        return np.stack([ids % Nx, (ids // Nx) % Ny, ids // (Nx * Ny)], axis=1).astype(np.int32)
+
     def x_rest(self) -> np.ndarray:
         """Free-DOF vector of the rest positions (the natural initial guess)."""
         return self.rest_pos[self.free_nodes].reshape(-1).astype(np.float64).copy()

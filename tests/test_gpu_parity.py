@@ -1,0 +1,152 @@
+"""GPU parity of libsgn against the FP64 oracle (runs through the C ABI on an MI355X).
+
+Inputs are the seeded problems of ``sgn_inputs`` with targets and ell set up
+by the oracle; every expected value comes from ``oracle/``.
+"""
+import numpy as np
+import pytest
+
+import sgn_inputs as si
+from oracle import dense as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2107_03285_amd import sgn  # noqa: E402
+
+
+def _cuda(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+_PROBS = {}
+
+
+def _problem(name):
+    if name not in _PROBS:
+        mk = {
+            "tiny": si.config_tiny,
+            "grid21": si.config_2d,
+            "cant4x2x2": lambda: si.problem_3d(4, 2, 2, 0.25, seed=1),
+            "cant8x3x3": lambda: si.problem_3d(8, 3, 3, 1 / 3, seed=2),
+            "rest3x2x2": lambda: si.problem_3d(3, 2, 2, 1 / 3, seed=1, param_kind=si.P_REST_POS),
+        }[name]
+        prob = D.setup_targets(mk())
+        p = prob.p_init()
+        x, info = D.equilibrium(prob, p, rtol=1e-11)
+        assert info.converged
+        _PROBS[name] = (prob, p, x)
+    return _PROBS[name]
+
+
+def _ctx(prob, **opt):
+    o = sgn.default_options(**opt)
+    return sgn.Context(prob, o).allocate()
+
+
+def test_mfma_lane_layout():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((16, 4))
+    B = rng.standard_normal((4, 16))
+    out = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    for prec, tol in ((0, 1e-14), (1, 1e-5)):
+        sgn.selftest_mfma(prec, _cuda(A), _cuda(B), out)
+        assert np.allclose(_host(out), A @ B, rtol=tol, atol=tol)
+
+
+def _dense_lower_entries(prob, x, p, ctx, which=sgn.SGN_SYS_SGN):
+    perm, _, rp, ci = ctx.symbolic(which)
+    if which == sgn.SGN_SYS_SGN:
+        K = D.sgn_matrix_dense(prob, x, p)
+    else:
+        K = D.stiffness(prob, x, p).toarray()
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    return K[perm[rows], perm[ci]]
+
+
+@pytest.mark.parametrize("name", ["tiny", "grid21", "cant4x2x2", "rest3x2x2"])
+def test_assembly_matches_oracle_and_is_deterministic(name):
+    prob, p, x = _problem(name)
+    ctx = _ctx(prob)
+    xd, pd = _cuda(x), _cuda(p)
+    ctx.assemble(xd, pd)
+    v1 = ctx.values()
+    ref = _dense_lower_entries(prob, x, p, ctx)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(v1 - ref)) <= 1e-12 * scale
+    ctx.assemble(xd, pd)
+    v2 = ctx.values()
+    assert np.array_equal(v1.view(np.uint64), v2.view(np.uint64))
+
+
+@pytest.mark.parametrize("name", ["tiny", "grid21", "cant4x2x2", "rest3x2x2"])
+def test_equilibrium_matches_oracle(name):
+    prob, p, x_ref = _problem(name)
+    ctx = _ctx(prob, newton_rtol=1e-11)
+    xd = _cuda(prob.x_rest())
+    info = ctx.equilibrium(_cuda(p), xd)
+    assert info.converged
+    x = _host(xd)
+    u_ref = x_ref - prob.x_rest()
+    assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(u_ref)
+    assert np.linalg.norm(D.residual(prob, x, p)) <= 1e-11 * np.linalg.norm(D.fext_free(prob))
+    # the Kx values at the solution match the oracle stiffness
+    kv = ctx.values(sgn.SGN_SYS_KX)
+    ref = _dense_lower_entries(prob, x, p, ctx, sgn.SGN_SYS_KX)
+    assert np.max(np.abs(kv - ref)) <= 1e-12 * np.abs(ref).max()
+
+
+def _blocks(prob, z):
+    nx, npar = prob.n_x, prob.n_p
+    return z[:nx], z[nx:nx + npar], z[nx + npar:]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision", [sgn.SGN_FP64, sgn.SGN_FP32_IR])
+@pytest.mark.parametrize("name", ["tiny", "grid21", "cant4x2x2", "cant8x3x3", "rest3x2x2"])
+def test_step_matches_dense_gauss_newton(name, precision):
+    prob, p, x = _problem(name)
+    ctx = _ctx(prob, precision=precision, newton_rtol=1e-11)
+    xd, pd = _cuda(x), _cuda(p)
+    ctx.equilibrium(pd, xd)
+    N = 2 * prob.n_x + prob.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(prob.n_p, dtype=torch.float64, device="cuda")
+    ctx.assemble(xd, pd, rhs, grad)
+    fi = ctx.factor()
+    if precision == sgn.SGN_FP64:  # the FP32 factor may misjudge near-zero pivots; refinement repairs them
+        assert (fi.n_pos, fi.n_neg, fi.n_zero) == (prob.n_x + prob.n_p, prob.n_x, 0)
+    sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+    si_ = ctx.solve(rhs, sol)
+    assert si_.rel_res <= 1e-10
+    xg = _host(xd)
+    st = D.dense_gn_step(prob, xg, p)
+    dx, dp, dl = _blocks(prob, _host(sol))
+    tol = 1e-9 if precision == sgn.SGN_FP64 else 1e-8
+    assert _rel(_host(grad), st.grad) <= 1e-10
+    assert _rel(dp, st.dp) <= tol
+    assert _rel(dx, st.dx) <= tol
+    assert _rel(dl, st.dlam) <= tol
+
+
+def test_kkt_rhs_gives_same_step():
+    prob, p, x = _problem("grid21")
+    ctx = _ctx(prob, rhs_kind=sgn.SGN_RHS_KKT)
+    xd, pd = _cuda(x), _cuda(p)
+    N = 2 * prob.n_x + prob.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.assemble(xd, pd, rhs)
+    ctx.factor()
+    sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.solve(rhs, sol)
+    st = D.dense_gn_step(prob, x, p)
+    dx, dp, dl = _blocks(prob, _host(sol))
+    assert _rel(dp, st.dp) <= 1e-9
+    assert _rel(dl - st.lam_adj, st.dlam) <= 1e-8

@@ -26,6 +26,11 @@ def c2d():
     return D.setup_targets(si.config_2d())
 
 
+@pytest.fixture(scope="module")
+def rest():
+    return D.setup_targets(si.problem_3d(3, 2, 2, 1 / 3, seed=1, param_kind=si.P_REST_POS))
+
+
 def _tiny3d(param_kind=si.P_LOGE, seed=3):
     return si.problem_3d(4, 2, 2, 0.25, seed=seed, param_kind=param_kind)
 
@@ -114,7 +119,7 @@ def test_adjoint_gradient_matches_central_differences(mk):
         assert abs(fd - g @ v) <= 1e-6 * max(abs(g @ v), 1e-3 * np.linalg.norm(g))
 
 
-@pytest.mark.parametrize("fixture", ["tiny", "c2d"])
+@pytest.mark.parametrize("fixture", ["tiny", "c2d", "rest"])
 def test_theorem1_sparse_system_reproduces_dense_gn_step(fixture, request):
     prob = request.getfixturevalue(fixture)
     p = prob.p_init()
@@ -141,7 +146,7 @@ def test_kkt_right_hand_side_shifts_multiplier_by_adjoint(tiny):
     assert np.linalg.norm(z[nx + npar:] - st.dlam - st.lam_adj) <= 1e-9 * np.linalg.norm(st.lam_adj)
 
 
-@pytest.mark.parametrize("fixture", ["tiny", "c2d"])
+@pytest.mark.parametrize("fixture", ["tiny", "c2d", "rest"])
 def test_kkt_inertia(fixture, request):
     prob = request.getfixturevalue(fixture)
     p = prob.p_init()
