@@ -107,6 +107,7 @@ typedef struct {
   double solve_rtol;            /* equilibrated residual |S(b - K z)|_2 / |S b|_2 */
   double eps_x, eps_lambda;     /* optional diagonal stabilisation (Sec. 5), default 0 */
   int max_newton, max_ir, max_minres, max_halvings;
+  int profile;                  /* 1: time every trailing-update launch with HIP events */
 } sgn_options;
 
 typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;
@@ -130,6 +131,18 @@ typedef struct {
   double ms_rhs, ms_assemble, ms_factor, ms_solve, ms_linesearch;
   sgn_solve_info solve;
 } sgn_step_info;
+
+/* Stage measurements of the last calls (HIP events on the context's stream). */
+typedef struct {
+  double assemble_ms;           /* element kernel + gathers of the last sgn_assemble */
+  double assemble_bytes;        /* algorithmic bytes: x, p, mesh in; K_SGN values out */
+  double factor_ms;             /* last sgn_factor: scaling, front assembly, factorisation */
+  double factor_flops;          /* dense front flops, sum s^3/3 + s^2 u + s u^2 */
+  double update_ms;             /* sum of MFMA trailing-update launch durations (profile = 1) */
+  double update_flops;          /* algorithmic flops of those launches, 2 k per updated entry */
+  int64_t update_launches;
+  double solve_ms;              /* last sgn_solve including refinement */
+} sgn_stats;
 
 /* Validate the problem, copy it, run the host symbolic analysis of both the
  * saddle-point system and the Kx system (nested-dissection order, permuted
@@ -176,6 +189,8 @@ sgn_status sgn_get_symbolic(sgn_ctx ctx, int which, int32_t* h_perm, int32_t* h_
                             int64_t* h_rowptr, int32_t* h_colind);
 /* Read back the assembled lower CSR values (host [nnz], new numbering). */
 sgn_status sgn_get_values(sgn_ctx ctx, int which, double* h_vals);
+/* Copy the stage measurements of the last calls into *out. */
+sgn_status sgn_get_stats(sgn_ctx ctx, sgn_stats* out);
 /* Self test of the matrix-core lane layout the factorisation kernels rely on:
  * d_out (16x16, row-major) = A (16x4, row-major d_a) * B (4x16, row-major d_b)
  * computed by one 16x16x4 MFMA in FP64 (prec 0) or FP32 (prec 1).  Device

@@ -193,7 +193,7 @@ def _spd_factor(K: np.ndarray):
                 raise
 
 
-def equilibrium(prob: Problem, p: np.ndarray, x0: np.ndarray = None, rtol: float = 1e-11,
+def equilibrium(prob: Problem, p: np.ndarray, x0: np.ndarray = None, rtol: float = 1e-10,
                 max_iter: int = 50, max_halvings: int = 40, dense_limit: int = 30000,
                 atol: float = 0.0):
     """Forward Newton solve of c(x, p) = 0 with monotone backtracking on Pi (Sec. 5).
@@ -201,16 +201,20 @@ def equilibrium(prob: Problem, p: np.ndarray, x0: np.ndarray = None, rtol: float
     Step acceptance: no inverted element and
     Pi(x + a dx) <= Pi(x) + 1e-4 a c^T dx + 1e-12 (sum_e |E_e| + |f^T x|), the
     last term absorbing rounding in Pi near convergence.  Stops at
-    |c|_2 <= rtol |f_ext|_2 + atol.
+    |c|_2 <= rtol |f_ext|_2 + atol, or when the residual has stalled at its
+    rounding floor: below 1e-7 |f_ext|_2 and no longer halving per step.
     """
     x = prob.x_rest() if x0 is None else x0.copy()
     fn = np.linalg.norm(fext_free(prob))
     alphas = []
     shifts = 0
+    prev = np.inf
     for it in range(max_iter + 1):
         c = residual(prob, x, p)
         rn = np.linalg.norm(c)
-        if rn <= rtol * fn + atol:
+        stalled = it > 0 and rn <= 1e-7 * fn and rn > 0.5 * prev
+        prev = rn
+        if rn <= rtol * fn + atol or stalled:
             return x, EqInfo(it, rn, True, shifts, alphas)
         if it == max_iter:
             break
@@ -354,7 +358,7 @@ def reduced_objective(prob: Problem, p: np.ndarray, x0: np.ndarray) -> float:
     return objective(prob, x, p)
 
 
-def setup_targets(prob: Problem, rtol: float = 1e-11) -> Problem:
+def setup_targets(prob: Problem, rtol: float = 1e-10) -> Problem:
     """Fill target values and the frozen length scale ell (problem set-up, not the method).
 
     ell = max |x(p0) - X| over free DOFs.  2D: targets are x(p*) on the target

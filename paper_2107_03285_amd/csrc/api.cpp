@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -88,6 +89,11 @@ struct Layout {
   }
 };
 
+bool verbose() {
+  static const bool v = std::getenv("SGN_VERBOSE") != nullptr;
+  return v;
+}
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -135,6 +141,15 @@ struct sgn_ctx_s {
   unsigned long long* d_ull = nullptr;
   bool kx_valid = false;
   bool sgn_assembled = false;
+  size_t ws_need = 0;  // workspace bytes, fixed at create (layout() with a null base resets pointers)
+  sgn_stats stats{};
+  std::vector<hipEvent_t> ev_pool;  // per-launch timing events (profile = 1)
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  ~sgn_ctx_s() {
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+    if (ev_a) hipEventDestroy(ev_a);
+    if (ev_b) hipEventDestroy(ev_b);
+  }
 };
 
 namespace {
@@ -162,6 +177,22 @@ sgn_status fail(sgn_ctx c, sgn_status s, const std::string& msg) {
 template <typename T>
 size_t bytes_of(const std::vector<T>& v) {
   return v.size() * sizeof(T);
+}
+
+hipError_t ensure_events(sgn_ctx c, size_t n) {
+  if (!c->ev_a) {
+    hipError_t e = hipEventCreate(&c->ev_a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&c->ev_b);
+    if (e != hipSuccess) return e;
+  }
+  while (c->ev_pool.size() < n) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    c->ev_pool.push_back(ev);
+  }
+  return hipSuccess;
 }
 
 size_t layout(sgn_ctx c, char* base) {
@@ -356,6 +387,30 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   f.lperm = D.lperm;
   f.counters = c->d_cnt;
   f.piv_tol = piv_tol;
+  const bool prof = c->opt.profile != 0 && si == 0;
+  size_t nev = 0;
+  double upd_flops = 0.0;
+  if (prof) {
+    size_t need = 0;
+    for (const LevelPlan& P : S.levels)
+      for (const PanelStep& ps : P.steps) need += 2 * ((ps.upd_tiles > 0) + (ps.outer_tiles > 0));
+    HIPCHK(ensure_events(c, need));
+  }
+  auto timed_update = [&](int64_t ntask, int64_t ntiles, const int64_t* tasks, double flops) -> hipError_t {
+    if (ntask <= 0 || ntiles <= 0) return hipSuccess;
+    if (prof) {
+      hipError_t e = hipEventRecord(c->ev_pool[nev], st);
+      if (e != hipSuccess) return e;
+    }
+    launch_update<T>(ntask, ntiles, tasks, f, front, st);
+    if (prof) {
+      hipError_t e = hipEventRecord(c->ev_pool[nev + 1], st);
+      if (e != hipSuccess) return e;
+      nev += 2;
+      upd_flops += flops;
+    }
+    return hipSuccess;
+  };
   for (int L = 0; L < S.nlevels; ++L) {
     const LevelPlan& P = S.levels[L];
     for (size_t r = 0; r < P.ea_begin.size(); ++r) {
@@ -366,12 +421,24 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
       const int64_t nt = ps.task_end - ps.task_begin;
       launch_panel_diag<T>(nt, D.panel_tasks + ps.task_begin * 3, f, front, st);
       launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
-      launch_update<T>(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, f, front, st);
-      launch_update<T>(ps.outer_end - ps.outer_begin, ps.outer_tiles, D.upd_tasks + ps.outer_begin * 6, f, front,
-                       st);
+      HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops));
+      HIPCHK(timed_update(ps.outer_end - ps.outer_begin, ps.outer_tiles, D.upd_tasks + ps.outer_begin * 6,
+                          ps.outer_flops));
     }
   }
   HIPCHK(hipGetLastError());
+  if (prof) {
+    HIPCHK(hipStreamSynchronize(st));
+    double ms = 0.0;
+    for (size_t k = 0; k < nev; k += 2) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, c->ev_pool[k], c->ev_pool[k + 1]));
+      ms += t;
+    }
+    c->stats.update_ms = ms;
+    c->stats.update_flops = upd_flops;
+    c->stats.update_launches = (int64_t)(nev / 2);
+  }
   HIPCHK(hipMemsetAsync(c->d_ull, 0, 4 * sizeof(unsigned long long), st));
   launch_inertia(S.N, D.dpiv, D.epiv, D.pivtype, c->d_ull, c->d_part, st);
   HIPCHK(hipGetLastError());
@@ -382,8 +449,18 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
 sgn_status factor_dispatch(sgn_ctx c, int si, double piv_tol, sgn_factor_info* info) {
   const double t0 = now_ms();
   DevSys& D = c->sys[si];
+  HIPCHK(ensure_events(c, 0));
+  if (si == 0) HIPCHK(hipEventRecord(c->ev_a, c->stream));
   if (D.prec) TRY(factor_system<float>(c, si, piv_tol));
   else TRY(factor_system<double>(c, si, piv_tol));
+  if (si == 0) {
+    HIPCHK(hipEventRecord(c->ev_b, c->stream));
+    HIPCHK(hipEventSynchronize(c->ev_b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+    c->stats.factor_ms = ms;
+    c->stats.factor_flops = c->A.sgn.flops;
+  }
   unsigned long long cnt[3] = {0, 0, 0};
   int pert = 0;
   std::vector<double> part(kRedBlocks);
@@ -541,6 +618,7 @@ sgn_status equilibrium_impl(sgn_ctx c, const double* p, double* x, sgn_eq_info* 
   const int64_t nx = A.mesh.n_x;
   const double tol = c->opt.newton_rtol * c->fext_norm + c->opt.newton_atol;
   int halvings = 0;
+  double prev_rn = INFINITY;
   c->kx_valid = false;
   for (int it = 0; it <= c->opt.max_newton; ++it) {
     int inv = 0;
@@ -554,6 +632,7 @@ sgn_status equilibrium_impl(sgn_ctx c, const double* p, double* x, sgn_eq_info* 
     double rn2;
     TRY(read_scalars(c, 3, 1, &rn2));
     const double rn = std::sqrt(rn2);
+    if (verbose()) fprintf(stderr, "[sgn] newton %d |c| = %.3e (rel %.3e)\n", it, rn, rn / c->fext_norm);
     // factorise Kx at this iterate (also needed at convergence for the adjoint)
     double tau = 0.0;
     double dmax = 0.0;
@@ -574,7 +653,11 @@ sgn_status equilibrium_impl(sgn_ctx c, const double* p, double* x, sgn_eq_info* 
         tau *= 10.0;
       }
     }
-    if (rn <= tol) {
+    // converged: below tolerance, or stalled at the rounding floor of the residual
+    // (|c| no longer halves once it is below 1e-7 |f_ext|)
+    const bool stalled = it > 0 && rn <= 1e-7 * c->fext_norm && rn > 0.5 * prev_rn;
+    prev_rn = rn;
+    if (rn <= tol || stalled) {
       c->kx_valid = (tau == 0.0);
       if (info) {
         info->iters = it;
@@ -596,6 +679,10 @@ sgn_status equilibrium_impl(sgn_ctx c, const double* p, double* x, sgn_eq_info* 
     sgn_status s = refined_solve(c, 1, D.b, D.z, &si);
     c->opt.solve_rtol = keep;
     if (s != SGN_OK && s != SGN_E_REFINE) return s;
+    if (verbose())
+      fprintf(stderr, "[sgn]   Kx inertia (%lld, %lld, %lld) tau %.2e, solve res %.2e after %d sweeps\n",
+              (long long)c->sys[1].inertia[0], (long long)c->sys[1].inertia[1], (long long)c->sys[1].inertia[2],
+              tau, si.rel_res, si.sweeps);
     launch_scatter_perm(nx, D.perm, nullptr, D.z, c->d_dx, c->stream);
     // backtracking on Pi
     double pi0, sc0;
@@ -618,6 +705,7 @@ sgn_status equilibrium_impl(sgn_ctx c, const double* p, double* x, sgn_eq_info* 
       alpha *= 0.5;
       ++halvings;
     }
+    if (verbose()) fprintf(stderr, "[sgn]   alpha %.3e (Pi0 %.6e, slope %.3e)\n", alpha, pi0, slope);
     if (!ok) {
       c->err = "Newton line search failed";
       return SGN_E_NEWTON;
@@ -655,12 +743,23 @@ sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rh
   const Analysis& A = c->A;
   const int64_t nx = A.mesh.n_x, np = A.mesh.n_p, N = A.sgn.N;
   int inv = 0;
+  HIPCHK(ensure_events(c, 0));
+  HIPCHK(hipEventRecord(c->ev_a, c->stream));
   TRY(run_element(c, x, p, 2, &inv));
   if (inv) {
     c->err = "inverted element in the given state";
     return SGN_E_INVERTED;
   }
   assemble_sgn(c);
+  HIPCHK(hipEventRecord(c->ev_b, c->stream));
+  HIPCHK(hipEventSynchronize(c->ev_b));
+  {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+    c->stats.assemble_ms = ms;
+    c->stats.assemble_bytes = 8.0 * (double)(nx + np) + 4.0 * (double)A.mesh.n_elems * (A.mesh.dim + 1) +
+                              8.0 * (double)A.mesh.rest.size() + 8.0 * (double)A.sgn.colind.size();
+  }
   c->sgn_assembled = true;
   c->sys[0].factored = false;
   if (obj) TRY(objective_value(c, x, p, obj));
@@ -741,9 +840,11 @@ sgn_status sgn_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_i
   const int64_t N = c->A.sgn.N;
   launch_gather_perm(N, D.perm, nullptr, rhs, c->d_old2, c->stream);
   double* zn = c->d_old;  // new-order solution
+  const double t0 = now_ms();
   sgn_status s = refined_solve(c, 0, c->d_old2, zn, info);
   launch_scatter_perm(N, D.perm, nullptr, zn, sol, c->stream);
   HIPCHK(hipStreamSynchronize(c->stream));
+  c->stats.solve_ms = now_ms() - t0;
   if (s != SGN_OK) return fail(c, s, c->err);
   return SGN_OK;
 }
@@ -768,6 +869,7 @@ void sgn_default_options(sgn_options* o) {
   o->max_ir = 10;
   o->max_minres = 500;
   o->max_halvings = 30;
+  o->profile = 0;
 }
 
 sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* stream, sgn_ctx* out) {
@@ -831,13 +933,14 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
     System& S = c->A.sgn;
     for (int32_t t : c->target_dof) S.diag_kind[S.iperm[t]] = 1;
   }
+  c->ws_need = layout(c, nullptr);
   return SGN_OK;
 }
 
 sgn_status sgn_workspace_size(sgn_ctx c, size_t* bytes) {
   if (!c || !bytes) return SGN_E_ARG;
   if (c->sticky) return SGN_E_STATE;
-  *bytes = layout(c, nullptr);
+  *bytes = c->ws_need;
   return SGN_OK;
 }
 
@@ -845,7 +948,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
   if (!c || !d_ws) return SGN_E_ARG;
   if (c->sticky) return SGN_E_STATE;
   if (((uintptr_t)d_ws & 255) != 0) return fail(c, SGN_E_ARG, "workspace must be 256-byte aligned");
-  const size_t need = layout(c, nullptr);
+  const size_t need = c->ws_need;
   if (bytes < need) return fail(c, SGN_E_NOMEM, "workspace too small");
   layout(c, reinterpret_cast<char*>(d_ws));
   const Analysis& A = c->A;
@@ -1069,6 +1172,12 @@ sgn_status sgn_selftest_mfma(int prec, const double* d_a, const double* d_b, dou
   launch_mfma_probe(prec, d_a, d_b, d_out, (hipStream_t)stream);
   if (hipGetLastError() != hipSuccess) return SGN_E_HIP;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SGN_E_HIP;
+  return SGN_OK;
+}
+
+sgn_status sgn_get_stats(sgn_ctx c, sgn_stats* out) {
+  if (!c || !out) return SGN_E_ARG;
+  *out = c->stats;
   return SGN_OK;
 }
 

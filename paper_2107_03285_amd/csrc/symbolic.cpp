@@ -168,6 +168,13 @@ inline int64_t find_slot(const System& S, int64_t r, int64_t c) {
   return it - S.colind.begin();
 }
 
+// 2 k flops per updated lower-triangle entry: columns [cb, ce), rows [c, m)
+double update_flops(int64_t m, int64_t cb, int64_t ce, int64_t k) {
+  const double n = (double)(ce - cb);
+  const double entries = n * (double)m - (double)(cb + ce - 1) * n / 2.0;
+  return 2.0 * (double)k * entries;
+}
+
 int64_t update_tiles(int64_t m, int64_t cb, int64_t ce) {
   int64_t R = (m - cb + kTile - 1) / kTile;
   int64_t ct = (ce - cb + kTile - 1) / kTile;
@@ -407,6 +414,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         ps.trsm_rows = std::max<int64_t>(ps.trsm_rows, S.sn_m[S.panel_tasks[q * 3]] - S.panel_tasks[q * 3 + 2]);
       ps.upd_begin = (int64_t)S.upd_tasks.size() / 6;
       int64_t tiles = 0;
+      double fl = 0.0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
         int t = S.level_sn[q];
         int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
@@ -419,12 +427,15 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
           int64_t m = S.sn_m[t];
           S.upd_tasks.insert(S.upd_tasks.end(), {t, c0, c1, c1, oend, tiles});
           tiles += update_tiles(m, c1, oend);
+          fl += update_flops(m, c1, oend, c1 - c0);
         }
       }
       ps.upd_end = (int64_t)S.upd_tasks.size() / 6;
       ps.upd_tiles = tiles;
+      ps.upd_flops = fl;
       ps.outer_begin = ps.upd_end;
       tiles = 0;
+      fl = 0.0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
         int t = S.level_sn[q];
         int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
@@ -437,10 +448,12 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         if (c1 < m) {
           S.upd_tasks.insert(S.upd_tasks.end(), {t, kb, c1, c1, m, tiles});
           tiles += update_tiles(m, c1, m);
+          fl += update_flops(m, c1, m, c1 - kb);
         }
       }
       ps.outer_end = (int64_t)S.upd_tasks.size() / 6;
       ps.outer_tiles = tiles;
+      ps.outer_flops = fl;
       P.steps.push_back(ps);
     }
   }

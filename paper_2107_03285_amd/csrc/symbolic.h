@@ -37,6 +37,7 @@ struct PanelStep {
   int64_t outer_begin, outer_end;  // range in the update task table (outer, k = block)
   int64_t upd_tiles, outer_tiles;  // tiles of each update launch
   int64_t trsm_rows;               // max rows below the panel over the step's tasks
+  double upd_flops, outer_flops;   // algorithmic flops of the two update launches
 };
 
 struct LevelPlan {

@@ -28,7 +28,8 @@ SGN_SYS_SGN, SGN_SYS_KX = 0, 1
 
 EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_workspace", "sgn_set_targets",
            "sgn_equilibrium", "sgn_assemble", "sgn_factor", "sgn_solve", "sgn_step", "sgn_get_sizes",
-           "sgn_get_symbolic", "sgn_get_values", "sgn_selftest_mfma", "sgn_last_error", "sgn_destroy"]
+           "sgn_get_symbolic", "sgn_get_values", "sgn_get_stats", "sgn_selftest_mfma", "sgn_last_error",
+           "sgn_destroy"]
 
 
 class sgn_problem(C.Structure):
@@ -45,7 +46,14 @@ class sgn_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("solver", C.c_int), ("rhs_kind", C.c_int),
                 ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("solve_rtol", C.c_double),
                 ("eps_x", C.c_double), ("eps_lambda", C.c_double), ("max_newton", C.c_int),
-                ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int)]
+                ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int),
+                ("profile", C.c_int)]
+
+
+class sgn_stats(C.Structure):
+    _fields_ = [("assemble_ms", C.c_double), ("assemble_bytes", C.c_double), ("factor_ms", C.c_double),
+                ("factor_flops", C.c_double), ("update_ms", C.c_double), ("update_flops", C.c_double),
+                ("update_launches", C.c_int64), ("solve_ms", C.c_double)]
 
 
 class sgn_eq_info(C.Structure):
@@ -104,6 +112,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_get_symbolic": (C.c_int, [vp, C.c_int, i32p, i32p, i64p, i32p]),
         "sgn_get_values": (C.c_int, [vp, C.c_int, dp]),
         "sgn_selftest_mfma": (C.c_int, [C.c_int, vp, vp, vp, vp]),
+        "sgn_get_stats": (C.c_int, [vp, C.POINTER(sgn_stats)]),
         "sgn_last_error": (C.c_char_p, [vp]),
         "sgn_destroy": (None, [vp]),
     }
@@ -270,6 +279,11 @@ class Context:
     def values(self, which=SGN_SYS_SGN):
         out = np.empty(self.sizes(which)["nnz"], np.float64)
         self._check(self.lib.sgn_get_values(self.h, which, _ptr(out, C.c_double)))
+        return out
+
+    def stats(self) -> sgn_stats:
+        out = sgn_stats()
+        self._check(self.lib.sgn_get_stats(self.h, C.byref(out)))
         return out
 
     def last_error(self) -> str:
