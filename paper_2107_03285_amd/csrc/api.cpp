@@ -53,6 +53,13 @@ struct DevSys {
   int64_t* ea_tasks = nullptr;
   int64_t* vec_ptr = nullptr;
   int32_t* vec_src = nullptr;
+  int32_t* solve_fwd_tasks = nullptr;
+  int32_t* solve_bwd_tasks = nullptr;
+  int64_t* sn_part_off = nullptr;
+  double* part = nullptr;      // split-k partial sums of the forward solve
+  int* solve_ctr = nullptr;    // [2 * nlevels] ticket counters of the pipelined solve launches
+  int* solve_flags = nullptr;  // [n_panels] ready flags (epoch numbers)
+  int epoch = 0;
   int64_t* const_slots = nullptr;
   int64_t n_const = 0;
   double* vals = nullptr;
@@ -233,6 +240,12 @@ size_t layout(sgn_ctx c, char* base) {
     D.ea_tasks = L.take<int64_t>(S.ea_tasks.size());
     D.vec_ptr = L.take<int64_t>(S.vec_ptr.size());
     D.vec_src = L.take<int32_t>(S.vec_src.size());
+    D.solve_fwd_tasks = L.take<int32_t>(S.solve_fwd_tasks.size());
+    D.solve_bwd_tasks = L.take<int32_t>(S.solve_bwd_tasks.size());
+    D.solve_ctr = L.take<int>(2 * (size_t)S.nlevels);
+    D.sn_part_off = L.take<int64_t>(S.sn_part_off.size());
+    D.part = L.take<double>(S.part_total);
+    D.solve_flags = L.take<int>(S.n_panels);
     D.n_const = (si == 0 && A.mesh.param_kind == 2) ? nx : 0;
     D.const_slots = L.take<int64_t>(D.n_const);
     D.vals = L.take<double>(S.colind.size());
@@ -486,9 +499,9 @@ sgn_status factor_dispatch(sgn_ctx c, int si, double piv_tol, sgn_factor_info* i
   return SGN_OK;
 }
 
-// solve in the system's (new, scaled) space: x = K^-1 b with b, x in new order, unscaled
+// solve in the system's (new, scaled) space: x = Ks^-1 b with b, x in new order
 template <typename T>
-void solve_once_t(sgn_ctx c, int si, const double* b_new, double* x_new) {
+sgn_status solve_once_t(sgn_ctx c, int si, const double* b_new, double* x_new) {
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
   DevSys& D = c->sys[si];
   hipStream_t st = c->stream;
@@ -514,27 +527,38 @@ void solve_once_t(sgn_ctx c, int si, const double* b_new, double* x_new) {
   a.panel_col = D.panel_col;
   a.tv = D.tv;
   a.tp = D.tp;
+  a.sn_part_off = D.sn_part_off;
+  a.part = D.part;
   const T* front = reinterpret_cast<const T*>(D.front);
+  HIPCHK(hipMemsetAsync(D.solve_ctr, 0, 2 * (size_t)S.nlevels * sizeof(int), st));
+  int* err = c->d_cnt + 12;
+  const int e_fwd = ++D.epoch, e_bwd = ++D.epoch;
   for (int L = 0; L < S.nlevels; ++L) {
     const LevelPlan& P = S.levels[L];
-    launch_fwd_level<T>(P.sn_end - P.sn_begin, D.level_sn + P.sn_begin, a, front, b_new, st);
+    launch_fwd_level<T>(P.sn_end - P.sn_begin, P.max_u, P.max_s, D.level_sn + P.sn_begin, D.solve_fwd_tasks + 2 * P.fwd_begin,
+                        P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr + 2 * L, D.solve_flags, e_fwd, err, st);
   }
   for (int L = S.nlevels - 1; L >= 0; --L) {
     const LevelPlan& P = S.levels[L];
-    launch_bwd_level<T>(P.sn_end - P.sn_begin, D.level_sn + P.sn_begin, a, front, x_new, st);
+    launch_bwd_level<T>(P.sn_end - P.sn_begin, P.max_s, D.level_sn + P.sn_begin, D.solve_bwd_tasks + 2 * P.bwd_begin,
+                        P.bwd_end - P.bwd_begin, a, front, x_new, D.solve_ctr + 2 * L + 1, D.solve_flags, e_bwd, err,
+                        st);
   }
+  HIPCHK(hipGetLastError());
+  return SGN_OK;
 }
 
 void scale_vec(sgn_ctx c, int64_t n, const double* s, const double* in, double* out);
 
 // x_new = K^-1 b_new with the current factor (x_new may alias b_new; uses D.sv)
-void solve_once(sgn_ctx c, int si, const double* b_new, double* x_new) {
+sgn_status solve_once(sgn_ctx c, int si, const double* b_new, double* x_new) {
   DevSys& D = c->sys[si];
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
   scale_vec(c, S.N, D.scale, b_new, D.sv);
-  if (D.prec) solve_once_t<float>(c, si, D.sv, x_new);
-  else solve_once_t<double>(c, si, D.sv, x_new);
+  if (D.prec) TRY(solve_once_t<float>(c, si, D.sv, x_new));
+  else TRY(solve_once_t<double>(c, si, D.sv, x_new));
   scale_vec(c, S.N, D.scale, x_new, x_new);
+  return SGN_OK;
 }
 
 void scale_vec(sgn_ctx c, int64_t n, const double* s, const double* in, double* out) {
@@ -547,7 +571,8 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
   DevSys& D = c->sys[si];
   const double t0 = now_ms();
-  solve_once(c, si, b_new, z_new);
+  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+  TRY(solve_once(c, si, b_new, z_new));
   scale_vec(c, S.N, D.scale, b_new, D.ir_s);
   dev_dot(c, S.N, D.ir_s, D.ir_s, 1);
   dev_dot(c, S.N, b_new, b_new, 2);
@@ -568,9 +593,16 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
     raw = rb > 0 ? std::sqrt(rn[1]) / rb : 0.0;
     if (rel <= c->opt.solve_rtol || sweeps >= max_ir || !(rel < prev)) break;
     prev = rel;
-    solve_once(c, si, D.ir_r, D.ir_d);
+    TRY(solve_once(c, si, D.ir_r, D.ir_d));
     launch_axpby(S.N, 1.0, z_new, 1.0, D.ir_d, z_new, c->stream);
     ++sweeps;
+  }
+  int timeout = 0;
+  HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (timeout) {
+    c->err = "a pipelined triangular solve timed out waiting for a panel";
+    return SGN_E_HIP;
   }
   if (info) {
     info->sweeps = sweeps;
@@ -986,6 +1018,11 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.ea_tasks, S.ea_tasks, st));
     HIPCHK(up(D.vec_ptr, S.vec_ptr, st));
     HIPCHK(up(D.vec_src, S.vec_src, st));
+    HIPCHK(up(D.solve_fwd_tasks, S.solve_fwd_tasks, st));
+    HIPCHK(up(D.solve_bwd_tasks, S.solve_bwd_tasks, st));
+    HIPCHK(up(D.sn_part_off, S.sn_part_off, st));
+    HIPCHK(hipMemsetAsync(D.solve_flags, 0xff, std::max<int64_t>(1, S.n_panels) * sizeof(int), st));
+    D.epoch = 0;
     if (D.n_const) {
       std::vector<int64_t> cs(D.n_const);
       for (int64_t i = 0; i < D.n_const; ++i) {

@@ -71,53 +71,73 @@ __global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, const int64_
   for (int64_t r = c + threadIdx.x; r < uC; r += 256) dst[rel[r] + Cc * mP] += src[r];
 }
 
-// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64.
+// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, by one
+// wavefront: lane i owns row i of the (symmetric, fully stored) block.
+// Bunch-Kaufman 1x1/2x2 pivoting is restricted to the rows of one node group.
+// Besides L11 and D it forms X = L11^-1 (unit lower) and stores it transposed
+// in the block's unused upper triangle, so the rows below the panel are solved
+// by independent dot products instead of a sequential substitution.
+// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, 256 threads.
+// Bunch-Kaufman 1x1/2x2 pivoting restricted to the rows of one node group.  The
+// pivot search is one LDS atomic max per candidate set (|a| bits with the row
+// index in the low bits, so ties go to the lower row), taken by wavefront 0;
+// the symmetric updates use lane = row, wavefront = every fourth column.
+// Alongside L11 the block accumulates X = L11^-1 (unit lower) from the
+// elementary column inverses, X <- L_k^-1 X, stored transposed in the upper
+// part of the finished rows (X[i][j] at A[j][i]); symmetric interchanges swap
+// those entries exactly as X's rows must be swapped.  The rows below the panel
+// are then solved by a matrix-core product against X.
 template <typename T>
 __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
                                                     T* __restrict__ front) {
   __shared__ double A[64][65];
-  __shared__ int pos[64];
-  __shared__ int s_kind, s_p, s_q, s_perm;
-  const int tid = threadIdx.x;
+  __shared__ int s_kind, s_p, s_q, s_pert;
+  __shared__ unsigned long long s_key, s_key2;
+  __shared__ int pos[64], ptype[64], gend_l[64];
+  __shared__ double dval[64], eval[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sn = (int)tasks[blockIdx.x * 3];
   const int c0 = (int)tasks[blockIdx.x * 3 + 1], c1 = (int)tasks[blockIdx.x * 3 + 2];
   const int w = c1 - c0;
   const int64_t m = f.sn_m[sn];
-  const int64_t gbase = f.sn_begin[sn] + c0;  // global var index of panel column 0
+  const int64_t gbase = f.sn_begin[sn] + c0;
   T* F = front + f.sn_front_off[sn];
-  for (int idx = tid; idx < w * w; idx += 256) {
-    const int i = idx % w, j = idx / w;
-    if (i >= j) {
-      const double v = (double)F[(c0 + i) + (int64_t)(c0 + j) * m];
-      A[i][j] = v;
-      A[j][i] = v;
+  for (int j = wave; j < w; j += 4)
+    if (lane >= j && lane < w) {
+      const double v = (double)F[(c0 + lane) + (int64_t)(c0 + j) * m];
+      A[lane][j] = v;
+      A[j][lane] = v;
     }
+  if (tid < 64) {
+    pos[tid] = tid;
+    gend_l[tid] = tid < w ? (int)(f.var_group_end[gbase + tid] - gbase) : w;
   }
-  if (tid < 64) pos[tid] = tid;
-  if (tid == 0) s_perm = 0;
   __syncthreads();
+  int npert = 0;
   int k = 0;
   while (k < w) {
-    if (tid == 0) {
-      const int gend = (int)(f.var_group_end[gbase + k] - gbase);
+    if (wave == 0) {
+      const int gend = gend_l[k];
+      if (lane == 0) {
+        s_key = 0ull;
+        s_key2 = 0ull;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const double v = (lane > k && lane < gend) ? fabs(A[lane][k]) : 0.0;
+      if (v > 0.0) atomicMax(&s_key, (__double_as_longlong(v) & ~63ull) | (unsigned long long)(63 - lane));
+      __builtin_amdgcn_wave_barrier();
+      const unsigned long long key = s_key;
+      const int imax = key ? 63 - (int)(key & 63ull) : k;
+      const double colmax = key ? fabs(A[imax][k]) : 0.0;
       const double absakk = fabs(A[k][k]);
-      double colmax = 0.0;
-      int imax = k;
-      for (int i = k + 1; i < gend; ++i)
-        if (fabs(A[i][k]) > colmax) {
-          colmax = fabs(A[i][k]);
-          imax = i;
-        }
-      int kind = 1, p = -1, q = -1;
+      int kind = 1, p = -1, q = -1, pert = 0;
       if (fmax(absakk, colmax) <= f.piv_tol) {
-        A[k][k] = A[k][k] >= 0.0 ? f.piv_tol : -f.piv_tol;
-        atomicAdd(&f.counters[0], 1);
-      } else if (absakk >= kAlphaBK * colmax) {
-        kind = 1;
-      } else {
-        double rowmax = 0.0;
-        for (int j = k; j < gend; ++j)
-          if (j != imax) rowmax = fmax(rowmax, fabs(A[imax][j]));
+        pert = 1;
+      } else if (absakk < kAlphaBK * colmax) {
+        const double v2 = (lane >= k && lane < gend && lane != imax) ? fabs(A[imax][lane]) : 0.0;
+        if (v2 > 0.0) atomicMax(&s_key2, (unsigned long long)__double_as_longlong(v2));
+        __builtin_amdgcn_wave_barrier();
+        const double rowmax = __longlong_as_double((long long)s_key2);
         if (absakk * rowmax >= kAlphaBK * colmax * colmax) {
           kind = 1;
         } else if (fabs(A[imax][imax]) >= kAlphaBK * rowmax) {
@@ -130,15 +150,18 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
           q = imax;
         }
       }
-      s_kind = kind;
-      s_p = p;
-      s_q = q;
-      if (p >= 0 && p != q) s_perm = 1;
+      if (lane == 0) {
+        s_kind = kind;
+        s_p = p;
+        s_q = q;
+        s_pert = pert;
+        if (pert) A[k][k] = A[k][k] >= 0.0 ? f.piv_tol : -f.piv_tol;
+      }
     }
     __syncthreads();
     const int kind = s_kind, p = s_p, q = s_q;
+    if (s_pert) ++npert;
     if (p >= 0 && p != q) {
-      // symmetric swap of indices p and q in the full square block
       for (int j = tid; j < w; j += 256) {
         const double t = A[p][j];
         A[p][j] = A[q][j];
@@ -160,26 +183,25 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
     if (kind == 1) {
       double d = A[k][k];
       if (fabs(d) < f.piv_tol) {
-        __syncthreads();
-        if (tid == 0) {
-          A[k][k] = d >= 0.0 ? f.piv_tol : -f.piv_tol;
-          atomicAdd(&f.counters[0], 1);
-        }
-        __syncthreads();
-        d = A[k][k];
+        d = d >= 0.0 ? f.piv_tol : -f.piv_tol;
+        ++npert;
       }
       const double id = 1.0 / d;
-      const int n = w - k - 1;
-      for (int idx = tid; idx < n * n; idx += 256) {
-        const int i = k + 1 + idx % n, j = k + 1 + idx / n;
-        A[i][j] -= A[i][k] * A[j][k] * id;
+      if (lane > k && lane < w) {
+        const double li = A[lane][k] * id;
+        for (int j = k + 1 + wave; j < w; j += 4) A[lane][j] -= li * A[j][k];  // Schur complement
+        for (int j = wave; j < k; j += 4) A[j][lane] -= li * A[j][k];        // X <- L_k^-1 X
       }
       __syncthreads();
-      for (int i = k + 1 + tid; i < w; i += 256) A[i][k] *= id;
+      if (tid > k && tid < w) {
+        const double li = A[tid][k] * id;
+        A[tid][k] = li;
+        A[k][tid] = -li;
+      }
       if (tid == 0) {
-        f.dpiv[gbase + k] = d;
-        f.epiv[gbase + k] = 0.0;
-        f.pivtype[gbase + k] = 0;
+        ptype[k] = 0;
+        dval[k] = d;
+        eval[k] = 0.0;
       }
       __syncthreads();
       k += 1;
@@ -187,123 +209,157 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
       const double a = A[k][k], b = A[k + 1][k], c = A[k + 1][k + 1];
       const double det = a * c - b * b;
       const double i00 = c / det, i01 = -b / det, i11 = a / det;
-      const int n = w - k - 2;
-      for (int idx = tid; idx < n * n; idx += 256) {
-        const int i = k + 2 + idx % n, j = k + 2 + idx / n;
-        const double ui0 = A[i][k], ui1 = A[i][k + 1], uj0 = A[j][k], uj1 = A[j][k + 1];
-        A[i][j] -= ui0 * (i00 * uj0 + i01 * uj1) + ui1 * (i01 * uj0 + i11 * uj1);
+      if (lane > k + 1 && lane < w) {
+        const double ui0 = A[lane][k], ui1 = A[lane][k + 1];
+        const double l0 = ui0 * i00 + ui1 * i01, l1 = ui0 * i01 + ui1 * i11;
+        for (int j = k + 2 + wave; j < w; j += 4) A[lane][j] -= l0 * A[j][k] + l1 * A[j][k + 1];
+        for (int j = wave; j < k; j += 4) A[j][lane] -= l0 * A[j][k] + l1 * A[j][k + 1];
       }
       __syncthreads();
-      for (int i = k + 2 + tid; i < w; i += 256) {
-        const double u0 = A[i][k], u1 = A[i][k + 1];
-        A[i][k] = u0 * i00 + u1 * i01;
-        A[i][k + 1] = u0 * i01 + u1 * i11;
+      if (tid > k + 1 && tid < w) {
+        const double u0 = A[tid][k], u1 = A[tid][k + 1];
+        const double l0 = u0 * i00 + u1 * i01, l1 = u0 * i01 + u1 * i11;
+        A[tid][k] = l0;
+        A[tid][k + 1] = l1;
+        A[k][tid] = -l0;
+        A[k + 1][tid] = -l1;
       }
       if (tid == 0) {
-        f.dpiv[gbase + k] = a;
-        f.dpiv[gbase + k + 1] = c;
-        f.epiv[gbase + k] = b;
-        f.epiv[gbase + k + 1] = 0.0;
-        f.pivtype[gbase + k] = 1;
-        f.pivtype[gbase + k + 1] = 2;
+        ptype[k] = 1;
+        ptype[k + 1] = 2;
+        dval[k] = a;
+        dval[k + 1] = c;
+        eval[k] = b;
+        eval[k + 1] = 0.0;
+        A[k + 1][k] = 0.0;  // L and X are the identity inside a 2x2 block
+        A[k][k + 1] = 0.0;
       }
       __syncthreads();
       k += 2;
     }
   }
-  // write back L11 (unit lower; zero inside 2x2 blocks) and the pivot order
-  for (int idx = tid; idx < w * w; idx += 256) {
-    const int i = idx % w, j = idx / w;
-    if (i < j) continue;
-    double v;
-    if (i == j) v = 1.0;
-    else if (i == j + 1 && f.pivtype[gbase + j] == 1) v = 0.0;
-    else v = A[i][j];
-    F[(c0 + i) + (int64_t)(c0 + j) * m] = (T)v;
+  // A holds L below the diagonal and X[j][i] at (i, j) above it: the transposed
+  // placement the rows-below solve reads
+  for (int j = wave; j < w; j += 4)
+    if (lane < w) F[(c0 + lane) + (int64_t)(c0 + j) * m] = (T)(lane == j ? 1.0 : A[lane][j]);
+  if (tid < w) {
+    f.dpiv[gbase + tid] = dval[tid];
+    f.epiv[gbase + tid] = eval[tid];
+    f.pivtype[gbase + tid] = ptype[tid];
+    f.lperm[gbase + tid] = c0 + pos[tid];
   }
-  if (tid < w) f.lperm[gbase + tid] = c0 + pos[tid];
-  if (s_perm && c0 > 0) {
-    // apply the row interchanges to the already factorised columns [0, c0)
-    const int kk = tid & 63, jj = tid >> 6;
-    for (int j0 = 0; j0 < c0; j0 += 4) {
-      const int j = j0 + jj;
-      T v = (T)0;
-      if (kk < w && j < c0) v = F[(c0 + pos[kk]) + (int64_t)j * m];
-      __syncthreads();
-      if (kk < w && j < c0) F[(c0 + kk) + (int64_t)j * m] = v;
-      __syncthreads();
-    }
-  }
+  if (tid == 0 && npert) atomicAdd(&f.counters[0], npert);
 }
 
-// Rows [c1, m) of a panel: L21 = F21 P^T L11^-T D^-1, one thread per row, FP64 arithmetic.
+// Rows [c1, m) of a panel, 64 per block: X = V X11^T on the matrix cores with
+// V = F21 P^T (panel columns in pivot order) and X11 = L11^-1 from the diagonal
+// block's upper triangle; then W = X goes transposed to the upper triangle and
+// L21 = X D^-1 to the lower part.  Precision T throughout (FP32 on the FP32 path).
 template <typename T>
 __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ tasks, FrontArgs f,
                                                     T* __restrict__ front) {
-  __shared__ double L[64][65];
+  __shared__ T sV[16][68];
+  __shared__ T sX[16][68];
+  __shared__ T sC[64][65];
   __shared__ double dd[64], ee[64];
   __shared__ int ty[64], ps[64];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t task = blockIdx.x;
   const int sn = (int)tasks[task * 3];
   const int c0 = (int)tasks[task * 3 + 1], c1 = (int)tasks[task * 3 + 2];
   const int w = c1 - c0;
   const int64_t m = f.sn_m[sn];
-  const int64_t r = c1 + (int64_t)blockIdx.y * 256 + tid;
-  if (c1 + (int64_t)blockIdx.y * 256 >= m) return;
+  const int64_t r0 = c1 + (int64_t)blockIdx.y * 64;
+  if (r0 >= m) return;
   const int64_t gbase = f.sn_begin[sn] + c0;
   T* F = front + f.sn_front_off[sn];
-  for (int idx = tid; idx < w * w; idx += 256) {
-    const int i = idx % w, j = idx / w;
-    L[i][j] = i > j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
-  }
-  if (tid < w) {
-    dd[tid] = f.dpiv[gbase + tid];
-    ee[tid] = f.epiv[gbase + tid];
-    ty[tid] = f.pivtype[gbase + tid];
-    ps[tid] = f.lperm[gbase + tid] - c0;
+  if (tid < 64) {
+    const bool in = tid < w;
+    dd[tid] = in ? f.dpiv[gbase + tid] : 1.0;
+    ee[tid] = in ? f.epiv[gbase + tid] : 0.0;
+    ty[tid] = in ? f.pivtype[gbase + tid] : 0;
+    ps[tid] = in ? f.lperm[gbase + tid] - c0 : 0;
   }
   __syncthreads();
-  if (r >= m) return;
-  double v[64];
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  dbl4 accd[2][2];
+  flt4 accf[2][2];
 #pragma unroll
-  for (int k = 0; k < 64; ++k) v[k] = k < w ? (double)F[r + (int64_t)(c0 + ps[k]) * m] : 0.0;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-  for (int k = 1; k < 64; ++k) {
-    if (k < w) {
-      double acc = v[k];
-#pragma unroll
-      for (int j = 0; j < k; ++j) acc -= v[j] * L[k][j];
-      v[k] = acc;
+    for (int y = 0; y < 2; ++y) {
+      accd[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+      accf[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
     }
-  }
+  for (int kb = 0; kb < 64; kb += 16) {
 #pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    if (k < w) {
-      if (ty[k] == 0) {
-        v[k] = v[k] / dd[k];
-      } else if (ty[k] == 1 && k + 1 < 64) {
-        const double a = dd[k], b = ee[k], c = dd[k + 1];
-        const double det = a * c - b * b;
-        const double x0 = v[k], x1 = v[k + 1];
-        v[k] = (c * x0 - b * x1) / det;
-        v[k + 1] = (a * x1 - b * x0) / det;
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int rr = idx & 63, kk = idx >> 6;
+      const int k = kb + kk;
+      const int64_t r = r0 + rr;
+      sV[kk][rr] = (k < w && r < m) ? F[r + (int64_t)(c0 + ps[k]) * m] : (T)0;
+      // sX[kk][c] = X[c][k]: 1 on the diagonal, stored at (row c0+k, column c0+c) for c > k
+      const int c = rr;
+      T xv = (T)0;
+      if (k < w && c < w) xv = c == k ? (T)1 : (c > k ? F[(c0 + k) + (int64_t)(c0 + c) * m] : (T)0);
+      sX[kk][c] = xv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          const T av = sX[kr][wc + bj * 16 + (lane & 15)];
+          const T bv = sV[kr][wr + bi * 16 + (lane & 15)];
+          if constexpr (sizeof(T) == 8) {
+            accd[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accd[bi][bj], 0, 0, 0);
+          } else {
+            accf[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, accf[bi][bj], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  // X tile -> LDS (sC[c][r])
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) {
+        const int rr = wr + bi * 16 + (lane & 15);
+        const int cc = wc + bj * 16 + mfma_row<T>(lane, reg);
+        sC[cc][rr] = sizeof(T) == 8 ? (T)accd[bi][bj][reg] : (T)accf[bi][bj][reg];
       }
-    }
+  __syncthreads();
+  // W = X, transposed into the upper triangle: consecutive threads walk the columns c
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int c = idx & 63, rr = idx >> 6;
+    const int64_t r = r0 + rr;
+    if (c < w && r < m) F[(c0 + c) + r * m] = sC[c][rr];
   }
-#pragma unroll
-  for (int k = 0; k < 64; ++k)
-    if (k < w) F[r + (int64_t)(c0 + k) * m] = (T)v[k];
-}
-
-template <typename T>
-__device__ inline T ld_value(const T* F, int64_t m, int64_t c, int64_t k, int64_t g, const FrontArgs& f) {
-  const int t = f.pivtype[g];
-  double v;
-  if (t == 0) v = (double)F[c + k * m] * f.dpiv[g];
-  else if (t == 1) v = (double)F[c + k * m] * f.dpiv[g] + (double)F[c + (k + 1) * m] * f.epiv[g];
-  else v = (double)F[c + (k - 1) * m] * f.epiv[g - 1] + (double)F[c + k * m] * f.dpiv[g];
-  return (T)v;
+  // L21 = X D^-1: consecutive threads walk the rows r
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int rr = idx & 63, c = idx >> 6;
+    const int64_t r = r0 + rr;
+    if (c >= w || r >= m) continue;
+    const double x = (double)sC[c][rr];
+    double l;
+    if (ty[c] == 0) {
+      l = x / dd[c];
+    } else if (ty[c] == 1) {
+      const double a = dd[c], b = ee[c], cc = dd[c + 1];
+      l = (cc * x - b * (double)sC[c + 1][rr]) / (a * cc - b * b);
+    } else {
+      const double a = dd[c - 1], b = ee[c - 1], cc = dd[c];
+      l = (a * x - b * (double)sC[c - 1][rr]) / (a * cc - b * b);
+    }
+    F[r + (int64_t)(c0 + c) * m] = (T)l;
+  }
 }
 
 // C[r, c] -= sum_{k in [k0,k1)} L[r,k] (L D)[c,k] on one 64 x 64 tile, MFMA 16x16x4.
@@ -335,7 +391,6 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   if (j >= ct) return;  // beyond the task's tiles (never for a consistent schedule)
   const int64_t i = j + lt;
   const int64_t r0 = cb + 64 * i, cc0 = cb + 64 * j;
-  const int64_t gsn = f.sn_begin[sn];
   T* F = front + f.sn_front_off[sn];
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   dbl4 accd[2][2];
@@ -352,11 +407,16 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
-      const int rr = idx & 63, kk = idx >> 6;
-      const int64_t k = kb + kk;
-      const int64_t r = r0 + rr, c = cc0 + rr;
-      sL[kk][rr] = (k < k1 && r < m) ? F[r + k * m] : (T)0;
-      sW[kk][rr] = (k < k1 && c < cmax) ? ld_value<T>(F, m, c, k, gsn + k, f) : (T)0;
+      {
+        const int rr = idx & 63, kk = idx >> 6;  // 64 consecutive rows of one column of L
+        const int64_t k = kb + kk, r = r0 + rr;
+        sL[kk][rr] = (k < k1 && r < m) ? F[r + k * m] : (T)0;
+      }
+      {
+        const int kk = idx & 15, cc = idx >> 4;  // 16 consecutive k of one column of W^T
+        const int64_t k = kb + kk, c = cc0 + cc;
+        sW[kk][cc] = (k < k1 && c < cmax) ? F[k + c * m] : (T)0;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -477,7 +537,7 @@ template <typename T>
 void launch_panel_trsm(int64_t ntasks, int64_t max_rows, const int64_t* tasks, const FrontArgs& f, T* front,
                        hipStream_t s) {
   if (ntasks <= 0 || max_rows <= 0) return;
-  dim3 g((unsigned)ntasks, (unsigned)((max_rows + 255) / 256));
+  dim3 g((unsigned)ntasks, (unsigned)((max_rows + 63) / 64));
   k_panel_trsm<T><<<g, 256, 0, s>>>(tasks, f, front);
 }
 

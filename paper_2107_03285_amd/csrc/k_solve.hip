@@ -1,14 +1,28 @@
 // Level-scheduled multifrontal triangular solves with the supernodal factor.
 //
-// Forward (leaves to root): each front gathers its pivot entries of the
-// right-hand side plus its children's contribution vectors (fixed child
-// order), applies its pivot permutation, solves with the unit lower panels
-// and leaves rows [s, m) as the contribution for its parent; then D^-1
-// (1x1 and 2x2 blocks).  Backward (root to leaves): each front reads the
-// already-solved ancestor entries of its structure, forms
-// z = w - L21^T v with a fixed-order block reduction, solves L11^T and
-// scatters through the inverse pivot permutation.  Vectors are FP64 whatever
-// the factor precision.
+// The factorisation does not interchange rows of already factorised columns:
+// each panel's Bunch-Kaufman permutation only reorders that panel's own
+// columns, so the rows of panel R inside the columns of earlier panels keep
+// their original order.  The solves therefore apply each panel's permutation
+// at the moment the panel is solved.
+//
+// Per tree level (forward, leaves to root):
+//   F0 (one block per front): gather the pivot entries of the right-hand side
+//      and the children's contribution vectors (fixed child order);
+//   F1 (one block per panel, pipelined): t_R -= sum_{Q<R} L_RQ y_Q as soon as
+//      each earlier panel Q of the same front has published y_Q, then permute
+//      and solve the panel's unit lower block in one wavefront;
+//   F2 (many blocks per front): contribution to the parent, t_u - L21 y.
+// Backward (root to leaves):
+//   B1 (many blocks per front): z = D^-1 y - L21^T v_u, one wavefront per
+//      column, v_u read from the solution vector (ancestors are solved);
+//   B2 (one block per panel, pipelined in reverse): z_R -= sum_{Q>R} L_QR^T v_Q,
+//      solve the panel's L^T block, undo its permutation.
+// Pipelined blocks take ordered tickets from an atomic counter, so a block
+// only ever waits for blocks that started before it; every wait is bounded
+// and reports a timeout through an error flag instead of hanging.  Vectors
+// are FP64 whatever the factor precision, and every sum has a fixed order,
+// so solves are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -17,19 +31,44 @@ namespace sgn {
 
 namespace {
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_fwd(const int32_t* __restrict__ level_sn, SolveArgs a,
-                                             const T* __restrict__ front, const double* __restrict__ b) {
-  const int32_t* panel_ptr = a.panel_ptr;
-  const int32_t* panel_col = a.panel_col;
-  __shared__ double ys[64];
+constexpr long kSpinLimit = 1L << 22;
+
+__device__ inline int ticket(int* counter) {
+  __shared__ int t;
+  if (threadIdx.x == 0) t = atomicAdd(counter, 1);
+  __syncthreads();
+  return t;
+}
+
+// true once flag == epoch; false (and err set) when the bounded wait runs out or an
+// earlier wait of the same solve already timed out (so a failure ends every wait fast)
+__device__ inline bool wait_ready(const int* flag, int epoch, int* err) {
+  for (long it = 0; it < kSpinLimit; ++it) {
+    if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch) return true;
+    if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  atomicExch(err, 1);
+  return false;
+}
+
+__device__ inline void publish(int* flag, int epoch) {
+  __threadfence();
+  __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_fwd_gather(const int32_t* __restrict__ level_sn, SolveArgs a,
+                                                    const double* __restrict__ b) {
   const int tid = threadIdx.x;
   const int J = level_sn[blockIdx.x];
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J];
   double* tv = a.tv + a.sn_vec_off[J];
-  double* tp = a.tp + a.sn_vec_off[J];
-  const T* F = front + f.sn_front_off[J];
   for (int64_t k = tid; k < m; k += 256) tv[k] = k < s ? b[g0 + k] : 0.0;
   __syncthreads();
   for (int32_t q = a.child_ptr[J]; q < a.child_ptr[J + 1]; ++q) {
@@ -40,110 +79,241 @@ __global__ void __launch_bounds__(256) k_fwd(const int32_t* __restrict__ level_s
     for (int64_t r = tid; r < uC; r += 256) tv[rel[r]] += cv[r];
     __syncthreads();
   }
-  for (int64_t k = tid; k < m; k += 256) tp[k] = k < s ? tv[f.lperm[g0 + k]] : tv[k];
-  __syncthreads();
-  for (int32_t pi = panel_ptr[J]; pi + 1 < panel_ptr[J + 1]; ++pi) {
-    const int c0 = panel_col[pi], c1 = panel_col[pi + 1];
-    for (int k = c0; k < c1; ++k) {
-      const double y = tp[k];
-      for (int i = k + 1 + tid; i < c1; i += 256) tp[i] -= (double)F[i + (int64_t)k * m] * y;
-      __syncthreads();
-    }
-    if (tid < c1 - c0) ys[tid] = tp[c0 + tid];
-    __syncthreads();
-    for (int64_t r = c1 + tid; r < m; r += 256) {
-      double acc = 0.0;
-      for (int k = c0; k < c1; ++k) acc += (double)F[r + (int64_t)k * m] * ys[k - c0];
-      tp[r] -= acc;
-    }
-    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ tasks, int64_t ntasks, SolveArgs a,
+                                                    const T* __restrict__ front, int* counter, int* flags,
+                                                    int epoch, int* err) {
+  __shared__ double part[4][64];
+  __shared__ double Ld[64][65];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = ticket(counter);
+  if (t >= ntasks) return;
+  const int J = tasks[2 * t], pi = tasks[2 * t + 1];
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J], m = f.sn_m[J];
+  const int32_t pbase = a.panel_ptr[J];
+  const int c0 = a.panel_col[pbase + pi], c1 = a.panel_col[pbase + pi + 1], w = c1 - c0;
+  const double* tv = a.tv + a.sn_vec_off[J];
+  double* tp = a.tp + a.sn_vec_off[J];
+  const T* F = front + f.sn_front_off[J];
+  // the panel's own block does not depend on other panels: load it before waiting
+  for (int idx = tid; idx < w * w; idx += 256) {
+    const int i = idx % w, j = idx / w;
+    Ld[i][j] = i > j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
   }
-  for (int64_t k = tid; k < s; k += 256) {
+  // contributions of the earlier panels, panel Q handled by wave Q % 4
+  double acc = 0.0;
+  const T* rowbase = F + (c0 + (lane < w ? lane : 0));
+  for (int q = wave; q < pi; q += 4) {
+    const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
+    // the factor entries do not depend on the other panel: issue their loads first
+    double fv[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) fv[k] = (k < nq && lane < w) ? (double)rowbase[(int64_t)(q0 + k) * m] : 0.0;
+    if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
+    __builtin_amdgcn_wave_barrier();
+    __threadfence();
+    const double tk = lane < nq ? tp[q0 + lane] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 64; ++k) acc += fv[k] * __shfl(tk, k, 64);
+  }
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+    // u in original row order, then the panel permutation, then the unit lower solve
+    double u = 0.0;
+    if (lane < w) u = tv[c0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    const int src = lane < w ? f.lperm[g0 + c0 + lane] - c0 : 0;
+    double y = __shfl(u, src, 64);
+    for (int k = 0; k < w; ++k) {
+      const double yk = __shfl(y, k, 64);
+      if (lane > k && lane < w) y -= Ld[lane][k] * yk;
+    }
+    if (lane < w) tp[c0 + lane] = y;
+    if (lane == 0) publish(flags + pbase + pi, epoch);
+  }
+}
+
+// Split-k partial sums of L21 y: block (front, 64-row chunk, k-chunk of kSolveKC columns);
+// wave w takes 64 of the chunk's columns, lane = row, the four waves are summed in order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fwd_rect(const int32_t* __restrict__ level_sn, SolveArgs a,
+                                                  const T* __restrict__ front) {
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int J = level_sn[blockIdx.x];
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J], u = m - s;
+  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int64_t kb = (int64_t)blockIdx.z * 256;
+  if (r0 >= u || kb >= s) return;
+  const double* tp = a.tp + a.sn_vec_off[J];
+  const T* F = front + f.sn_front_off[J];
+  const int64_t r = r0 + lane;
+  const int64_t k0 = kb + 64 * wave;
+  const int nk = k0 >= s ? 0 : (int)((s - k0) < 64 ? (s - k0) : 64);
+  const T* rowp = F + s + (r < u ? r : 0) + k0 * m;
+  double fv[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) fv[k] = (k < nk && r < u) ? (double)rowp[(int64_t)k * m] : 0.0;
+  const double tk = lane < nk ? tp[k0 + lane] : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) acc += fv[k] * __shfl(tk, k, 64);
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && r < u)
+    a.part[a.sn_part_off[J] + blockIdx.z * u + r] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// t_u = tv_u - sum over k-chunks (ascending) of the partial sums
+__global__ void __launch_bounds__(256) k_fwd_rect_sum(const int32_t* __restrict__ level_sn, SolveArgs a) {
+  const int J = level_sn[blockIdx.x];
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J], u = m - s;
+  const int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (r >= u) return;
+  const int64_t nkc = (s + 255) / 256;
+  const double* pp = a.part + a.sn_part_off[J] + r;
+  double acc = 0.0;
+  for (int64_t kc = 0; kc < nkc; ++kc) acc += pp[kc * u];
+  a.tp[a.sn_vec_off[J] + s + r] = a.tv[a.sn_vec_off[J] + s + r] - acc;
+}
+
+// z_k = (D^-1 y)_k - sum_r L21[r, k] x[row_r] into tv[k]; one wavefront per pivot column
+template <typename T>
+__global__ void __launch_bounds__(256) k_bwd_rect(const int32_t* __restrict__ level_sn, SolveArgs a,
+                                                  const T* __restrict__ front, const double* __restrict__ x) {
+  const int lane = threadIdx.x & 63;
+  const int J = level_sn[blockIdx.x];
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J], u = m - s;
+  const int64_t k = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (k >= s) return;
+  const double* tp = a.tp + a.sn_vec_off[J];
+  double* tv = a.tv + a.sn_vec_off[J];
+  const T* F = front + f.sn_front_off[J] + s + k * m;
+  const int32_t* rows = f.sn_rows + f.sn_rows_ptr[J];
+  double acc = 0.0;
+  int64_t r = lane;
+  for (; r + 192 < u; r += 256) {  // four independent loads in flight per lane
+    const double a0 = (double)F[r], a1 = (double)F[r + 64], a2 = (double)F[r + 128], a3 = (double)F[r + 192];
+    const double v0 = x[rows[r]], v1 = x[rows[r + 64]], v2 = x[rows[r + 128]], v3 = x[rows[r + 192]];
+    acc += a0 * v0;
+    acc += a1 * v1;
+    acc += a2 * v2;
+    acc += a3 * v3;
+  }
+  for (; r < u; r += 64) acc += (double)F[r] * x[rows[r]];
+  acc = wave_sum(acc);
+  if (lane == 0) {
     const int t = f.pivtype[g0 + k];
+    double w;
     if (t == 0) {
-      tp[k] = tp[k] / f.dpiv[g0 + k];
+      w = tp[k] / f.dpiv[g0 + k];
     } else if (t == 1) {
       const double A = f.dpiv[g0 + k], B = f.epiv[g0 + k], C = f.dpiv[g0 + k + 1];
-      const double det = A * C - B * B;
-      const double x0 = tp[k], x1 = tp[k + 1];
-      tp[k] = (C * x0 - B * x1) / det;
-      tp[k + 1] = (A * x1 - B * x0) / det;
+      w = (C * tp[k] - B * tp[k + 1]) / (A * C - B * B);
+    } else {
+      const double A = f.dpiv[g0 + k - 1], B = f.epiv[g0 + k - 1], C = f.dpiv[g0 + k];
+      w = (A * tp[k] - B * tp[k - 1]) / (A * C - B * B);
     }
+    tv[k] = w - acc;
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_bwd(const int32_t* __restrict__ level_sn, SolveArgs a,
-                                             const T* __restrict__ front, double* __restrict__ x) {
-  const int32_t* panel_ptr = a.panel_ptr;
-  const int32_t* panel_col = a.panel_col;
-  __shared__ double red[16][257];
-  __shared__ double z[64];
-  const int tid = threadIdx.x;
-  const int J = level_sn[blockIdx.x];
+__global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ tasks, int64_t ntasks, SolveArgs a,
+                                                    const T* __restrict__ front, double* __restrict__ x,
+                                                    int* counter, int* flags, int epoch, int* err) {
+  __shared__ double part[4][64];
+  __shared__ double Ld[64][65];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = ticket(counter);
+  if (t >= ntasks) return;
+  const int J = tasks[2 * t], pi = tasks[2 * t + 1];
   const FrontArgs& f = a.f;
-  const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J];
-  double* tp = a.tp + a.sn_vec_off[J];
+  const int64_t g0 = f.sn_begin[J], m = f.sn_m[J];
+  const int32_t pbase = a.panel_ptr[J];
+  const int np = a.panel_ptr[J + 1] - pbase - 1;
+  const int c0 = a.panel_col[pbase + pi], c1 = a.panel_col[pbase + pi + 1], w = c1 - c0;
+  const double* tv = a.tv + a.sn_vec_off[J];
   const T* F = front + f.sn_front_off[J];
-  const int32_t* rows = f.sn_rows + f.sn_rows_ptr[J];
-  for (int64_t r = tid; r < m - s; r += 256) tp[s + r] = x[rows[r]];
-  __syncthreads();
-  for (int32_t pi = panel_ptr[J + 1] - 2; pi >= panel_ptr[J]; --pi) {
-    const int c0 = panel_col[pi], c1 = panel_col[pi + 1];
-    const int w = c1 - c0;
-    for (int kb = 0; kb < w; kb += 16) {
-      double acc[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-      for (int64_t r = c1 + tid; r < m; r += 256) {
-        const double v = tp[r];
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (kb + q < w) acc[q] += (double)F[r + (int64_t)(c0 + kb + q) * m] * v;
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) red[q][tid] = acc[q];
-      __syncthreads();
-      for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h)
-#pragma unroll
-          for (int q = 0; q < 16; ++q) red[q][tid] += red[q][tid + h];
-        __syncthreads();
-      }
-      if (tid < 16 && kb + tid < w) z[kb + tid] = tp[c0 + kb + tid] - red[tid][0];
-      __syncthreads();
-    }
-    for (int k = w - 1; k >= 0; --k) {
-      const double v = z[k];
-      for (int i = tid; i < k; i += 256) z[i] -= (double)F[(c0 + k) + (int64_t)(c0 + i) * m] * v;
-      __syncthreads();
-    }
-    if (tid < w) tp[c0 + tid] = z[tid];
-    __syncthreads();
+  for (int idx = tid; idx < w * w; idx += 256) {
+    const int i = idx % w, j = idx / w;
+    Ld[i][j] = i > j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
   }
-  for (int64_t k = tid; k < s; k += 256) x[g0 + f.lperm[g0 + k]] = tp[k];
+  // contributions of the later panels Q (every fourth one per wave, in the order they are
+  // solved): lane = column c0+lane of panel R, summing L[q0 + k', c0 + lane] v[q0 + k']
+  double acc = 0.0;
+  const T* colbase = F + (int64_t)(c0 + (lane < w ? lane : 0)) * m;
+  for (int q = np - 1 - wave; q > pi; q -= 4) {  // completion order: last panel first
+    const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
+    const T* col = colbase + q0;
+    double fv[64];
+#pragma unroll
+    for (int kk = 0; kk < 64; ++kk) fv[kk] = (kk < nq && lane < w) ? (double)col[kk] : 0.0;
+    if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
+    __builtin_amdgcn_wave_barrier();
+    __threadfence();
+    const double vl = lane < nq ? x[g0 + q0 + lane] : 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 64; ++kk) acc += fv[kk] * __shfl(vl, kk, 64);
+  }
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+    double z = 0.0;
+    if (lane < w) z = tv[c0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    for (int k = w - 1; k >= 0; --k) {
+      const double vk = __shfl(z, k, 64);
+      if (lane < k) z -= Ld[k][lane] * vk;
+    }
+    if (lane < w) x[g0 + f.lperm[g0 + c0 + lane]] = z;
+    if (lane == 0) publish(flags + pbase + pi, epoch);
+  }
 }
 
 }  // namespace
 
 template <typename T>
-void launch_fwd_level(int64_t nsn, const int32_t* level_sn, const SolveArgs& a, const T* front, const double* b,
-                      hipStream_t s) {
-  if (nsn > 0) k_fwd<T><<<(unsigned)nsn, 256, 0, s>>>(level_sn, a, front, b);
+void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* level_sn, const int32_t* tasks,
+                      int64_t ntasks, const SolveArgs& a, const T* front, const double* b, int* counter, int* flags,
+                      int epoch, int* err, hipStream_t s) {
+  if (nsn <= 0) return;
+  k_fwd_gather<<<(unsigned)nsn, 256, 0, s>>>(level_sn, a, b);
+  if (ntasks > 0) k_fwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, counter, flags, epoch, err);
+  if (max_u > 0) {
+    if (max_s > 0) {
+      dim3 g((unsigned)nsn, (unsigned)((max_u + 63) / 64), (unsigned)((max_s + 255) / 256));
+      k_fwd_rect<T><<<g, 256, 0, s>>>(level_sn, a, front);
+    }
+    dim3 g2((unsigned)nsn, (unsigned)((max_u + 255) / 256));
+    k_fwd_rect_sum<<<g2, 256, 0, s>>>(level_sn, a);
+  }
 }
 
 template <typename T>
-void launch_bwd_level(int64_t nsn, const int32_t* level_sn, const SolveArgs& a, const T* front, double* x,
+void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
+                      const SolveArgs& a, const T* front, double* x, int* counter, int* flags, int epoch, int* err,
                       hipStream_t s) {
-  if (nsn > 0) k_bwd<T><<<(unsigned)nsn, 256, 0, s>>>(level_sn, a, front, x);
+  if (nsn <= 0) return;
+  dim3 g((unsigned)nsn, (unsigned)((max_s + 3) / 4));
+  k_bwd_rect<T><<<g, 256, 0, s>>>(level_sn, a, front, x);
+  if (ntasks > 0)
+    k_bwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, x, counter, flags, epoch, err);
 }
 
-template void launch_fwd_level<double>(int64_t, const int32_t*, const SolveArgs&, const double*, const double*,
+template void launch_fwd_level<double>(int64_t, int64_t, int64_t, const int32_t*, const int32_t*, int64_t,
+                                       const SolveArgs&, const double*, const double*, int*, int*, int, int*,
                                        hipStream_t);
-template void launch_fwd_level<float>(int64_t, const int32_t*, const SolveArgs&, const float*, const double*,
-                                      hipStream_t);
-template void launch_bwd_level<double>(int64_t, const int32_t*, const SolveArgs&, const double*, double*,
-                                       hipStream_t);
-template void launch_bwd_level<float>(int64_t, const int32_t*, const SolveArgs&, const float*, double*, hipStream_t);
+template void launch_fwd_level<float>(int64_t, int64_t, int64_t, const int32_t*, const int32_t*, int64_t,
+                                      const SolveArgs&, const float*, const double*, int*, int*, int, int*, hipStream_t);
+template void launch_bwd_level<double>(int64_t, int64_t, const int32_t*, const int32_t*, int64_t, const SolveArgs&,
+                                       const double*, double*, int*, int*, int, int*, hipStream_t);
+template void launch_bwd_level<float>(int64_t, int64_t, const int32_t*, const int32_t*, int64_t, const SolveArgs&,
+                                      const float*, double*, int*, int*, int, int*, hipStream_t);
 
 }  // namespace sgn

@@ -108,14 +108,21 @@ struct SolveArgs {
   const int64_t* sn_vec_off;
   const int32_t* panel_ptr;
   const int32_t* panel_col;
+  const int64_t* sn_part_off;
+  double* part;  // split-k partial sums of L21 y
   double* tv;  // per-front accumulation vectors
   double* tp;  // per-front permuted working vectors
 };
+// One tree level of the forward / backward solve.  tasks: (front, panel) pairs in
+// pipeline order; counter: zeroed ticket counter of this launch; flags: per-panel
+// ready flags compared against epoch; err: set when a bounded wait runs out.
 template <typename T>
-void launch_fwd_level(int64_t nsn, const int32_t* level_sn, const SolveArgs& a, const T* front, const double* b,
-                      hipStream_t s);
+void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
+                      const SolveArgs& a, const T* front, const double* b, int* counter, int* flags, int epoch,
+                      int* err, hipStream_t s);
 template <typename T>
-void launch_bwd_level(int64_t nsn, const int32_t* level_sn, const SolveArgs& a, const T* front, double* x,
+void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
+                      const SolveArgs& a, const T* front, double* x, int* counter, int* flags, int epoch, int* err,
                       hipStream_t s);
 
 // ---------------------------------------------------------------- self test

@@ -278,6 +278,12 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     S.factor_entries += m * s;
     S.max_front = std::max<int>(S.max_front, (int)m);
   }
+  S.sn_part_off.assign(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) {
+    int64_t m = S.sn_m[t], sz = S.sn_begin[t + 1] - S.sn_begin[t];
+    S.sn_part_off[t + 1] = S.sn_part_off[t] + (m - sz) * ((sz + kSolveKC - 1) / kSolveKC);
+  }
+  S.part_total = S.sn_part_off[nt];
   S.front_total = S.sn_front_off[nt];
   S.vec_total = S.sn_vec_off[nt];
   // relative maps child struct -> parent front index
@@ -367,6 +373,9 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.panel_tasks.clear();
   S.upd_tasks.clear();
   S.ea_tasks.clear();
+  S.solve_fwd_tasks.clear();
+  S.solve_bwd_tasks.clear();
+  S.n_panels = (int64_t)S.panel_col.size();
   for (int L = 0; L < S.nlevels; ++L) {
     LevelPlan& P = S.levels[L];
     P.sn_begin = (int64_t)S.level_sn.size();
@@ -378,8 +387,24 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         maxp = std::max(maxp, S.panel_ptr[t + 1] - S.panel_ptr[t] - 1);
         P.max_children = std::max(P.max_children, S.child_ptr[t + 1] - S.child_ptr[t]);
         P.max_m = std::max<int64_t>(P.max_m, S.sn_m[t]);
+        P.max_s = std::max<int64_t>(P.max_s, S.sn_begin[t + 1] - S.sn_begin[t]);
+        P.max_u = std::max<int64_t>(P.max_u, S.sn_m[t] - (S.sn_begin[t + 1] - S.sn_begin[t]));
       }
     P.sn_end = (int64_t)S.level_sn.size();
+    P.fwd_begin = (int64_t)S.solve_fwd_tasks.size() / 2;
+    P.bwd_begin = (int64_t)S.solve_bwd_tasks.size() / 2;
+    for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
+      const int t = S.level_sn[q];
+      const int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
+      for (int k = 0; k < np; ++k) {
+        S.solve_fwd_tasks.push_back(t);
+        S.solve_fwd_tasks.push_back(k);
+        S.solve_bwd_tasks.push_back(t);
+        S.solve_bwd_tasks.push_back(np - 1 - k);
+      }
+    }
+    P.fwd_end = (int64_t)S.solve_fwd_tasks.size() / 2;
+    P.bwd_end = (int64_t)S.solve_bwd_tasks.size() / 2;
     for (int r = 0; r < P.max_children; ++r) {
       P.ea_begin.push_back((int64_t)S.ea_tasks.size() / 3);
       int64_t work = 0;

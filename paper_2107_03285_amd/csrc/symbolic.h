@@ -13,6 +13,7 @@ namespace sgn {
 constexpr int kPanel = 64;        // panel width of the blocked front factorisation
 constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
 constexpr int kTile = 64;         // update tile edge
+constexpr int kSolveKC = 256;     // k-chunk of the split-k L21 y product in the forward solve
 
 enum SystemKind { SYS_SGN = 0, SYS_KX = 1 };
 
@@ -45,7 +46,9 @@ struct LevelPlan {
   int max_children;                    // extend-add rounds
   std::vector<int64_t> ea_begin, ea_end, ea_work;  // per round: range in ea task table, total entries
   std::vector<PanelStep> steps;
-  int64_t max_m = 0;
+  int64_t max_m = 0, max_s = 0, max_u = 0;
+  int64_t fwd_begin = 0, fwd_end = 0;  // range (pairs) in solve_fwd_tasks: panels ascending per front
+  int64_t bwd_begin = 0, bwd_end = 0;  // range (pairs) in solve_bwd_tasks: panels descending per front
 };
 
 struct System {
@@ -70,6 +73,8 @@ struct System {
   std::vector<int32_t> sn_m;
   std::vector<int64_t> sn_front_off;     // element offset of the m x m column-major front
   std::vector<int64_t> sn_vec_off;       // element offset of the length-m solve vector
+  std::vector<int64_t> sn_part_off;      // offset of the split-k partial sums of L21 y (u * ceil(s / kSolveKC))
+  int64_t part_total = 0;
   std::vector<int64_t> relmap_off;       // [nsn+1] into relmap
   std::vector<int32_t> relmap;           // struct row r of child -> index in parent front
   std::vector<int32_t> child_ptr, child_list;
@@ -87,6 +92,9 @@ struct System {
   std::vector<int64_t> panel_tasks;      // (sn, c0, c1) per task: 3 entries
   std::vector<int64_t> upd_tasks;        // (sn, k0, k1, cb, ce, tile_prefix): 6 entries
   std::vector<int64_t> ea_tasks;         // (child, parent, work_prefix): 3 entries
+  std::vector<int32_t> solve_fwd_tasks;  // (sn, panel index) pairs, per level
+  std::vector<int32_t> solve_bwd_tasks;
+  int64_t n_panels = 0;                  // total panels (ready flags of the pipelined solves)
   // element -> lower CSR slot contributions and their inverse (gather) map
   int elem_stride = 0;                   // values per element in the element buffer
   std::vector<int64_t> slot_ptr;         // [nnz+1]
