@@ -35,6 +35,12 @@ WORKLOADS = {
 }
 PEAK = {"fp64": 78.6, "fp32": 157.3}  # dense matrix-core TFLOP/s of one MI355X
 HBM_PEAK = 8000.0  # GB/s
+# HBM traffic of the update kernel, from two hardware-counter runs of this script (FETCH_SIZE, then
+# WRITE_SIZE, scaled by what the counters read for a plain copy of known size).  The record holds a
+# hash of the kernel's source; a record taken from another version of the kernel is not used.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_update_cantilever_100x25x25_traffic.json")
+UPDATE_SOURCES = [os.path.join(ROOT, "paper_2107_03285_amd", "csrc", "k_factor.hip")]
+COPY_ELEMS = 1 << 28  # float32 elements of the calibration copy: 1 GiB read + 1 GiB written
 
 
 def log(*a):
@@ -66,15 +72,53 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"{n} steps in {dt:.1f} s"}
 
 
+def update_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in UPDATE_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload):
+    """Bytes per update launch from the counter record, or None if there is none for this workload or the
+    kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload or rec.get("source_sha256") != update_source_hash():
+        return None
+    return rec
+
+
+def copy_calibration():
+    """A plain elementwise copy (negation) of 1 GiB float32, three times: its counter readings give the
+    scale from FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    a = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 x torch.neg over {COPY_ELEMS * 4} bytes read and written")
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cantilever_100x25x25", choices=sorted(WORKLOADS))
     ap.add_argument("--paths", default="fp32ir,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events on the update kernel")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB copy first (for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sharded factorisation "
@@ -86,6 +130,8 @@ def main():
     from paper_2107_03285_amd import sgn
 
     dev = "cuda:0"
+    if args.copy_calibration:
+        copy_calibration()
     prob = WORKLOADS[args.workload]()
     log(f"[bench] workload {prob.name}: n_x={prob.n_x} n_p={prob.n_p} N={2 * prob.n_x + prob.n_p}")
     paths = [s.strip() for s in args.paths.split(",") if s.strip()]
@@ -143,8 +189,12 @@ def main():
         asm_ms = fac_ms = sol_ms = 0.0
         res = []
         sweeps = []
+        step_ms = []
         for k in range(args.steps):
+            ts = time.perf_counter()
             fi, si_ = run_step(ctx, rhs, sol)
+            torch.cuda.synchronize()
+            step_ms.append(1e3 * (time.perf_counter() - ts))
             st = ctx.stats()
             upd_ms += st.update_ms
             upd_fl += st.update_flops
@@ -159,7 +209,8 @@ def main():
         st = ctx.stats()
         K = args.steps
         results[path] = dict(
-            steps_per_s=K / dt, ms_per_step=1e3 * dt / K, factor_ms=fac_ms / K, solve_ms=sol_ms / K,
+            steps_per_s=K / dt, ms_per_step=1e3 * dt / K, median_ms=float(np.median(step_ms)),
+            iqr_ms=float(np.percentile(step_ms, 75) - np.percentile(step_ms, 25)), factor_ms=fac_ms / K, solve_ms=sol_ms / K,
             assemble_ms=asm_ms / K, assemble_gbs=st.assemble_bytes / (asm_ms / K * 1e-3) / 1e9,
             factor_tflops=st.factor_flops / (fac_ms / K * 1e-3) / 1e12, rel_res_max=max(res),
             refine_sweeps=max(sweeps), inertia=[fi.n_pos, fi.n_neg, fi.n_zero], perturbed=fi.n_perturbed,
@@ -186,8 +237,11 @@ def main():
     peak = PEAK["fp32" if head == "fp32ir" else "fp64"]
     roof = None
     if r["update_tflops"] is not None:
+        rec = recorded_traffic(prob.name) if head == "fp32ir" else None
         roof = {"bound": "mfma", "achieved": round(r["update_tflops"], 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(r["update_tflops"] / peak, 4), "traffic": None,
+                "frac": round(r["update_tflops"] / peak, 4),
+                "traffic": rec["bytes_per_launch"] if rec else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_update (MFMA trailing update of the fronts)",
                 "avg_launch_us": r["update_avg_us"], "flops_per_launch": r["update_flops_per_launch"]}
     cpu = None
