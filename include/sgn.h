@@ -179,6 +179,58 @@ sgn_status sgn_solve(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_
  * acceptance f(alpha) <= f(0) + 1e-4 alpha g^T dp.  (d_p, d_x) must be an
  * equilibrium on entry and are updated in place. */
 sgn_status sgn_step(sgn_ctx ctx, double* d_p, double* d_x, sgn_step_info* info);
+
+/* ---- Learned-preconditioner path.  The paper names preconditioning of the
+ * saddle-point system and iterative saddle-point solvers as future work
+ * (Sec. 6.1) after standard preconditioned Krylov solvers performed poorly
+ * on its problems (Sec. 5); the operator below is this library's own.
+ *
+ * Reference factor: the factorisation left by the most recent sgn_factor (or
+ * by a MINRES fallback), P (S K_ref S) P^T = L D L^T.  Preconditioner:
+ *   M = S^-1 P^T L B L^T P S^-1,  B = blockdiag_i(R_i C_i C_i^T R_i^T),
+ * over the node groups i (one free mesh node: its owned parameters, then x_v,
+ * then lambda_v, in elimination order).  R_i R_i^T = |D_i| is the eigen-
+ * absolute value of the group's 1x1 and 2x2 pivots (for a 2x2 pivot
+ * [[a,b],[b,e]] the first position takes the eigenvalue (a+e)/2 + rho with
+ * eigenvector (cos t, sin t), t = atan2(b, (a-e)/2)/2).  C_i is built from raw
+ * FP32 corrections: exp(r) on each owned-parameter position, and on the
+ * trailing 2d positions the lower-triangular block with diagonal exp(r_tt)
+ * and off-diagonal r_ij.  Zero corrections give B = |D|.  M is symmetric
+ * positive definite by construction. */
+
+/* Set (or clear, with NULLs) the raw corrections: d_corr_node [n_nodes *
+ * (2d)(2d+1)/2] float, per mesh node the lower triangle row by row (entry
+ * (i,j), i >= j, at i(i+1)/2 + j; positions ordered x_v components then
+ * lambda_v components); d_corr_par [n_p] float, per parameter.  Device
+ * pointers, caller-owned, read by every later preconditioner application
+ * until replaced; fixed nodes' entries are unused. */
+sgn_status sgn_set_pc_correction(sgn_ctx ctx, const float* d_corr_node, const float* d_corr_par);
+/* d_out = K_SGN d_in with the currently assembled matrix ([N] device arrays,
+ * block order, distinct). */
+sgn_status sgn_spmv(sgn_ctx ctx, const double* d_in, double* d_out);
+/* d_out = M^-1 d_in ([N], block order; may alias).  d_fwd (optional, [N])
+ * receives the forward-solve result L^-1 P S d_in in pivot order, the input
+ * of sgn_pc_grad.  Needs a reference factor (SGN_E_STATE otherwise). */
+sgn_status sgn_pc_apply(sgn_ctx ctx, const double* d_in, double* d_out, double* d_fwd);
+/* d_fwd = L^-1 P S d_in (pivot order) without the block and backward solves. */
+sgn_status sgn_pc_forward(sgn_ctx ctx, const double* d_in, double* d_fwd);
+/* Accumulate weight * d(ya^T B^-1 yb)/d(raw corrections) into d_grad_node
+ * (layout of d_corr_node) and d_grad_par (layout of d_corr_par; either may be
+ * NULL), where ya, yb are sgn_pc_forward results.  For a scalar loss l with
+ * dl/dy = g of y = M^-1 w, dl/dr = grad of fwd(g)^T B^-1 fwd(w).  Uses the
+ * corrections currently set; deterministic (every entry has one writer). */
+sgn_status sgn_pc_grad(sgn_ctx ctx, const double* d_fwd_a, const double* d_fwd_b, double weight,
+                       float* d_grad_node, float* d_grad_par);
+/* Solve K_SGN sol = rhs (assembled matrix) by preconditioned MINRES with the
+ * reference factor's M, to the equilibrated relative residual solve_rtol
+ * (row scaling of the current matrix).  Falls back to a fresh exact LDL^T
+ * (which becomes the new reference) plus refined solve when there is no
+ * reference factor, after max_minres iterations, or when the residual shrinks
+ * less than tenfold over 50 iterations; info->fallback reports it and
+ * info->sweeps counts MINRES iterations plus refinement sweeps.  sgn_step uses
+ * this solve when options.solver == SGN_MINRES_LEARNED. */
+sgn_status sgn_solve_minres(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_info* info);
+
 /* Sizes of a system: N, nnz of the lower CSR, number of supernodes, factor
  * entries sum(m*s) and dense front flops of one factorisation. */
 sgn_status sgn_get_sizes(sgn_ctx ctx, int which, int64_t* n, int64_t* nnz, int64_t* n_supernodes,

@@ -22,4 +22,7 @@ Modules:
   dense     -- global assembly, Newton equilibrium, dense S / GN step, dense
                solve of the saddle-point system, objective and gradient.
   symbolic  -- K_SGN pattern, nested-dissection order, permuted CSR, etree.
+  precond   -- dense LDL^T with node-group-restricted Bunch-Kaufman pivoting and
+               the node-block preconditioner built from it (the library's
+               MINRES path; the paper leaves preconditioning to future work).
 """

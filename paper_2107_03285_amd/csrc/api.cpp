@@ -79,8 +79,17 @@ struct DevSys {
   double* ir_r = nullptr;  // internal to refined_solve: residual
   double* ir_d = nullptr;  // internal to refined_solve: correction
   double* ir_s = nullptr;  // internal to refined_solve: scaled residual
+  // node-block preconditioner (SGN system only)
+  int32_t* grp_ptr = nullptr;
+  int32_t* grp_node = nullptr;
+  int64_t* grp_vec = nullptr;
+  int64_t ngroups = 0;
+  double* pc_w = nullptr;      // [N] block-solved forward result (pivot order)
+  double* cur_scale = nullptr; // [N] row scaling of the currently assembled matrix (residual weights)
+  double* mr[10] = {};         // MINRES work vectors
   int prec = 0;  // 0: FP64 fronts, 1: FP32 fronts
-  bool factored = false;
+  bool factored = false;  // a factorisation is held (the MINRES reference)
+  bool current = false;   // ... and it is of the currently assembled matrix
   int64_t inertia[3] = {0, 0, 0};
 };
 
@@ -146,6 +155,8 @@ struct sgn_ctx_s {
   double* d_scal = nullptr;
   int* d_cnt = nullptr;
   unsigned long long* d_ull = nullptr;
+  const float* corr_node = nullptr;  // caller-owned raw preconditioner corrections (null: none)
+  const float* corr_par = nullptr;
   bool kx_valid = false;
   bool sgn_assembled = false;
   size_t ws_need = 0;  // workspace bytes, fixed at create (layout() with a null base resets pointers)
@@ -153,9 +164,9 @@ struct sgn_ctx_s {
   std::vector<hipEvent_t> ev_pool;  // per-launch timing events (profile = 1)
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   ~sgn_ctx_s() {
-    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
-    if (ev_a) hipEventDestroy(ev_a);
-    if (ev_b) hipEventDestroy(ev_b);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
   }
 };
 
@@ -267,6 +278,15 @@ size_t layout(sgn_ctx c, char* base) {
     D.ir_r = L.take<double>(S.N);
     D.ir_d = L.take<double>(S.N);
     D.ir_s = L.take<double>(S.N);
+    if (si == 0) {
+      D.ngroups = (int64_t)S.grp_node.size();
+      D.grp_ptr = L.take<int32_t>(S.grp_ptr.size());
+      D.grp_node = L.take<int32_t>(S.grp_node.size());
+      D.grp_vec = L.take<int64_t>(S.grp_vec.size());
+      D.pc_w = L.take<double>(S.N);
+      D.cur_scale = L.take<double>(S.N);
+      for (double*& v : D.mr) v = L.take<double>(S.N);
+    }
   }
   c->d_elems = L.take<int32_t>(ne * nv);
   c->d_efdof = L.take<int32_t>(ne * nv);
@@ -456,6 +476,7 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   launch_inertia(S.N, D.dpiv, D.epiv, D.pivtype, c->d_ull, c->d_part, st);
   HIPCHK(hipGetLastError());
   D.factored = true;
+  D.current = true;
   return SGN_OK;
 }
 
@@ -499,12 +520,8 @@ sgn_status factor_dispatch(sgn_ctx c, int si, double piv_tol, sgn_factor_info* i
   return SGN_OK;
 }
 
-// solve in the system's (new, scaled) space: x = Ks^-1 b with b, x in new order
-template <typename T>
-sgn_status solve_once_t(sgn_ctx c, int si, const double* b_new, double* x_new) {
-  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+SolveArgs solve_args(sgn_ctx c, int si) {
   DevSys& D = c->sys[si];
-  hipStream_t st = c->stream;
   SolveArgs a;
   a.f.sn_begin = D.sn_begin;
   a.f.sn_m = D.sn_m;
@@ -529,15 +546,42 @@ sgn_status solve_once_t(sgn_ctx c, int si, const double* b_new, double* x_new) {
   a.tp = D.tp;
   a.sn_part_off = D.sn_part_off;
   a.part = D.part;
+  a.wd = nullptr;
+  return a;
+}
+
+// forward sweep y = L^-1 P b (b in the system's new, scaled order); y is left in the
+// per-front vectors tp (pivot order)
+template <typename T>
+sgn_status fwd_sweep_t(sgn_ctx c, int si, const double* b_new) {
+  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+  DevSys& D = c->sys[si];
+  hipStream_t st = c->stream;
+  const SolveArgs a = solve_args(c, si);
   const T* front = reinterpret_cast<const T*>(D.front);
   HIPCHK(hipMemsetAsync(D.solve_ctr, 0, 2 * (size_t)S.nlevels * sizeof(int), st));
   int* err = c->d_cnt + 12;
-  const int e_fwd = ++D.epoch, e_bwd = ++D.epoch;
+  const int e_fwd = ++D.epoch;
   for (int L = 0; L < S.nlevels; ++L) {
     const LevelPlan& P = S.levels[L];
     launch_fwd_level<T>(P.sn_end - P.sn_begin, P.max_u, P.max_s, D.level_sn + P.sn_begin, D.solve_fwd_tasks + 2 * P.fwd_begin,
                         P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr + 2 * L, D.solve_flags, e_fwd, err, st);
   }
+  HIPCHK(hipGetLastError());
+  return SGN_OK;
+}
+
+// backward sweep x = P^T L^-T w, with w = D^-1 y from tp (wd null) or given in pivot order
+template <typename T>
+sgn_status bwd_sweep_t(sgn_ctx c, int si, double* x_new, const double* wd) {
+  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+  DevSys& D = c->sys[si];
+  hipStream_t st = c->stream;
+  SolveArgs a = solve_args(c, si);
+  a.wd = wd;
+  const T* front = reinterpret_cast<const T*>(D.front);
+  int* err = c->d_cnt + 12;
+  const int e_bwd = ++D.epoch;
   for (int L = S.nlevels - 1; L >= 0; --L) {
     const LevelPlan& P = S.levels[L];
     launch_bwd_level<T>(P.sn_end - P.sn_begin, P.max_s, D.level_sn + P.sn_begin, D.solve_bwd_tasks + 2 * P.bwd_begin,
@@ -548,6 +592,13 @@ sgn_status solve_once_t(sgn_ctx c, int si, const double* b_new, double* x_new) {
   return SGN_OK;
 }
 
+sgn_status fwd_sweep(sgn_ctx c, int si, const double* b_new) {
+  return c->sys[si].prec ? fwd_sweep_t<float>(c, si, b_new) : fwd_sweep_t<double>(c, si, b_new);
+}
+sgn_status bwd_sweep(sgn_ctx c, int si, double* x_new, const double* wd) {
+  return c->sys[si].prec ? bwd_sweep_t<float>(c, si, x_new, wd) : bwd_sweep_t<double>(c, si, x_new, wd);
+}
+
 void scale_vec(sgn_ctx c, int64_t n, const double* s, const double* in, double* out);
 
 // x_new = K^-1 b_new with the current factor (x_new may alias b_new; uses D.sv)
@@ -555,9 +606,50 @@ sgn_status solve_once(sgn_ctx c, int si, const double* b_new, double* x_new) {
   DevSys& D = c->sys[si];
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
   scale_vec(c, S.N, D.scale, b_new, D.sv);
-  if (D.prec) TRY(solve_once_t<float>(c, si, D.sv, x_new));
-  else TRY(solve_once_t<double>(c, si, D.sv, x_new));
+  TRY(fwd_sweep(c, si, D.sv));
+  TRY(bwd_sweep(c, si, x_new, nullptr));
   scale_vec(c, S.N, D.scale, x_new, x_new);
+  return SGN_OK;
+}
+
+PcArgs pc_args(sgn_ctx c) {
+  DevSys& D = c->sys[0];
+  PcArgs a;
+  a.ngroups = D.ngroups;
+  a.dim = c->A.mesh.dim;
+  a.nx = c->A.mesh.n_x;
+  a.grp_ptr = D.grp_ptr;
+  a.grp_node = D.grp_node;
+  a.grp_vec = D.grp_vec;
+  a.perm = D.perm;
+  a.dpiv = D.dpiv;
+  a.epiv = D.epiv;
+  a.pivtype = D.pivtype;
+  a.corr_node = c->corr_node;
+  a.corr_par = c->corr_par;
+  return a;
+}
+
+// out_new = M^-1 in_new with the node-block preconditioner of the reference factor (new order;
+// out_new may alias in_new); ysave: optional flat copy of the forward result (pivot order)
+sgn_status pc_apply_new(sgn_ctx c, const double* in_new, double* out_new, double* ysave) {
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  scale_vec(c, N, D.scale, in_new, D.sv);
+  TRY(fwd_sweep(c, 0, D.sv));
+  launch_pc_block(pc_args(c), D.tp, ysave, D.pc_w, c->stream);
+  TRY(bwd_sweep(c, 0, out_new, D.pc_w));
+  scale_vec(c, N, D.scale, out_new, out_new);
+  return SGN_OK;
+}
+
+// flat forward result y = L^-1 P S in (pivot order) of the reference factor
+sgn_status pc_forward_new(sgn_ctx c, const double* in_new, double* y) {
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  scale_vec(c, N, D.scale, in_new, D.sv);
+  TRY(fwd_sweep(c, 0, D.sv));
+  launch_pc_block(pc_args(c), D.tp, y, D.pc_w, c->stream);  // saves y; the block result is not used
   return SGN_OK;
 }
 
@@ -615,6 +707,104 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
     c->err = "refinement stopped at equilibrated relative residual " + std::to_string(rel);
     return SGN_E_REFINE;
   }
+  return SGN_OK;
+}
+
+// Preconditioned MINRES on the assembled SGN matrix (new order, unscaled), with the
+// node-block preconditioner of the reference factor.  The iterate minimises the
+// M^-1-norm of the residual over the Krylov space (Lanczos three-term recurrence with
+// M-inner products, QR of the tridiagonal by Givens rotations, three-term update of
+// the search directions).  Convergence is judged on the true residual with the same
+// equilibrated measure as the direct solve, with the row scaling of the current
+// matrix.  Returns SGN_OK with *converged false when it hits max_iter or stagnates
+// (less than a tenfold reduction over `window` iterations).
+sgn_status minres_new(sgn_ctx c, const double* b, double* x, int max_iter, int window, int* iters, double* rel_out,
+                      bool* converged) {
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  hipStream_t st = c->stream;
+  double *v_prev = D.mr[0], *v = D.mr[1], *v_next = D.mr[2], *z = D.mr[3], *z_next = D.mr[4];
+  double *w_prev = D.mr[5], *w = D.mr[6], *w_next = D.mr[7], *q = D.mr[8], *r = D.mr[9];
+  *converged = false;
+  *iters = 0;
+  launch_row_scaling(N, D.frowptr, D.fslot, D.vals, D.cur_scale, st);
+  launch_fill(N, 0.0, x, st);
+  launch_fill(N, 0.0, v_prev, st);
+  launch_fill(N, 0.0, w_prev, st);
+  launch_fill(N, 0.0, w, st);
+  HIPCHK(hipMemcpyAsync(v, b, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  scale_vec(c, N, D.cur_scale, b, r);
+  dev_dot(c, N, r, r, 20);
+  TRY(pc_apply_new(c, v, z, nullptr));
+  dev_dot(c, N, v, z, 21);
+  double h[2];
+  TRY(read_scalars(c, 20, 2, h));
+  const double sb = std::sqrt(h[0]);
+  if (sb == 0.0) {
+    *converged = true;
+    *rel_out = 0.0;
+    return SGN_OK;
+  }
+  if (!(h[1] > 0.0)) {
+    *rel_out = 1.0;
+    return SGN_OK;  // preconditioner not positive on b: let the caller fall back
+  }
+  double gam = std::sqrt(h[1]), gam_prev = 1.0, eta = gam;
+  double c_prev = 1.0, cc = 1.0, s_prev = 0.0, ss = 0.0;
+  std::vector<double> hist;
+  double rel = 1.0;
+  for (int j = 1; j <= max_iter; ++j) {
+    launch_lincomb3(N, 1.0 / gam, z, 0.0, nullptr, 0.0, nullptr, z, st);  // z_j normalised
+    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, z, q, st);
+    dev_dot(c, N, q, z, 20);
+    double dl;
+    TRY(read_scalars(c, 20, 1, &dl));
+    launch_lincomb3(N, 1.0, q, -dl / gam, v, -gam / gam_prev, v_prev, v_next, st);
+    TRY(pc_apply_new(c, v_next, z_next, nullptr));
+    dev_dot(c, N, v_next, z_next, 21);
+    double g2;
+    TRY(read_scalars(c, 21, 1, &g2));
+    if (g2 < 0.0) break;  // the preconditioner lost definiteness in rounding
+    const double gam_next = std::sqrt(g2);
+    const double a0 = cc * dl - c_prev * ss * gam;
+    const double a1 = std::sqrt(a0 * a0 + gam_next * gam_next);
+    const double a2 = ss * dl + c_prev * cc * gam;
+    const double a3 = s_prev * gam;
+    if (a1 == 0.0) break;
+    const double c_next = a0 / a1, s_next = gam_next / a1;
+    launch_lincomb3(N, 1.0 / a1, z, -a3 / a1, w_prev, -a2 / a1, w, w_next, st);
+    launch_axpby(N, 1.0, x, c_next * eta, w_next, x, st);
+    eta = -s_next * eta;
+    // true equilibrated residual of the iterate
+    launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, x, b, r, st);
+    scale_vec(c, N, D.cur_scale, r, r);
+    dev_dot(c, N, r, r, 22);
+    double rn;
+    TRY(read_scalars(c, 22, 1, &rn));
+    rel = std::sqrt(rn) / sb;
+    hist.push_back(rel);
+    *iters = j;
+    if (verbose()) fprintf(stderr, "[sgn] minres %d: rel %.3e |eta| %.3e\n", j, rel, std::fabs(eta));
+    if (rel <= c->opt.solve_rtol) {
+      *converged = true;
+      break;
+    }
+    if (j > window && rel > 0.1 * hist[j - 1 - window]) break;  // stagnation
+    if (gam_next == 0.0) break;  // invariant subspace: the iterate is exact in it
+    // rotate
+    std::swap(v_prev, v);
+    std::swap(v, v_next);
+    std::swap(z, z_next);
+    std::swap(w_prev, w);
+    std::swap(w, w_next);
+    gam_prev = gam;
+    gam = gam_next;
+    c_prev = cc;
+    cc = c_next;
+    s_prev = ss;
+    ss = s_next;
+  }
+  *rel_out = rel;
   return SGN_OK;
 }
 
@@ -793,7 +983,7 @@ sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rh
                               8.0 * (double)A.mesh.rest.size() + 8.0 * (double)A.sgn.colind.size();
   }
   c->sgn_assembled = true;
-  c->sys[0].factored = false;
+  c->sys[0].current = false;
   if (obj) TRY(objective_value(c, x, p, obj));
   if (rhs_old || grad) {
     const int64_t nt = (int64_t)c->target_dof.size();
@@ -868,7 +1058,7 @@ sgn_status sgn_factor_impl(sgn_ctx c, sgn_factor_info* info) {
 
 sgn_status sgn_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_info* info) {
   DevSys& D = c->sys[0];
-  if (!D.factored) return fail(c, SGN_E_STATE, "sgn_solve before sgn_factor");
+  if (!D.current) return fail(c, SGN_E_STATE, "sgn_solve before sgn_factor of the assembled matrix");
   const int64_t N = c->A.sgn.N;
   launch_gather_perm(N, D.perm, nullptr, rhs, c->d_old2, c->stream);
   double* zn = c->d_old;  // new-order solution
@@ -878,6 +1068,54 @@ sgn_status sgn_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_i
   HIPCHK(hipStreamSynchronize(c->stream));
   c->stats.solve_ms = now_ms() - t0;
   if (s != SGN_OK) return fail(c, s, c->err);
+  return SGN_OK;
+}
+
+// MINRES with the reference factor's preconditioner; on stagnation, on max_minres
+// iterations, or without a reference factor: exact factorisation of the current
+// matrix (which becomes the new reference) and the refined direct solve.
+sgn_status minres_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_info* info) {
+  DevSys& D = c->sys[0];
+  if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "sgn_solve_minres before sgn_assemble");
+  const int64_t N = c->A.sgn.N;
+  const double t0 = now_ms();
+  launch_gather_perm(N, D.perm, nullptr, rhs, c->d_old2, c->stream);
+  double* zn = c->d_old;
+  sgn_solve_info si{};
+  bool conv = false;
+  if (D.factored) {
+    HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+    int it = 0;
+    double rel = 1.0;
+    TRY(minres_new(c, c->d_old2, zn, c->opt.max_minres, 50, &it, &rel, &conv));
+    int timeout = 0;
+    HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (timeout) return fail(c, SGN_E_HIP, "a pipelined triangular solve timed out waiting for a panel");
+    si.sweeps = it;
+    si.rel_res = rel;
+    si.raw_rel_res = -1.0;
+  }
+  if (!conv) {
+    sgn_factor_info fi{};
+    TRY(sgn_factor_impl(c, &fi));
+    const int it = si.sweeps;
+    sgn_status s = refined_solve(c, 0, c->d_old2, zn, &si);
+    if (s != SGN_OK) return fail(c, s, c->err);
+    si.sweeps += it;
+    si.fallback = 1;
+  }
+  launch_scatter_perm(N, D.perm, nullptr, zn, sol, c->stream);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  si.ms = now_ms() - t0;
+  c->stats.solve_ms = si.ms;
+  if (info) *info = si;
+  return SGN_OK;
+}
+
+sgn_status pc_ready(sgn_ctx c) {
+  TRY(check_ready(c));
+  if (!c->sys[0].factored) return fail(c, SGN_E_STATE, "no reference factor (call sgn_factor first)");
   return SGN_OK;
 }
 
@@ -1021,6 +1259,11 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.solve_fwd_tasks, S.solve_fwd_tasks, st));
     HIPCHK(up(D.solve_bwd_tasks, S.solve_bwd_tasks, st));
     HIPCHK(up(D.sn_part_off, S.sn_part_off, st));
+    if (si == 0) {
+      HIPCHK(up(D.grp_ptr, S.grp_ptr, st));
+      HIPCHK(up(D.grp_node, S.grp_node, st));
+      HIPCHK(up(D.grp_vec, S.grp_vec, st));
+    }
     HIPCHK(hipMemsetAsync(D.solve_flags, 0xff, std::max<int64_t>(1, S.n_panels) * sizeof(int), st));
     D.epoch = 0;
     if (D.n_const) {
@@ -1110,14 +1353,17 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   double t1 = now_ms();
   si.ms_rhs = 0;
   si.ms_assemble = t1 - t0;
-  {
+  if (c->opt.solver == SGN_MINRES_LEARNED) {
+    sgn_status s = minres_solve_impl(c, rhs, sol, &si.solve);
+    if (s != SGN_OK) return s;
+  } else {
     sgn_factor_info fi{};
     sgn_status s = sgn_factor_impl(c, &fi);
     if (s != SGN_OK) return s;
   }
   double t2 = now_ms();
   si.ms_factor = t2 - t1;
-  {
+  if (c->opt.solver != SGN_MINRES_LEARNED) {
     sgn_status s = sgn_solve_impl(c, rhs, sol, &si.solve);
     if (s != SGN_OK) return s;
   }
@@ -1171,6 +1417,73 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   HIPCHK(hipMemcpyAsync(d_x, c->d_xt, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return SGN_OK;
+}
+
+sgn_status sgn_set_pc_correction(sgn_ctx c, const float* d_corr_node, const float* d_corr_par) {
+  TRY(check_ready(c));
+  c->corr_node = d_corr_node;
+  c->corr_par = d_corr_par;
+  return SGN_OK;
+}
+
+sgn_status sgn_spmv(sgn_ctx c, const double* d_in, double* d_out) {
+  TRY(check_ready(c));
+  if (!d_in || !d_out || d_in == d_out) return fail(c, SGN_E_ARG, "sgn_spmv needs distinct vectors");
+  if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "sgn_spmv before sgn_assemble");
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  launch_gather_perm(N, D.perm, nullptr, d_in, c->d_old2, c->stream);
+  launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, c->d_old2, c->d_old, c->stream);
+  launch_scatter_perm(N, D.perm, nullptr, c->d_old, d_out, c->stream);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+sgn_status sgn_pc_apply(sgn_ctx c, const double* d_in, double* d_out, double* d_fwd) {
+  TRY(pc_ready(c));
+  if (!d_in || !d_out) return fail(c, SGN_E_ARG, "null vector");
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+  launch_gather_perm(N, D.perm, nullptr, d_in, c->d_old2, c->stream);
+  TRY(pc_apply_new(c, c->d_old2, c->d_old, d_fwd));
+  launch_scatter_perm(N, D.perm, nullptr, c->d_old, d_out, c->stream);
+  int timeout = 0;
+  HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (timeout) return fail(c, SGN_E_HIP, "a pipelined triangular solve timed out waiting for a panel");
+  return SGN_OK;
+}
+
+sgn_status sgn_pc_forward(sgn_ctx c, const double* d_in, double* d_fwd) {
+  TRY(pc_ready(c));
+  if (!d_in || !d_fwd) return fail(c, SGN_E_ARG, "null vector");
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+  launch_gather_perm(N, D.perm, nullptr, d_in, c->d_old2, c->stream);
+  TRY(pc_forward_new(c, c->d_old2, d_fwd));
+  int timeout = 0;
+  HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (timeout) return fail(c, SGN_E_HIP, "a pipelined triangular solve timed out waiting for a panel");
+  return SGN_OK;
+}
+
+sgn_status sgn_pc_grad(sgn_ctx c, const double* d_fwd_a, const double* d_fwd_b, double weight, float* d_grad_node,
+                       float* d_grad_par) {
+  TRY(pc_ready(c));
+  if (!d_fwd_a || !d_fwd_b) return fail(c, SGN_E_ARG, "null vector");
+  launch_pc_grad(pc_args(c), d_fwd_a, d_fwd_b, weight, d_grad_node, d_grad_par, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+sgn_status sgn_solve_minres(sgn_ctx c, const double* d_rhs, double* d_sol, sgn_solve_info* info) {
+  TRY(check_ready(c));
+  if (!d_rhs || !d_sol || d_rhs == d_sol) return fail(c, SGN_E_ARG, "sgn_solve_minres needs distinct vectors");
+  return minres_solve_impl(c, d_rhs, d_sol, info);
 }
 
 sgn_status sgn_get_sizes(sgn_ctx c, int which, int64_t* n, int64_t* nnz, int64_t* nsn, int64_t* fe, double* fl) {

@@ -15,7 +15,8 @@
 //   F2 (many blocks per front): contribution to the parent, t_u - L21 y.
 // Backward (root to leaves):
 //   B1 (many blocks per front): z = D^-1 y - L21^T v_u, one wavefront per
-//      column, v_u read from the solution vector (ancestors are solved);
+//      column, v_u read from the solution vector (ancestors are solved); a
+//      preconditioner supplies its own block solve of D in place of D^-1 y;
 //   B2 (one block per panel, pipelined in reverse): z_R -= sum_{Q>R} L_QR^T v_Q,
 //      solve the panel's L^T block, undo its permutation.
 // Pipelined blocks take ordered tickets from an atomic counter, so a block
@@ -211,7 +212,9 @@ __global__ void __launch_bounds__(256) k_bwd_rect(const int32_t* __restrict__ le
   if (lane == 0) {
     const int t = f.pivtype[g0 + k];
     double w;
-    if (t == 0) {
+    if (a.wd) {
+      w = a.wd[g0 + k];
+    } else if (t == 0) {
       w = tp[k] / f.dpiv[g0 + k];
     } else if (t == 1) {
       const double A = f.dpiv[g0 + k], B = f.epiv[g0 + k], C = f.dpiv[g0 + k + 1];

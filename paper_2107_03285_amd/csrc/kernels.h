@@ -112,6 +112,7 @@ struct SolveArgs {
   double* part;  // split-k partial sums of L21 y
   double* tv;  // per-front accumulation vectors
   double* tp;  // per-front permuted working vectors
+  const double* wd;  // null: the backward solve applies D^-1; else it takes D^-1 y from here (pivot order)
 };
 // One tree level of the forward / backward solve.  tasks: (front, panel) pairs in
 // pipeline order; counter: zeroed ticket counter of this launch; flags: per-panel
@@ -124,6 +125,30 @@ template <typename T>
 void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
                       const SolveArgs& a, const T* front, double* x, int* counter, int* flags, int epoch, int* err,
                       hipStream_t s);
+
+// ---------------------------------------------------------------- node-block preconditioner
+struct PcArgs {
+  int64_t ngroups;
+  int dim;
+  int64_t nx;
+  const int32_t* grp_ptr;    // [ngroups+1] first pivot position of each node group
+  const int32_t* grp_node;   // [ngroups] mesh node of the group
+  const int64_t* grp_vec;    // [ngroups] solve-vector index of the group's first position
+  const int32_t* perm;       // new -> old variable (owned parameter positions -> parameter id)
+  const double* dpiv;
+  const double* epiv;
+  const int32_t* pivtype;
+  const float* corr_node;    // [n_nodes * (2d)(2d+1)/2] raw lower-triangular corrections, or null
+  const float* corr_par;     // [n_p] raw parameter corrections, or null
+};
+// w = B^-1 y per node group (y from the forward solve's vectors tp; ysave: optional flat copy of y)
+void launch_pc_block(const PcArgs& a, const double* tp, double* ysave, double* w, hipStream_t s);
+// gn, gp += weight * d(ya^T B^-1 yb)/d(raw corrections)
+void launch_pc_grad(const PcArgs& a, const double* ya, const double* yb, double weight, float* gn, float* gp,
+                    hipStream_t s);
+// out = a x + b y + c z (y, z may be null)
+void launch_lincomb3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,
+                     double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- self test
 // C(16x16) = A(16x4) B(4x16) on one MFMA; out holds D row-major (double or float)

@@ -659,6 +659,17 @@ std::string analyse(Analysis& A) {
     }
     std::string err = finish_system(S, nd.tree, vbeg, pub, pub_n, adj);
     if (!err.empty()) return "SGN: " + err;
+    S.grp_ptr.resize(nfree + 1);
+    S.grp_node.resize(nfree);
+    S.grp_vec.resize(nfree);
+    for (int64_t q = 0; q <= nfree; ++q) S.grp_ptr[q] = (int32_t)vbeg[q];
+    for (int64_t q = 0; q < nfree; ++q) {
+      const int64_t g = vbeg[q];
+      const int J = S.var_sn[g];
+      if (S.var_sn[vbeg[q + 1] - 1] != J) return "SGN: node group split across supernodes";
+      S.grp_node[q] = (int32_t)nd.order[q];
+      S.grp_vec[q] = S.sn_vec_off[J] + (g - S.sn_begin[J]);
+    }
   }
   // ---------------------------------------------------------------- Kx system
   {

@@ -64,6 +64,11 @@ struct System {
   std::vector<int32_t> fcol, fslot;
   // pivot groups (BK pivoting is restricted to a group), new numbering
   std::vector<int32_t> var_group_end;    // per var: end (exclusive) of its group
+  // node groups of the SGN system (owned parameters, x_v, lambda_v of one free node), in elimination
+  // order: first position, mesh node, and the solve-vector index of the first position
+  std::vector<int32_t> grp_ptr;          // [n_free+1]
+  std::vector<int32_t> grp_node;         // [n_free]
+  std::vector<int64_t> grp_vec;          // [n_free]
   // supernodes (contiguous pivot ranges)
   int nsn = 0;
   std::vector<int32_t> sn_begin;         // [nsn+1]

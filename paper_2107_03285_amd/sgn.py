@@ -29,7 +29,8 @@ SGN_SYS_SGN, SGN_SYS_KX = 0, 1
 EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_workspace", "sgn_set_targets",
            "sgn_equilibrium", "sgn_assemble", "sgn_factor", "sgn_solve", "sgn_step", "sgn_get_sizes",
            "sgn_get_symbolic", "sgn_get_values", "sgn_get_stats", "sgn_selftest_mfma", "sgn_last_error",
-           "sgn_destroy"]
+           "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
+           "sgn_solve_minres"]
 
 
 class sgn_problem(C.Structure):
@@ -115,6 +116,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_get_stats": (C.c_int, [vp, C.POINTER(sgn_stats)]),
         "sgn_last_error": (C.c_char_p, [vp]),
         "sgn_destroy": (None, [vp]),
+        "sgn_set_pc_correction": (C.c_int, [vp, vp, vp]),
+        "sgn_spmv": (C.c_int, [vp, vp, vp]),
+        "sgn_pc_apply": (C.c_int, [vp, vp, vp, vp]),
+        "sgn_pc_forward": (C.c_int, [vp, vp, vp]),
+        "sgn_pc_grad": (C.c_int, [vp, vp, vp, C.c_double, vp, vp]),
+        "sgn_solve_minres": (C.c_int, [vp, vp, vp, C.POINTER(sgn_solve_info)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -270,6 +277,29 @@ class Context:
         info = sgn_solve_info()
         self._check(self.lib.sgn_solve(self.h, _dev_ptr(rhs), _dev_ptr(sol), C.byref(info)))
         return info
+
+    def solve_minres(self, rhs, sol):
+        info = sgn_solve_info()
+        self._check(self.lib.sgn_solve_minres(self.h, _dev_ptr(rhs), _dev_ptr(sol), C.byref(info)))
+        return info
+
+    def set_pc_correction(self, corr_node=None, corr_par=None):
+        """Raw FP32 corrections (device tensors [n_nodes * (2d)(2d+1)/2], [n_p]) or None."""
+        self._keep["corr"] = (corr_node, corr_par)
+        self._check(self.lib.sgn_set_pc_correction(self.h, _dev_ptr(corr_node), _dev_ptr(corr_par)))
+
+    def spmv(self, x, y):
+        self._check(self.lib.sgn_spmv(self.h, _dev_ptr(x), _dev_ptr(y)))
+
+    def pc_apply(self, v, out, fwd=None):
+        self._check(self.lib.sgn_pc_apply(self.h, _dev_ptr(v), _dev_ptr(out), _dev_ptr(fwd)))
+
+    def pc_forward(self, v, fwd):
+        self._check(self.lib.sgn_pc_forward(self.h, _dev_ptr(v), _dev_ptr(fwd)))
+
+    def pc_grad(self, fwd_a, fwd_b, weight, grad_node=None, grad_par=None):
+        self._check(self.lib.sgn_pc_grad(self.h, _dev_ptr(fwd_a), _dev_ptr(fwd_b), float(weight),
+                                         _dev_ptr(grad_node), _dev_ptr(grad_par)))
 
     def step(self, p, x):
         info = sgn_step_info()
