@@ -231,6 +231,44 @@ sgn_status sgn_pc_grad(sgn_ctx ctx, const double* d_fwd_a, const double* d_fwd_b
  * this solve when options.solver == SGN_MINRES_LEARNED. */
 sgn_status sgn_solve_minres(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_info* info);
 
+/* ---- Preconditioner network (FP32 weights and activations).  A mesh graph
+ * network maps the change from a reference state (x_a, p_a) to the current
+ * state (x, p) to the raw corrections of sgn_set_pc_correction.  Graph: mesh
+ * nodes, one directed edge each way between nodes sharing an element.
+ * Inputs: per node (x - x_a)/ell, (x - X)/ell (zero on fixed nodes), a fixed
+ * flag, and the mean over the node's elements of (p - p_a) and of p (log
+ * modulus) or |p_v - p_a,v|/ell and |p_v|/ell (per-node parameters); per edge
+ * (X_s - X_d)/hbar and ((x_s - x_d) - (X_s - X_d))/ell, hbar the mean rest edge
+ * length.  Encoders to width 64 (tanh), three layers of
+ *   e <- e + tanh(W [h_dst, h_src, e] + b),  h <- h + tanh(W [h, mean_in(e)] + b),
+ * decoders: per node W h + b to the (2d)(2d+1)/2 block entries (then d
+ * parameter corrections for per-node parameters), per element W mean(h) + b
+ * (log modulus).  Weight vector layout: dense layers in the order enc_node,
+ * enc_edge, (edge_l, node_l) for l = 0..2, dec_node, dec_elem, each as W
+ * (K x N row-major) followed by b (N).  Every reduction has a fixed order:
+ * results are bitwise reproducible.  All pointers are device pointers owned by
+ * the caller; activations of the last forward pass live in the workspace. */
+
+/* Number of FP32 weights of the context's network. */
+sgn_status sgn_gnn_num_weights(sgn_ctx ctx, int64_t* n);
+/* Glorot-uniform initial weights from a counter-based generator (splitmix64
+ * of seed); the decoders start at zero (corrections 0, M uses |D|). */
+sgn_status sgn_gnn_init(sgn_ctx ctx, float* d_w, uint64_t seed);
+/* Forward pass: d_corr_node [n_nodes * (2d)(2d+1)/2], d_corr_par [n_p] (the
+ * layouts of sgn_set_pc_correction).  d_x_ref, d_x [n_x] and d_p_ref, d_p
+ * [n_p] are FP64 states; ell is the context's length scale. */
+sgn_status sgn_gnn_forward(sgn_ctx ctx, const float* d_w, const double* d_x_ref, const double* d_p_ref,
+                           const double* d_x, const double* d_p, float* d_corr_node, float* d_corr_par);
+/* Backward pass of the last forward: d_gw [n_weights] += the gradient of
+ * sum(d_gcorr_node * corr_node) + sum(d_gcorr_par * corr_par) (either
+ * cotangent may be NULL).  SGN_E_STATE before any forward pass. */
+sgn_status sgn_gnn_backward(sgn_ctx ctx, const float* d_w, const float* d_gcorr_node, const float* d_gcorr_par,
+                            float* d_gw);
+/* One Adam step with bias correction (step >= 1) on n FP32 weights; m and v
+ * are the caller's moment buffers (zero before step 1).  Synchronises stream. */
+sgn_status sgn_adam(int64_t n, float* d_w, const float* d_g, float* d_m, float* d_v, float lr, float beta1,
+                    float beta2, float eps, int step, void* stream);
+
 /* Sizes of a system: N, nnz of the lower CSR, number of supernodes, factor
  * entries sum(m*s) and dense front flops of one factorisation. */
 sgn_status sgn_get_sizes(sgn_ctx ctx, int which, int64_t* n, int64_t* nnz, int64_t* n_supernodes,

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/sgn.h"
+#include "gnn.h"
 #include "kernels.h"
 #include "symbolic.h"
 
@@ -155,6 +156,14 @@ struct sgn_ctx_s {
   double* d_scal = nullptr;
   int* d_cnt = nullptr;
   unsigned long long* d_ull = nullptr;
+  // preconditioner network: graph tables and activations (FP32)
+  GnnGraph G;
+  struct {
+    int32_t *src, *dst, *in_ptr, *out_ptr, *out_list, *inc_ptr, *inc_list, *nfdof;
+    float *nf, *ef, *h[kGnnLayers + 1], *yn[kGnnLayers], *agg[kGnnLayers], *e[kGnnLayers + 1], *ye[kGnnLayers];
+    float *dec, *emb, *dh[2], *de[2], *dz, *dx, *dagg, *ddec, *demb, *part;
+  } g{};
+  bool gnn_fwd_done = false;
   const float* corr_node = nullptr;  // caller-owned raw preconditioner corrections (null: none)
   const float* corr_par = nullptr;
   bool kx_valid = false;
@@ -287,6 +296,43 @@ size_t layout(sgn_ctx c, char* base) {
       D.cur_scale = L.take<double>(S.N);
       for (double*& v : D.mr) v = L.take<double>(S.N);
     }
+  }
+  {
+    const GnnGraph& G = c->G;
+    const int64_t nn = A.mesh.n_nodes, E = G.n_edges, H = kGnnH;
+    const int64_t rows = std::max<int64_t>(std::max<int64_t>(E, nn), ne);
+    auto& g = c->g;
+    g.src = L.take<int32_t>(E);
+    g.dst = L.take<int32_t>(E);
+    g.in_ptr = L.take<int32_t>(nn + 1);
+    g.out_ptr = L.take<int32_t>(nn + 1);
+    g.out_list = L.take<int32_t>(E);
+    g.inc_ptr = L.take<int32_t>(nn + 1);
+    g.inc_list = L.take<int32_t>(ne * nv);
+    g.nfdof = L.take<int32_t>(nn);
+    g.nf = L.take<float>(nn * G.fn);
+    g.ef = L.take<float>(E * G.fe);
+    for (int l = 0; l <= kGnnLayers; ++l) {
+      g.h[l] = L.take<float>(nn * H);
+      g.e[l] = L.take<float>(E * H);
+    }
+    for (int l = 0; l < kGnnLayers; ++l) {
+      g.yn[l] = L.take<float>(nn * H);
+      g.agg[l] = L.take<float>(nn * H);
+      g.ye[l] = L.take<float>(E * H);
+    }
+    g.dec = L.take<float>(nn * G.nout_node);
+    g.emb = L.take<float>(G.param_kind == 0 ? ne * H : 0);
+    for (int i = 0; i < 2; ++i) {
+      g.dh[i] = L.take<float>(nn * H);
+      g.de[i] = L.take<float>(E * H);
+    }
+    g.dz = L.take<float>(rows * H);
+    g.dx = L.take<float>(rows * kGnnMaxK);
+    g.dagg = L.take<float>(nn * H);
+    g.ddec = L.take<float>(nn * G.nout_node);
+    g.demb = L.take<float>(G.param_kind == 0 ? ne * H : 0);
+    g.part = L.take<float>((int64_t)wgrad_parts(rows) * (kGnnMaxK + 1) * H);
   }
   c->d_elems = L.take<int32_t>(ne * nv);
   c->d_efdof = L.take<int32_t>(ne * nv);
@@ -1113,6 +1159,166 @@ sgn_status minres_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solv
   return SGN_OK;
 }
 
+// ------------------------------------------------------------------ preconditioner network
+DenseArgs dense_args(const float* w, const GnnDense& L, int64_t rows, int act) {
+  DenseArgs a{};
+  a.rows = rows;
+  a.nseg = 0;
+  a.K = 0;
+  a.W = w + L.w;
+  a.N = L.n;
+  a.act = act;
+  return a;
+}
+
+void add_seg(DenseArgs& a, const float* src, const int32_t* idx, int width, int ld) {
+  a.seg[a.nseg++] = DenseSeg{src, idx, width, ld};
+  a.K += width;
+}
+
+sgn_status gnn_forward_impl(sgn_ctx c, const float* w, const double* x_ref, const double* p_ref, const double* x,
+                            const double* p, float* cn, float* cp) {
+  const GnnGraph& G = c->G;
+  auto& g = c->g;
+  hipStream_t st = c->stream;
+  const int64_t nn = G.n_nodes, E = G.n_edges, ne = G.n_elems, H = kGnnH;
+  GnnFeatArgs fa{};
+  fa.n_nodes = nn;
+  fa.n_edges = E;
+  fa.dim = G.dim;
+  fa.param_kind = G.param_kind;
+  fa.nfdof = g.nfdof;
+  fa.rest = c->d_rest;
+  fa.x = x;
+  fa.x_ref = x_ref;
+  fa.p = p;
+  fa.p_ref = p_ref;
+  fa.inc_ptr = g.inc_ptr;
+  fa.inc_list = g.inc_list;
+  fa.ell = c->ell;
+  fa.hbar = G.hbar;
+  launch_gnn_features(fa, g.src, g.dst, g.nf, g.ef, st);
+  {
+    DenseArgs a = dense_args(w, G.enc_n, nn, 1);
+    add_seg(a, g.nf, nullptr, G.fn, G.fn);
+    a.out = g.h[0];
+    a.ld_out = H;
+    launch_dense_fwd(a, st);
+    DenseArgs b = dense_args(w, G.enc_e, E, 1);
+    add_seg(b, g.ef, nullptr, G.fe, G.fe);
+    b.out = g.e[0];
+    b.ld_out = H;
+    launch_dense_fwd(b, st);
+  }
+  for (int l = 0; l < kGnnLayers; ++l) {
+    DenseArgs a = dense_args(w, G.edge[l], E, 1);
+    add_seg(a, g.h[l], g.dst, H, H);
+    add_seg(a, g.h[l], g.src, H, H);
+    add_seg(a, g.e[l], nullptr, H, H);
+    a.res = g.e[l];
+    a.ld_res = H;
+    a.out = g.e[l + 1];
+    a.ld_out = H;
+    a.ysave = g.ye[l];
+    launch_dense_fwd(a, st);
+    launch_fill_f32(nn * H, 0.0f, g.agg[l], st);
+    launch_gather_add(nn, g.in_ptr, nullptr, g.e[l + 1], H, 0, H, 1.0f, 1, g.agg[l], H, st);
+    DenseArgs b = dense_args(w, G.node[l], nn, 1);
+    add_seg(b, g.h[l], nullptr, H, H);
+    add_seg(b, g.agg[l], nullptr, H, H);
+    b.res = g.h[l];
+    b.ld_res = H;
+    b.out = g.h[l + 1];
+    b.ld_out = H;
+    b.ysave = g.yn[l];
+    launch_dense_fwd(b, st);
+  }
+  {
+    DenseArgs a = dense_args(w, G.dec_n, nn, 0);
+    add_seg(a, g.h[kGnnLayers], nullptr, H, H);
+    a.out = g.dec;
+    a.ld_out = G.nout_node;
+    launch_dense_fwd(a, st);
+    launch_split_out(nn, G.tri, G.nout_node, G.dim, G.param_kind != 0, g.nfdof, g.dec, cn, cp, st);
+  }
+  if (G.param_kind == 0) {
+    launch_elem_mean(ne, G.dim + 1, c->d_elems, g.h[kGnnLayers], g.emb, st);
+    DenseArgs a = dense_args(w, G.dec_e, ne, 0);
+    add_seg(a, g.emb, nullptr, H, H);
+    a.out = cp;
+    a.ld_out = 1;
+    launch_dense_fwd(a, st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  c->gnn_fwd_done = true;
+  return SGN_OK;
+}
+
+// gw += d(sum gcn . cn + gcp . cp)/dw with the activations of the last forward pass
+sgn_status gnn_backward_impl(sgn_ctx c, const float* w, const float* gcn, const float* gcp, float* gw) {
+  const GnnGraph& G = c->G;
+  auto& g = c->g;
+  hipStream_t st = c->stream;
+  const int64_t nn = G.n_nodes, E = G.n_edges, ne = G.n_elems, H = kGnnH;
+  float* dh = g.dh[0];  // dL/dh of the current layer
+  float* de = g.de[0];  // dL/de of the current layer
+  launch_fill_f32(nn * H, 0.0f, dh, st);
+  launch_fill_f32(E * H, 0.0f, de, st);
+  // decoders
+  launch_split_bwd(nn, G.tri, G.nout_node, G.dim, G.param_kind != 0, g.nfdof, gcn, gcp, g.ddec, st);
+  {
+    DenseArgs a = dense_args(w, G.dec_n, nn, 0);
+    add_seg(a, g.h[kGnnLayers], nullptr, H, H);
+    launch_dense_bwd(a, g.ddec, G.nout_node, nullptr, g.dz, g.dx, st);
+    launch_dense_wgrad(a, g.dz, g.part, gw + G.dec_n.w, st);
+    launch_gather_add(nn, nullptr, nullptr, g.dx, H, 0, H, 1.0f, 0, dh, H, st);
+  }
+  if (G.param_kind == 0 && gcp) {
+    DenseArgs a = dense_args(w, G.dec_e, ne, 0);
+    add_seg(a, g.emb, nullptr, H, H);
+    launch_dense_bwd(a, gcp, 1, nullptr, g.dz, g.demb, st);
+    launch_dense_wgrad(a, g.dz, g.part, gw + G.dec_e.w, st);
+    launch_gather_add(nn, g.inc_ptr, g.inc_list, g.demb, H, 0, H, 1.0f / (float)(G.dim + 1), 0, dh, H, st);
+  }
+  // message-passing layers in reverse
+  for (int l = kGnnLayers - 1; l >= 0; --l) {
+    {  // node update: h[l+1] = h[l] + tanh(W [h[l], agg[l]] + b)
+      DenseArgs a = dense_args(w, G.node[l], nn, 1);
+      add_seg(a, g.h[l], nullptr, H, H);
+      add_seg(a, g.agg[l], nullptr, H, H);
+      launch_dense_bwd(a, dh, H, g.yn[l], g.dz, g.dx, st);
+      launch_dense_wgrad(a, g.dz, g.part, gw + G.node[l].w, st);
+      launch_gather_add(nn, nullptr, nullptr, g.dx, 2 * H, 0, H, 1.0f, 0, dh, H, st);  // residual + h input
+      launch_edge_mean_bwd(E, g.dst, g.in_ptr, g.dx, 2 * H, H, de, st);                // agg = mean of e[l+1]
+    }
+    {  // edge update: e[l+1] = e[l] + tanh(W [h[l]_dst, h[l]_src, e[l]] + b)
+      DenseArgs a = dense_args(w, G.edge[l], E, 1);
+      add_seg(a, g.h[l], g.dst, H, H);
+      add_seg(a, g.h[l], g.src, H, H);
+      add_seg(a, g.e[l], nullptr, H, H);
+      launch_dense_bwd(a, de, H, g.ye[l], g.dz, g.dx, st);
+      launch_dense_wgrad(a, g.dz, g.part, gw + G.edge[l].w, st);
+      launch_gather_add(E, nullptr, nullptr, g.dx, 3 * H, 2 * H, H, 1.0f, 0, de, H, st);           // residual + e input
+      launch_gather_add(nn, g.in_ptr, nullptr, g.dx, 3 * H, 0, H, 1.0f, 0, dh, H, st);           // h as receiver
+      launch_gather_add(nn, g.out_ptr, g.out_list, g.dx, 3 * H, H, H, 1.0f, 0, dh, H, st);       // h as sender
+    }
+  }
+  {  // encoders (tanh outputs e[0], h[0])
+    DenseArgs a = dense_args(w, G.enc_e, E, 1);
+    add_seg(a, g.ef, nullptr, G.fe, G.fe);
+    launch_dense_bwd(a, de, H, g.e[0], g.dz, nullptr, st);
+    launch_dense_wgrad(a, g.dz, g.part, gw + G.enc_e.w, st);
+    DenseArgs b = dense_args(w, G.enc_n, nn, 1);
+    add_seg(b, g.nf, nullptr, G.fn, G.fn);
+    launch_dense_bwd(b, dh, H, g.h[0], g.dz, nullptr, st);
+    launch_dense_wgrad(b, g.dz, g.part, gw + G.enc_n.w, st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return SGN_OK;
+}
+
 sgn_status pc_ready(sgn_ctx c) {
   TRY(check_ready(c));
   if (!c->sys[0].factored) return fail(c, SGN_E_STATE, "no reference factor (call sgn_factor first)");
@@ -1173,6 +1379,8 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
   if (!(pr->E0 > 0) || !(pr->nu > -1.0 && pr->nu < 0.5)) return fail(c, SGN_E_ARG, "invalid material");
   std::string err = analyse(c->A);
   if (!err.empty()) return fail(c, SGN_E_ARG, "symbolic analysis: " + err);
+  err = build_gnn_graph(m, c->G);
+  if (!err.empty()) return fail(c, SGN_E_ARG, "preconditioner graph: " + err);
   const int64_t nx = m.n_x, np = m.n_p;
   if (pr->n_targets < 0 || (pr->n_targets > 0 && !pr->target_dof)) return fail(c, SGN_E_ARG, "targets");
   c->target_dof.assign(pr->target_dof, pr->target_dof + pr->n_targets);
@@ -1277,6 +1485,17 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
       HIPCHK(hipMemcpyAsync(D.const_slots, cs.data(), cs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
     }
+  }
+  {
+    const GnnGraph& G = c->G;
+    HIPCHK(up(c->g.src, G.e_src, st));
+    HIPCHK(up(c->g.dst, G.e_dst, st));
+    HIPCHK(up(c->g.in_ptr, G.in_ptr, st));
+    HIPCHK(up(c->g.out_ptr, G.out_ptr, st));
+    HIPCHK(up(c->g.out_list, G.out_list, st));
+    HIPCHK(up(c->g.inc_ptr, G.inc_ptr, st));
+    HIPCHK(up(c->g.inc_list, G.inc_list, st));
+    HIPCHK(up(c->g.nfdof, A.mesh.fdof, st));
   }
   HIPCHK(up(c->d_elems, A.mesh.elems, st));
   HIPCHK(up(c->d_efdof, c->efdof, st));
@@ -1484,6 +1703,47 @@ sgn_status sgn_solve_minres(sgn_ctx c, const double* d_rhs, double* d_sol, sgn_s
   TRY(check_ready(c));
   if (!d_rhs || !d_sol || d_rhs == d_sol) return fail(c, SGN_E_ARG, "sgn_solve_minres needs distinct vectors");
   return minres_solve_impl(c, d_rhs, d_sol, info);
+}
+
+sgn_status sgn_gnn_num_weights(sgn_ctx c, int64_t* n) {
+  if (!c || !n) return SGN_E_ARG;
+  *n = c->G.n_weights;
+  return SGN_OK;
+}
+
+sgn_status sgn_gnn_init(sgn_ctx c, float* d_w, uint64_t seed) {
+  TRY(check_ready(c));
+  if (!d_w) return fail(c, SGN_E_ARG, "null weights");
+  std::vector<float> w;
+  gnn_init_weights(c->G, seed, w);
+  HIPCHK(hipMemcpyAsync(d_w, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+sgn_status sgn_gnn_forward(sgn_ctx c, const float* d_w, const double* d_x_ref, const double* d_p_ref,
+                           const double* d_x, const double* d_p, float* d_corr_node, float* d_corr_par) {
+  TRY(check_ready(c));
+  if (!d_w || !d_x_ref || !d_p_ref || !d_x || !d_p || !d_corr_node || !d_corr_par)
+    return fail(c, SGN_E_ARG, "null argument");
+  return gnn_forward_impl(c, d_w, d_x_ref, d_p_ref, d_x, d_p, d_corr_node, d_corr_par);
+}
+
+sgn_status sgn_gnn_backward(sgn_ctx c, const float* d_w, const float* d_gcorr_node, const float* d_gcorr_par,
+                            float* d_gw) {
+  TRY(check_ready(c));
+  if (!d_w || !d_gw) return fail(c, SGN_E_ARG, "null argument");
+  if (!c->gnn_fwd_done) return fail(c, SGN_E_STATE, "sgn_gnn_backward before sgn_gnn_forward");
+  return gnn_backward_impl(c, d_w, d_gcorr_node, d_gcorr_par, d_gw);
+}
+
+sgn_status sgn_adam(int64_t n, float* d_w, const float* d_g, float* d_m, float* d_v, float lr, float beta1,
+                    float beta2, float eps, int step, void* stream) {
+  if (n < 0 || (n > 0 && (!d_w || !d_g || !d_m || !d_v)) || step < 1) return SGN_E_ARG;
+  launch_adam(n, d_w, d_g, d_m, d_v, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  if (hipGetLastError() != hipSuccess) return SGN_E_HIP;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SGN_E_HIP;
+  return SGN_OK;
 }
 
 sgn_status sgn_get_sizes(sgn_ctx c, int which, int64_t* n, int64_t* nnz, int64_t* nsn, int64_t* fe, double* fl) {

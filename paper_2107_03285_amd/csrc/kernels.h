@@ -150,6 +150,63 @@ void launch_pc_grad(const PcArgs& a, const double* ya, const double* yb, double 
 void launch_lincomb3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,
                      double* out, hipStream_t s);
 
+// ---------------------------------------------------------------- preconditioner network (FP32)
+struct DenseSeg {
+  const float* src;     // row r of the segment: src[(idx ? idx[r] : r) * ld + 0 .. width)
+  const int32_t* idx;
+  int width, ld;
+};
+struct DenseArgs {
+  int64_t rows;
+  DenseSeg seg[3];
+  int nseg, K;          // K = sum of segment widths (<= 192)
+  const float* W;       // [K x N] row-major, bias [N] right after
+  int N;                // outputs (<= 64)
+  int act;              // 1: tanh, 0: identity
+  const float* res;     // optional residual added to the output
+  int ld_res;
+  float* out;
+  int ld_out;
+  float* ysave;         // optional [rows x N] activation outputs (for the backward pass)
+};
+struct GnnFeatArgs {
+  int64_t n_nodes, n_edges;
+  int dim, param_kind;
+  const int32_t* nfdof;     // [n_nodes] first free DOF, -1 fixed
+  const double* rest;       // [n_nodes * dim]
+  const double* x;          // current state [n_x]
+  const double* x_ref;      // reference state [n_x]
+  const double* p;          // [n_p]
+  const double* p_ref;      // [n_p]
+  const int32_t* inc_ptr;   // node -> elements
+  const int32_t* inc_list;
+  double ell, hbar;
+};
+void launch_dense_fwd(const DenseArgs& a, hipStream_t s);
+void launch_dense_bwd(const DenseArgs& a, const float* dout, int ld_dout, const float* y, float* dz, float* dx,
+                      hipStream_t s);
+int wgrad_parts(int64_t rows);
+// gw[(K+1) x N] += sum over rows of [x_r; 1] dz_r^T (part: wgrad_parts(rows) * (K+1) * N floats)
+void launch_dense_wgrad(const DenseArgs& a, const float* dz, float* part, float* gw, hipStream_t s);
+// dst[v, 0:width] += scale * sum_{k in [ptr[v], ptr[v+1])} src[list ? list[k] : k, col : col + width]
+// (without ptr: the single row v; divide_by_count: mean instead of sum)
+void launch_gather_add(int64_t nv, const int32_t* ptr, const int32_t* list, const float* src, int ld_src, int col,
+                       int width, float scale, int divide_by_count, float* dst, int ld_dst, hipStream_t s);
+// dE[e, :] += dagg[dst_e, col : col + 64] / deg(dst_e)
+void launch_edge_mean_bwd(int64_t ne, const int32_t* dst, const int32_t* in_ptr, const float* dagg, int ld, int col,
+                          float* dE, hipStream_t s);
+void launch_elem_mean(int64_t ne, int nv, const int32_t* elems, const float* h, float* emb, hipStream_t s);
+void launch_gnn_features(const GnnFeatArgs& a, const int32_t* src, const int32_t* dst, float* nf, float* ef,
+                         hipStream_t s);
+void launch_split_out(int64_t n_nodes, int tri, int nout, int d, int per_node_params, const int32_t* nfdof,
+                      const float* dec, float* cn, float* cp, hipStream_t s);
+void launch_split_bwd(int64_t n_nodes, int tri, int nout, int d, int per_node_params, const int32_t* nfdof,
+                      const float* gcn, const float* gcp, float* ddec, hipStream_t s);
+void launch_add_f32(int64_t n, const float* src, float* dst, hipStream_t s);
+void launch_fill_f32(int64_t n, float v, float* dst, hipStream_t s);
+void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                 int t, hipStream_t s);
+
 // ---------------------------------------------------------------- self test
 // C(16x16) = A(16x4) B(4x16) on one MFMA; out holds D row-major (double or float)
 void launch_mfma_probe(int prec, const double* a, const double* b, double* out, hipStream_t s);

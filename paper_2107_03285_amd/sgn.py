@@ -30,7 +30,8 @@ EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_w
            "sgn_equilibrium", "sgn_assemble", "sgn_factor", "sgn_solve", "sgn_step", "sgn_get_sizes",
            "sgn_get_symbolic", "sgn_get_values", "sgn_get_stats", "sgn_selftest_mfma", "sgn_last_error",
            "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
-           "sgn_solve_minres"]
+           "sgn_solve_minres", "sgn_gnn_num_weights", "sgn_gnn_init", "sgn_gnn_forward", "sgn_gnn_backward",
+           "sgn_adam"]
 
 
 class sgn_problem(C.Structure):
@@ -122,6 +123,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_pc_forward": (C.c_int, [vp, vp, vp]),
         "sgn_pc_grad": (C.c_int, [vp, vp, vp, C.c_double, vp, vp]),
         "sgn_solve_minres": (C.c_int, [vp, vp, vp, C.POINTER(sgn_solve_info)]),
+        "sgn_gnn_num_weights": (C.c_int, [vp, i64p]),
+        "sgn_gnn_init": (C.c_int, [vp, vp, C.c_uint64]),
+        "sgn_gnn_forward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "sgn_gnn_backward": (C.c_int, [vp, vp, vp, vp, vp]),
+        "sgn_adam": (C.c_int, [C.c_int64, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
+                               vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -301,6 +308,22 @@ class Context:
         self._check(self.lib.sgn_pc_grad(self.h, _dev_ptr(fwd_a), _dev_ptr(fwd_b), float(weight),
                                          _dev_ptr(grad_node), _dev_ptr(grad_par)))
 
+    def gnn_num_weights(self) -> int:
+        n = C.c_int64()
+        self._check(self.lib.sgn_gnn_num_weights(self.h, C.byref(n)))
+        return n.value
+
+    def gnn_init(self, w, seed=0):
+        self._check(self.lib.sgn_gnn_init(self.h, _dev_ptr(w), C.c_uint64(seed)))
+
+    def gnn_forward(self, w, x_ref, p_ref, x, p, corr_node, corr_par):
+        self._check(self.lib.sgn_gnn_forward(self.h, _dev_ptr(w), _dev_ptr(x_ref), _dev_ptr(p_ref), _dev_ptr(x),
+                                             _dev_ptr(p), _dev_ptr(corr_node), _dev_ptr(corr_par)))
+
+    def gnn_backward(self, w, gcorr_node, gcorr_par, gw):
+        self._check(self.lib.sgn_gnn_backward(self.h, _dev_ptr(w), _dev_ptr(gcorr_node), _dev_ptr(gcorr_par),
+                                              _dev_ptr(gw)))
+
     def step(self, p, x):
         info = sgn_step_info()
         self._check(self.lib.sgn_step(self.h, _dev_ptr(p), _dev_ptr(x), C.byref(info)))
@@ -318,6 +341,16 @@ class Context:
 
     def last_error(self) -> str:
         return self.lib.sgn_last_error(self.h).decode()
+
+
+def adam(w, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One Adam step on FP32 device tensors (w updated in place)."""
+    lib = load_library()
+    st = lib.sgn_adam(w.numel(), _dev_ptr(w), _dev_ptr(g), _dev_ptr(m), _dev_ptr(v), float(lr), float(beta1),
+                      float(beta2), float(eps), int(step),
+                      C.c_void_p(int(stream.cuda_stream)) if stream is not None else None)
+    if st != SGN_OK:
+        raise SgnError(st, "adam")
 
 
 def selftest_mfma(prec, a, b, out, stream=None):
