@@ -269,6 +269,25 @@ sgn_status sgn_gnn_backward(sgn_ctx ctx, const float* d_w, const float* d_gcorr_
 sgn_status sgn_adam(int64_t n, float* d_w, const float* d_g, float* d_m, float* d_v, float lr, float beta1,
                     float beta2, float eps, int step, void* stream);
 
+/* Use the network with weights d_w (caller-owned, device; NULL to stop):
+ * every sgn_solve_minres (and sgn_step with SGN_MINRES_LEARNED) first
+ * evaluates it for the move from the reference factor's state (the (x, p) of
+ * the assembly that sgn_factor factorised) to the currently assembled state
+ * and uses its corrections; sgn_pc_apply / sgn_pc_grad then read them too.
+ * sgn_set_pc_correction replaces this with fixed corrections. */
+sgn_status sgn_set_pc_weights(sgn_ctx ctx, const float* d_w);
+/* Training loss of the network for the reference factor and the assembled
+ * matrix K: *h_loss = mean over the probes u of |T^2 u - u|^2 / |u|^2 with
+ * T = (R C)^-1 L^-1 P S K S P^T L^-T (R C)^-T, the symmetric matrix similar
+ * to M^-1 K (its spectrum is what MINRES sees; with the reference matrix
+ * itself and no correction T^2 = I).  The symmetric form keeps the loss at the
+ * scale of the spectrum: M^-1 K itself is far from normal because the
+ * restricted pivoting leaves L badly conditioned.  d_gw [n_weights] += the
+ * loss's weight gradient.  d_probes: n_probes vectors of [N] in whitened
+ * coordinates (pivot order), device; Gaussian probes are the intended use. */
+sgn_status sgn_pc_train_loss(sgn_ctx ctx, const float* d_w, const double* d_probes, int n_probes, float* d_gw,
+                             double* h_loss);
+
 /* Sizes of a system: N, nnz of the lower CSR, number of supernodes, factor
  * entries sum(m*s) and dense front flops of one factorisation. */
 sgn_status sgn_get_sizes(sgn_ctx ctx, int which, int64_t* n, int64_t* nnz, int64_t* n_supernodes,

@@ -166,3 +166,32 @@ def grad_complex_step(prob, w, gn, gp, state, idx, h=1e-30):
 def directional_complex_step(prob, w, gn, gp, state, u, h=1e-30):
     """d/de loss_dot(w + e u) at e = 0."""
     return loss_dot(prob, w.astype(np.complex128) + 1j * h * u, gn, gp, *state).imag / h
+
+
+def symmetric_operator(prob: Problem, P, K, corr_node, corr_par):
+    """T = (R C)^-1 L^-1 Q K Q^T L^-T (R C)^-T, Q the map from block order to the equilibrated pivot
+    order (Q v = (S v_new)[piv]); dense, complex-safe in the corrections."""
+    from .precond import correction_matrix
+    cplx = np.iscomplexobj(corr_node) or np.iscomplexobj(corr_par)
+    C = correction_matrix(prob, P.perm, P.starts, P.nodes, corr_node, corr_par,
+                          dtype=np.complex128 if cplx else np.float64)
+    n = K.shape[0]
+    Q = np.zeros((n, n))
+    Q[np.arange(n), P.perm[P.piv]] = P.S[P.piv]
+    F = P.L @ P.R @ C  # M = Q^T F F^T Q in the equilibrated pivot order
+    Kp = Q @ K @ Q.T
+    return np.linalg.solve(F, np.linalg.solve(F, Kp.T).T)
+
+
+def train_loss(prob: Problem, P, K, w, state, probes):
+    """Mean over probes u (whitened pivot coordinates) of sum(T^2 u - u)^2 / |u|^2 with T the
+    symmetric form of the preconditioned matrix (symmetric_operator) and the network's corrections
+    for `state` (x_ref, p_ref, x, p, ell).  Plain squares (no conjugation) keep it holomorphic in
+    the weights, for the complex step."""
+    cn, cp = forward(prob, w, *state)
+    T = symmetric_operator(prob, P, K, cn, cp)
+    total = 0.0
+    for u in probes:
+        e = T @ (T @ u) - u
+        total = total + np.sum(e * e) / np.sum(u * u)
+    return total / len(probes)

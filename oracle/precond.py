@@ -214,8 +214,11 @@ class Preconditioner:
 
     def apply(self, v: np.ndarray, corr_node=None, corr_par=None) -> np.ndarray:
         """M^-1 v = S P^T L^-T B^-1 L^-1 P S v (user order), by triangular and block solves: restricted
-        pivoting leaves L badly conditioned, so the dense M is not inverted directly.  v may be [N] or [N, k]."""
-        C = correction_matrix(self.prob, self.perm, self.starts, self.nodes, corr_node, corr_par)
+        pivoting leaves L badly conditioned, so the dense M is not inverted directly.  v may be [N] or [N, k];
+        complex corrections or v propagate (complex step)."""
+        cplx = np.iscomplexobj(corr_node) or np.iscomplexobj(corr_par)
+        C = correction_matrix(self.prob, self.perm, self.starts, self.nodes, corr_node, corr_par,
+                              dtype=np.complex128 if cplx else np.float64)
         B = self.R @ C @ C.T @ self.R.T
         vv = v.reshape(v.shape[0], -1)
         y = self.forward(vv)

@@ -164,6 +164,16 @@ struct sgn_ctx_s {
     float *dec, *emb, *dh[2], *de[2], *dz, *dx, *dagg, *ddec, *demb, *part;
   } g{};
   bool gnn_fwd_done = false;
+  const float* pc_weights = nullptr;  // caller-owned network weights (null: corrections as set)
+  bool use_own = false;               // the preconditioner reads own_cn / own_cp
+  float* own_cn = nullptr;            // corrections computed by the network
+  float* own_cp = nullptr;
+  float* g_cn = nullptr;              // their gradients (training loss)
+  float* g_cp = nullptr;
+  double* d_x_asm = nullptr;          // state of the last SGN assembly
+  double* d_p_asm = nullptr;
+  double* d_x_fac = nullptr;          // state of the reference factor
+  double* d_p_fac = nullptr;
   const float* corr_node = nullptr;  // caller-owned raw preconditioner corrections (null: none)
   const float* corr_par = nullptr;
   bool kx_valid = false;
@@ -334,6 +344,14 @@ size_t layout(sgn_ctx c, char* base) {
     g.demb = L.take<float>(G.param_kind == 0 ? ne * H : 0);
     g.part = L.take<float>((int64_t)wgrad_parts(rows) * (kGnnMaxK + 1) * H);
   }
+  c->own_cn = L.take<float>((int64_t)A.mesh.n_nodes * c->G.tri);
+  c->own_cp = L.take<float>(np);
+  c->g_cn = L.take<float>((int64_t)A.mesh.n_nodes * c->G.tri);
+  c->g_cp = L.take<float>(np);
+  c->d_x_asm = L.take<double>(nx);
+  c->d_p_asm = L.take<double>(np);
+  c->d_x_fac = L.take<double>(nx);
+  c->d_p_fac = L.take<double>(np);
   c->d_elems = L.take<int32_t>(ne * nv);
   c->d_efdof = L.take<int32_t>(ne * nv);
   c->d_rest = L.take<double>(A.mesh.rest.size());
@@ -626,6 +644,7 @@ sgn_status bwd_sweep_t(sgn_ctx c, int si, double* x_new, const double* wd) {
   SolveArgs a = solve_args(c, si);
   a.wd = wd;
   const T* front = reinterpret_cast<const T*>(D.front);
+  HIPCHK(hipMemsetAsync(D.solve_ctr, 0, 2 * (size_t)S.nlevels * sizeof(int), st));  // tickets start at 0
   int* err = c->d_cnt + 12;
   const int e_bwd = ++D.epoch;
   for (int L = S.nlevels - 1; L >= 0; --L) {
@@ -671,8 +690,8 @@ PcArgs pc_args(sgn_ctx c) {
   a.dpiv = D.dpiv;
   a.epiv = D.epiv;
   a.pivtype = D.pivtype;
-  a.corr_node = c->corr_node;
-  a.corr_par = c->corr_par;
+  a.corr_node = c->use_own ? c->own_cn : c->corr_node;
+  a.corr_par = c->use_own ? c->own_cp : c->corr_par;
   return a;
 }
 
@@ -1030,6 +1049,8 @@ sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rh
   }
   c->sgn_assembled = true;
   c->sys[0].current = false;
+  HIPCHK(hipMemcpyAsync(c->d_x_asm, x, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_p_asm, p, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (obj) TRY(objective_value(c, x, p, obj));
   if (rhs_old || grad) {
     const int64_t nt = (int64_t)c->target_dof.size();
@@ -1088,6 +1109,8 @@ sgn_status check_ready(sgn_ctx c) {
 
 sgn_status sgn_factor_impl(sgn_ctx c, sgn_factor_info* info) {
   if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "sgn_factor before sgn_assemble");
+  HIPCHK(hipMemcpyAsync(c->d_x_fac, c->d_x_asm, c->A.mesh.n_x * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_p_fac, c->d_p_asm, c->A.mesh.n_p * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   sgn_factor_info fi{};
   const double tol = c->sys[0].prec ? 1e-12 : 1e-14;
   TRY(factor_dispatch(c, 0, tol, &fi));
@@ -1117,6 +1140,9 @@ sgn_status sgn_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_i
   return SGN_OK;
 }
 
+sgn_status gnn_forward_impl(sgn_ctx c, const float* w, const double* x_ref, const double* p_ref, const double* x,
+                            const double* p, float* cn, float* cp);
+
 // MINRES with the reference factor's preconditioner; on stagnation, on max_minres
 // iterations, or without a reference factor: exact factorisation of the current
 // matrix (which becomes the new reference) and the refined direct solve.
@@ -1130,6 +1156,10 @@ sgn_status minres_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solv
   sgn_solve_info si{};
   bool conv = false;
   if (D.factored) {
+    if (c->pc_weights) {  // corrections for the move from the reference state to the assembled one
+      TRY(gnn_forward_impl(c, c->pc_weights, c->d_x_fac, c->d_p_fac, c->d_x_asm, c->d_p_asm, c->own_cn, c->own_cp));
+      c->use_own = true;
+    }
     HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
     int it = 0;
     double rel = 1.0;
@@ -1316,6 +1346,65 @@ sgn_status gnn_backward_impl(sgn_ctx c, const float* w, const float* gcn, const 
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
+  return SGN_OK;
+}
+
+// out = T v (flat, pivot order) with T = (R C)^-1 L^-1 P S K S P^T L^-T (R C)^-T, the symmetric
+// matrix similar to M^-1 K; z, q are new-order work vectors
+sgn_status t_apply(sgn_ctx c, const PcArgs& pa, const double* v, double* out, double* z, double* q) {
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  launch_pc_half_bwd(pa, v, D.pc_w, c->stream);
+  TRY(bwd_sweep(c, 0, z, D.pc_w));
+  scale_vec(c, N, D.scale, z, z);
+  launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, z, q, c->stream);
+  scale_vec(c, N, D.scale, q, D.sv);
+  TRY(fwd_sweep(c, 0, D.sv));
+  launch_pc_half_fwd(pa, D.tp, out, c->stream);
+  return SGN_OK;
+}
+
+// Training loss of the network: mean over probes u of |T^2 u - u|^2 / |u|^2, T the symmetric form of
+// the preconditioned matrix (same spectrum as M^-1 K; zero when the spectrum is {+1, -1}), with the
+// network's corrections for the move from the reference state to the assembled one; its weight
+// gradient is added to gw.  With a = T u, b = T a, e = b - u, f = T e, g = T f:
+//   dl = (2/|u|^2) [e^T dT a + f^T dT u].
+sgn_status pc_train_loss_impl(sgn_ctx c, const float* w, const double* probes, int nprobe, float* gw, double* loss) {
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  hipStream_t st = c->stream;
+  TRY(gnn_forward_impl(c, w, c->d_x_fac, c->d_p_fac, c->d_x_asm, c->d_p_asm, c->own_cn, c->own_cp));
+  c->use_own = true;
+  launch_fill_f32((int64_t)c->A.mesh.n_nodes * c->G.tri, 0.0f, c->g_cn, st);
+  launch_fill_f32(c->A.mesh.n_p, 0.0f, c->g_cp, st);
+  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), st));
+  double *a = D.mr[0], *b = D.mr[1], *e = D.mr[2], *f = D.mr[3], *g = D.mr[4], *z = D.mr[5], *q = D.mr[6];
+  const PcArgs pa = pc_args(c);
+  const double wt = 1.0 / (double)nprobe;
+  double total = 0.0;
+  for (int k = 0; k < nprobe; ++k) {
+    const double* u = probes + (int64_t)k * N;
+    TRY(t_apply(c, pa, u, a, z, q));
+    TRY(t_apply(c, pa, a, b, z, q));
+    launch_lincomb3(N, 1.0, b, -1.0, u, 0.0, nullptr, e, st);
+    TRY(t_apply(c, pa, e, f, z, q));
+    TRY(t_apply(c, pa, f, g, z, q));
+    dev_dot(c, N, u, u, 24);
+    dev_dot(c, N, e, e, 25);
+    double h[2];
+    TRY(read_scalars(c, 24, 2, h));
+    if (!(h[0] > 0.0)) return fail(c, SGN_E_ARG, "zero probe vector");
+    total += h[1] / h[0];
+    const double s = 2.0 / h[0] * wt;
+    launch_pc_sym_grad(pa, e, b, a, f, s, c->g_cn, c->g_cp, st);
+    launch_pc_sym_grad(pa, f, a, u, g, s, c->g_cn, c->g_cp, st);
+  }
+  TRY(gnn_backward_impl(c, w, c->g_cn, c->g_cp, gw));
+  int timeout = 0;
+  HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (timeout) return fail(c, SGN_E_HIP, "a pipelined triangular solve timed out waiting for a panel");
+  *loss = total * wt;
   return SGN_OK;
 }
 
@@ -1642,6 +1731,8 @@ sgn_status sgn_set_pc_correction(sgn_ctx c, const float* d_corr_node, const floa
   TRY(check_ready(c));
   c->corr_node = d_corr_node;
   c->corr_par = d_corr_par;
+  c->pc_weights = nullptr;
+  c->use_own = false;
   return SGN_OK;
 }
 
@@ -1744,6 +1835,24 @@ sgn_status sgn_adam(int64_t n, float* d_w, const float* d_g, float* d_m, float* 
   if (hipGetLastError() != hipSuccess) return SGN_E_HIP;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SGN_E_HIP;
   return SGN_OK;
+}
+
+sgn_status sgn_set_pc_weights(sgn_ctx c, const float* d_w) {
+  TRY(check_ready(c));
+  c->pc_weights = d_w;
+  c->use_own = false;
+  return SGN_OK;
+}
+
+sgn_status sgn_pc_train_loss(sgn_ctx c, const float* d_w, const double* d_probes, int n_probes, float* d_gw,
+                             double* h_loss) {
+  TRY(pc_ready(c));
+  if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "sgn_pc_train_loss before sgn_assemble");
+  if (!d_w || !d_probes || n_probes < 1 || !d_gw || !h_loss) return fail(c, SGN_E_ARG, "invalid argument");
+  const bool keep = c->use_own;
+  sgn_status s = pc_train_loss_impl(c, d_w, d_probes, n_probes, d_gw, h_loss);
+  c->use_own = keep && c->pc_weights;
+  return s;
 }
 
 sgn_status sgn_get_sizes(sgn_ctx c, int which, int64_t* n, int64_t* nnz, int64_t* nsn, int64_t* fe, double* fl) {

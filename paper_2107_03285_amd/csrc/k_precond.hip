@@ -191,6 +191,83 @@ __global__ void __launch_bounds__(128) k_pc_grad(PcArgs a, const double* __restr
     }
 }
 
+// Halves of B^-1 = (R C)^-T (R C)^-1 for the symmetric form of the preconditioned matrix,
+// T = (R C)^-1 L^-1 P S K S P^T L^-T (R C)^-T, which is similar to M^-1 K:
+//   k_pc_half_fwd:  u = C^-1 R^-1 y   (y from the forward solve's vectors, u flat in pivot order)
+//   k_pc_half_bwd:  w = R^-T C^-T v   (flat to flat; w feeds the backward solve)
+__global__ void __launch_bounds__(128) k_pc_half_fwd(PcArgs a, const double* __restrict__ tp, double* __restrict__ u) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.ngroups) return;
+  const int g0 = a.grp_ptr[q], n = a.grp_ptr[q + 1] - g0;
+  const int nb = 2 * a.dim, nown = n - nb;
+  const double* yv = tp + a.grp_vec[q];
+  double y[64];
+  for (int k = 0; k < n; ++k) y[k] = yv[k];
+  whiten(a.dpiv, a.epiv, a.pivtype, g0, n, y, true);
+  Corr C;
+  double ps[64];
+  load_corr(a.corr_node, a.corr_par, a.perm, a.nx, g0, nown, nb, a.grp_node[q], ps, C);
+  for (int k = 0; k < nown; ++k) y[k] /= ps[k];
+  blk_lower_solve(C, y + nown);
+  for (int k = 0; k < n; ++k) u[g0 + k] = y[k];
+}
+
+__global__ void __launch_bounds__(128) k_pc_half_bwd(PcArgs a, const double* __restrict__ v, double* __restrict__ w) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.ngroups) return;
+  const int g0 = a.grp_ptr[q], n = a.grp_ptr[q + 1] - g0;
+  const int nb = 2 * a.dim, nown = n - nb;
+  double y[64];
+  for (int k = 0; k < n; ++k) y[k] = v[g0 + k];
+  Corr C;
+  double ps[64];
+  load_corr(a.corr_node, a.corr_par, a.perm, a.nx, g0, nown, nb, a.grp_node[q], ps, C);
+  for (int k = 0; k < nown; ++k) y[k] /= ps[k];
+  blk_upper_solve(C, y + nown);
+  whiten(a.dpiv, a.epiv, a.pivtype, g0, n, y, false);
+  for (int k = 0; k < n; ++k) w[g0 + k] = y[k];
+}
+
+// gradient of x^T T y with respect to the raw corrections (x, y, Tx, Ty flat, whitened, pivot order),
+// scaled by `weight` and added to gn / gp.  With T = C^-1 A C^-T:
+//   d(x^T T y)/dC_ij = -[(C^-T x)_i (T y)_j + (C^-T y)_i (T x)_j]  on the block's lower triangle,
+// and the same with the 1x1 scale s on owned-parameter positions; d/dr = C_ii d/dC_ii on diagonals.
+__global__ void __launch_bounds__(128) k_pc_sym_grad(PcArgs a, const double* __restrict__ x,
+                                                     const double* __restrict__ ty, const double* __restrict__ y,
+                                                     const double* __restrict__ tx, double weight,
+                                                     float* __restrict__ gn, float* __restrict__ gp) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.ngroups) return;
+  const int g0 = a.grp_ptr[q], n = a.grp_ptr[q + 1] - g0;
+  const int nb = 2 * a.dim, nown = n - nb;
+  const int node = a.grp_node[q];
+  Corr C;
+  double ps[64];
+  load_corr(a.corr_node, a.corr_par, a.perm, a.nx, g0, nown, nb, node, ps, C);
+  for (int k = 0; k < nown; ++k) {
+    const int i = g0 + k;
+    const double g = -(x[i] / ps[k] * ty[i] + y[i] / ps[k] * tx[i]) * ps[k];
+    if (gp) gp[a.perm[i] - a.nx] += (float)(weight * g);
+  }
+  if (!gn) return;
+  const int b0 = g0 + nown;
+  double cx[6], cy[6];
+  for (int i = 0; i < nb; ++i) {
+    cx[i] = x[b0 + i];
+    cy[i] = y[b0 + i];
+  }
+  blk_upper_solve(C, cx);  // C^-T x
+  blk_upper_solve(C, cy);
+  const int tri = nb * (nb + 1) / 2;
+  float* g = gn + (int64_t)node * tri;
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = -(cx[i] * ty[b0 + j] + cy[i] * tx[b0 + j]);
+      if (i == j) v *= C.blk[i][i];
+      g[i * (i + 1) / 2 + j] += (float)(weight * v);
+    }
+}
+
 __global__ void k_lincomb3(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
                            double c, const double* __restrict__ z, double* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -212,6 +289,20 @@ void launch_pc_block(const PcArgs& a, const double* tp, double* ysave, double* w
 void launch_pc_grad(const PcArgs& a, const double* ya, const double* yb, double weight, float* gn, float* gp,
                     hipStream_t s) {
   if (a.ngroups > 0) k_pc_grad<<<(unsigned)((a.ngroups + 127) / 128), 128, 0, s>>>(a, ya, yb, weight, gn, gp);
+}
+
+void launch_pc_half_fwd(const PcArgs& a, const double* tp, double* u, hipStream_t s) {
+  if (a.ngroups > 0) k_pc_half_fwd<<<(unsigned)((a.ngroups + 127) / 128), 128, 0, s>>>(a, tp, u);
+}
+
+void launch_pc_half_bwd(const PcArgs& a, const double* v, double* w, hipStream_t s) {
+  if (a.ngroups > 0) k_pc_half_bwd<<<(unsigned)((a.ngroups + 127) / 128), 128, 0, s>>>(a, v, w);
+}
+
+void launch_pc_sym_grad(const PcArgs& a, const double* x, const double* ty, const double* y, const double* tx,
+                        double weight, float* gn, float* gp, hipStream_t s) {
+  if (a.ngroups > 0)
+    k_pc_sym_grad<<<(unsigned)((a.ngroups + 127) / 128), 128, 0, s>>>(a, x, ty, y, tx, weight, gn, gp);
 }
 
 void launch_lincomb3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,

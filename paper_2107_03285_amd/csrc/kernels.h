@@ -146,6 +146,12 @@ void launch_pc_block(const PcArgs& a, const double* tp, double* ysave, double* w
 // gn, gp += weight * d(ya^T B^-1 yb)/d(raw corrections)
 void launch_pc_grad(const PcArgs& a, const double* ya, const double* yb, double weight, float* gn, float* gp,
                     hipStream_t s);
+// halves of B^-1 = (R C)^-T (R C)^-1: u = C^-1 R^-1 y (y from tp), w = R^-T C^-T v (flat, pivot order)
+void launch_pc_half_fwd(const PcArgs& a, const double* tp, double* u, hipStream_t s);
+void launch_pc_half_bwd(const PcArgs& a, const double* v, double* w, hipStream_t s);
+// gn, gp += weight * d(x^T T y)/d(raw corrections), T = (RC)^-1 L^-1 P S K S P^T L^-T (RC)^-T
+void launch_pc_sym_grad(const PcArgs& a, const double* x, const double* ty, const double* y, const double* tx,
+                        double weight, float* gn, float* gp, hipStream_t s);
 // out = a x + b y + c z (y, z may be null)
 void launch_lincomb3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,
                      double* out, hipStream_t s);

@@ -31,7 +31,7 @@ EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_w
            "sgn_get_symbolic", "sgn_get_values", "sgn_get_stats", "sgn_selftest_mfma", "sgn_last_error",
            "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
            "sgn_solve_minres", "sgn_gnn_num_weights", "sgn_gnn_init", "sgn_gnn_forward", "sgn_gnn_backward",
-           "sgn_adam"]
+           "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss"]
 
 
 class sgn_problem(C.Structure):
@@ -127,6 +127,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_gnn_init": (C.c_int, [vp, vp, C.c_uint64]),
         "sgn_gnn_forward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "sgn_gnn_backward": (C.c_int, [vp, vp, vp, vp, vp]),
+        "sgn_set_pc_weights": (C.c_int, [vp, vp]),
+        "sgn_pc_train_loss": (C.c_int, [vp, vp, vp, C.c_int, vp, dp]),
         "sgn_adam": (C.c_int, [C.c_int64, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
                                vp]),
     }
@@ -323,6 +325,17 @@ class Context:
     def gnn_backward(self, w, gcorr_node, gcorr_par, gw):
         self._check(self.lib.sgn_gnn_backward(self.h, _dev_ptr(w), _dev_ptr(gcorr_node), _dev_ptr(gcorr_par),
                                               _dev_ptr(gw)))
+
+    def set_pc_weights(self, w):
+        self._keep["pc_weights"] = w
+        self._check(self.lib.sgn_set_pc_weights(self.h, _dev_ptr(w)))
+
+    def pc_train_loss(self, w, probes, gw) -> float:
+        """probes: device float64 tensor [k, N]; gw += gradient; returns the mean loss."""
+        loss = C.c_double()
+        self._check(self.lib.sgn_pc_train_loss(self.h, _dev_ptr(w), _dev_ptr(probes), int(probes.shape[0]),
+                                               _dev_ptr(gw), C.byref(loss)))
+        return loss.value
 
     def step(self, p, x):
         info = sgn_step_info()

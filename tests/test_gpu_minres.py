@@ -233,3 +233,36 @@ def test_outer_iterations_with_minres_match_direct():
     assert t1[0][2] == 1  # no reference before the first step
     assert np.allclose([f for _, f, _ in t0], [f for _, f, _ in t1], rtol=1e-8)
     assert np.linalg.norm(p1 - p0) <= 1e-7 * np.linalg.norm(p0)
+
+
+def test_training_loss_and_gradient_match_oracle():
+    """The library's training loss and its weight gradient against the oracle (complex step)."""
+    from oracle import gnn as G
+    prob, p, x, K, P, ctx = _factored("loge3x2x2")
+    p1 = p + 0.01 * np.random.default_rng(9).standard_normal(prob.n_p)
+    x1, info = D.equilibrium(prob, p1, x0=x, rtol=1e-11)
+    assert info.converged
+    K1 = PC.sgn_matrix(prob, x1, p1)
+    ctx.assemble(_cuda(x1), _cuda(p1))
+    rng = np.random.default_rng(21)
+    w = (0.05 * rng.standard_normal(ctx.gnn_num_weights())).astype(np.float32)
+    probes = rng.standard_normal((2, K.shape[0]))
+    wd = _cuda(w, torch.float32)
+    gw = torch.zeros_like(wd)
+    loss = ctx.pc_train_loss(wd, _cuda(probes), gw)
+    state = (x, p, x1, p1, prob.length_scale)
+    ref = G.train_loss(prob, P, K1, w.astype(np.float64), state, probes)
+    assert abs(loss - ref) <= 1e-3 * ref
+    u = rng.standard_normal(w.size)
+    h = 1e-30
+    dd = G.train_loss(prob, P, K1, w.astype(np.float64) + 1j * h * u, state, probes).imag / h
+    g = _host(gw)
+    assert abs(g @ u - dd) <= 2e-3 * np.sum(np.abs(g * u)) + 1e-3 * abs(dd)
+    # the network's corrections drive MINRES when the weights are set
+    ctx.set_pc_weights(wd)
+    b = rng.standard_normal(K.shape[0])
+    sol = torch.zeros(K.shape[0], dtype=torch.float64, device="cuda")
+    info = ctx.solve_minres(_cuda(b), sol)
+    assert info.rel_res <= 1e-10
+    ref_sol = _dense_solve(K1, b)
+    assert np.linalg.norm(_host(sol) - ref_sol) <= 1e-7 * np.linalg.norm(ref_sol)
