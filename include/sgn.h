@@ -277,16 +277,20 @@ sgn_status sgn_adam(int64_t n, float* d_w, const float* d_g, float* d_m, float* 
  * sgn_set_pc_correction replaces this with fixed corrections. */
 sgn_status sgn_set_pc_weights(sgn_ctx ctx, const float* d_w);
 /* Training loss of the network for the reference factor and the assembled
- * matrix K: *h_loss = mean over the probes u of |T^2 u - u|^2 / |u|^2 with
- * T = (R C)^-1 L^-1 P S K S P^T L^-T (R C)^-T, the symmetric matrix similar
- * to M^-1 K (its spectrum is what MINRES sees; with the reference matrix
- * itself and no correction T^2 = I).  The symmetric form keeps the loss at the
- * scale of the spectrum: M^-1 K itself is far from normal because the
- * restricted pivoting leaves L badly conditioned.  d_gw [n_weights] += the
- * loss's weight gradient.  d_probes: n_probes vectors of [N] in whitened
- * coordinates (pivot order), device; Gaussian probes are the intended use. */
-sgn_status sgn_pc_train_loss(sgn_ctx ctx, const float* d_w, const double* d_probes, int n_probes, float* d_gw,
-                             double* h_loss);
+ * matrix K: *h_loss = mean over the probes u of
+ *   min_gamma |gamma T^2 u - u|^2 / |u|^2 = 1 - (u^T T^2 u)^2 / (|u|^2 |T^2 u|^2)
+ * with T = (R C)^-1 L^-1 P S K S P^T L^-T (R C)^-T, the symmetric matrix
+ * similar to M^-1 K (its spectrum is what MINRES sees; with the reference
+ * matrix itself and no correction T^2 = I).  The symmetric form keeps the
+ * loss at the scale of the spectrum (M^-1 K itself is far from normal
+ * because the restricted pivoting leaves L badly conditioned), and the free
+ * gamma makes it blind to a scaling of M, as MINRES is.  d_gw [n_weights] +=
+ * the loss's weight gradient.  d_probes: n_probes vectors of [N] in whitened
+ * coordinates (pivot order), device; Gaussian probes are the intended use.
+ * log_form = 1 adds the gradient of log(loss) instead (samples whose loss
+ * spans many decades then weigh alike); *h_loss is the loss either way. */
+sgn_status sgn_pc_train_loss(sgn_ctx ctx, const float* d_w, const double* d_probes, int n_probes, int log_form,
+                             float* d_gw, double* h_loss);
 
 /* Sizes of a system: N, nnz of the lower CSR, number of supernodes, factor
  * entries sum(m*s) and dense front flops of one factorisation. */

@@ -184,14 +184,17 @@ def symmetric_operator(prob: Problem, P, K, corr_node, corr_par):
 
 
 def train_loss(prob: Problem, P, K, w, state, probes):
-    """Mean over probes u (whitened pivot coordinates) of sum(T^2 u - u)^2 / |u|^2 with T the
-    symmetric form of the preconditioned matrix (symmetric_operator) and the network's corrections
-    for `state` (x_ref, p_ref, x, p, ell).  Plain squares (no conjugation) keep it holomorphic in
-    the weights, for the complex step."""
+    """Mean over probes u (whitened pivot coordinates) of min_gamma |gamma T^2 u - u|^2 / |u|^2 with T
+    the symmetric form of the preconditioned matrix (symmetric_operator) and the network's
+    corrections for `state` (x_ref, p_ref, x, p, ell).  The minimising gamma = u^T b / b^T b
+    (b = T^2 u) is substituted.  Plain products (no conjugation) keep it holomorphic in the weights,
+    for the complex step."""
     cn, cp = forward(prob, w, *state)
     T = symmetric_operator(prob, P, K, cn, cp)
     total = 0.0
     for u in probes:
-        e = T @ (T @ u) - u
+        b = T @ (T @ u)
+        gam = np.sum(u * b) / np.sum(b * b)
+        e = gam * b - u
         total = total + np.sum(e * e) / np.sum(u * u)
     return total / len(probes)

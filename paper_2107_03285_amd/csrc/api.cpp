@@ -1364,12 +1364,15 @@ sgn_status t_apply(sgn_ctx c, const PcArgs& pa, const double* v, double* out, do
   return SGN_OK;
 }
 
-// Training loss of the network: mean over probes u of |T^2 u - u|^2 / |u|^2, T the symmetric form of
-// the preconditioned matrix (same spectrum as M^-1 K; zero when the spectrum is {+1, -1}), with the
-// network's corrections for the move from the reference state to the assembled one; its weight
-// gradient is added to gw.  With a = T u, b = T a, e = b - u, f = T e, g = T f:
+// Training loss of the network: mean over probes u of min_gamma |gamma T^2 u - u|^2 / |u|^2, T the
+// symmetric form of the preconditioned matrix (same spectrum as M^-1 K), with the network's
+// corrections for the move from the reference state to the assembled one.  It vanishes when T^2 is
+// a multiple of I (spectrum {+c, -c}), and it does not change when M is scaled, as MINRES does not:
+// without the free gamma, inflating M (T -> 0) would be a spurious minimum of loss 1.  With a = T u,
+// b = T a, gamma = u^T b / b^T b, e = gamma (gamma b - u), f = T e, g = T f (envelope theorem):
 //   dl = (2/|u|^2) [e^T dT a + f^T dT u].
-sgn_status pc_train_loss_impl(sgn_ctx c, const float* w, const double* probes, int nprobe, float* gw, double* loss) {
+sgn_status pc_train_loss_impl(sgn_ctx c, const float* w, const double* probes, int nprobe, int log_form, float* gw,
+                              double* loss) {
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;
   hipStream_t st = c->stream;
@@ -1386,18 +1389,26 @@ sgn_status pc_train_loss_impl(sgn_ctx c, const float* w, const double* probes, i
     const double* u = probes + (int64_t)k * N;
     TRY(t_apply(c, pa, u, a, z, q));
     TRY(t_apply(c, pa, a, b, z, q));
-    launch_lincomb3(N, 1.0, b, -1.0, u, 0.0, nullptr, e, st);
+    dev_dot(c, N, u, u, 24);
+    dev_dot(c, N, u, b, 25);
+    dev_dot(c, N, b, b, 26);
+    double h[3];
+    TRY(read_scalars(c, 24, 3, h));
+    if (!(h[0] > 0.0)) return fail(c, SGN_E_ARG, "zero probe vector");
+    const double gam = h[2] > 0.0 ? h[1] / h[2] : 0.0;
+    // |gamma b - u|^2 = |u|^2 - (u^T b)^2 / |b|^2
+    total += h[2] > 0.0 ? std::max(0.0, 1.0 - h[1] * h[1] / (h[0] * h[2])) : 1.0;
+    launch_lincomb3(N, gam * gam, b, -gam, u, 0.0, nullptr, e, st);
     TRY(t_apply(c, pa, e, f, z, q));
     TRY(t_apply(c, pa, f, g, z, q));
-    dev_dot(c, N, u, u, 24);
-    dev_dot(c, N, e, e, 25);
-    double h[2];
-    TRY(read_scalars(c, 24, 2, h));
-    if (!(h[0] > 0.0)) return fail(c, SGN_E_ARG, "zero probe vector");
-    total += h[1] / h[0];
     const double s = 2.0 / h[0] * wt;
     launch_pc_sym_grad(pa, e, b, a, f, s, c->g_cn, c->g_cp, st);
     launch_pc_sym_grad(pa, f, a, u, g, s, c->g_cn, c->g_cp, st);
+  }
+  if (log_form && total > 0.0) {  // gradient of log(loss): scale the correction gradients by 1/loss
+    const float sc = (float)(1.0 / (total * wt));
+    launch_scale_f32((int64_t)c->A.mesh.n_nodes * c->G.tri, sc, c->g_cn, st);
+    launch_scale_f32(c->A.mesh.n_p, sc, c->g_cp, st);
   }
   TRY(gnn_backward_impl(c, w, c->g_cn, c->g_cp, gw));
   int timeout = 0;
@@ -1844,13 +1855,13 @@ sgn_status sgn_set_pc_weights(sgn_ctx c, const float* d_w) {
   return SGN_OK;
 }
 
-sgn_status sgn_pc_train_loss(sgn_ctx c, const float* d_w, const double* d_probes, int n_probes, float* d_gw,
-                             double* h_loss) {
+sgn_status sgn_pc_train_loss(sgn_ctx c, const float* d_w, const double* d_probes, int n_probes, int log_form,
+                             float* d_gw, double* h_loss) {
   TRY(pc_ready(c));
   if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "sgn_pc_train_loss before sgn_assemble");
   if (!d_w || !d_probes || n_probes < 1 || !d_gw || !h_loss) return fail(c, SGN_E_ARG, "invalid argument");
   const bool keep = c->use_own;
-  sgn_status s = pc_train_loss_impl(c, d_w, d_probes, n_probes, d_gw, h_loss);
+  sgn_status s = pc_train_loss_impl(c, d_w, d_probes, n_probes, log_form, d_gw, h_loss);
   c->use_own = keep && c->pc_weights;
   return s;
 }

@@ -245,6 +245,11 @@ __global__ void k_add_f32(int64_t n, const float* __restrict__ src, float* __res
     dst[i] += src[i];
 }
 
+__global__ void k_scale_f32(int64_t n, float a, float* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] *= a;
+}
+
 __global__ void k_fill_f32(int64_t n, float v, float* __restrict__ dst) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = v;
@@ -335,6 +340,10 @@ void launch_split_bwd(int64_t n_nodes, int tri, int nout, int d, int per_node_pa
 
 void launch_add_f32(int64_t n, const float* src, float* dst, hipStream_t s) {
   if (n > 0) k_add_f32<<<blocks_for(n, 256, 8192), 256, 0, s>>>(n, src, dst);
+}
+
+void launch_scale_f32(int64_t n, float a, float* dst, hipStream_t s) {
+  if (n > 0) k_scale_f32<<<blocks_for(n, 256, 8192), 256, 0, s>>>(n, a, dst);
 }
 
 void launch_fill_f32(int64_t n, float v, float* dst, hipStream_t s) {

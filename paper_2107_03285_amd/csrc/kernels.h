@@ -210,6 +210,7 @@ void launch_split_bwd(int64_t n_nodes, int tri, int nout, int d, int per_node_pa
                       const float* gcn, const float* gcp, float* ddec, hipStream_t s);
 void launch_add_f32(int64_t n, const float* src, float* dst, hipStream_t s);
 void launch_fill_f32(int64_t n, float v, float* dst, hipStream_t s);
+void launch_scale_f32(int64_t n, float a, float* dst, hipStream_t s);
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                  int t, hipStream_t s);
 

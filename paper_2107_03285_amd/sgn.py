@@ -128,7 +128,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_gnn_forward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "sgn_gnn_backward": (C.c_int, [vp, vp, vp, vp, vp]),
         "sgn_set_pc_weights": (C.c_int, [vp, vp]),
-        "sgn_pc_train_loss": (C.c_int, [vp, vp, vp, C.c_int, vp, dp]),
+        "sgn_pc_train_loss": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp, dp]),
         "sgn_adam": (C.c_int, [C.c_int64, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
                                vp]),
     }
@@ -330,11 +330,11 @@ class Context:
         self._keep["pc_weights"] = w
         self._check(self.lib.sgn_set_pc_weights(self.h, _dev_ptr(w)))
 
-    def pc_train_loss(self, w, probes, gw) -> float:
-        """probes: device float64 tensor [k, N]; gw += gradient; returns the mean loss."""
+    def pc_train_loss(self, w, probes, gw, log_form=False) -> float:
+        """probes: device float64 tensor [k, N]; gw += gradient (of log(loss) with log_form); returns the mean loss."""
         loss = C.c_double()
         self._check(self.lib.sgn_pc_train_loss(self.h, _dev_ptr(w), _dev_ptr(probes), int(probes.shape[0]),
-                                               _dev_ptr(gw), C.byref(loss)))
+                                               int(bool(log_form)), _dev_ptr(gw), C.byref(loss)))
         return loss.value
 
     def step(self, p, x):
