@@ -96,6 +96,14 @@ typedef struct {
   const double* target_val;     /* [n_targets] (may be NULL until sgn_set_targets) */
   double target_w, length_scale, reg_mu;
   const double* p_ref;          /* [n_p] Tikhonov reference */
+  /* Batches of independent problems: n_components > 1 declares the mesh a
+   * disjoint union whose component c owns the nodes [component_ptr[c],
+   * component_ptr[c+1]) (and only elements among them); node_grid then holds
+   * each component's own grid coordinates.  Every component is ordered on its
+   * own, so the elimination tree is a forest and each level of the supernodal
+   * schedule covers the same level of all components.  0 or 1: one problem. */
+  int n_components;
+  const int32_t* component_ptr; /* [n_components+1], 0 first, n_nodes last */
 } sgn_problem;
 
 typedef struct {
@@ -291,6 +299,22 @@ sgn_status sgn_set_pc_weights(sgn_ctx ctx, const float* d_w);
  * spans many decades then weigh alike); *h_loss is the loss either way. */
 sgn_status sgn_pc_train_loss(sgn_ctx ctx, const float* d_w, const double* d_probes, int n_probes, int log_form,
                              float* d_gw, double* h_loss);
+
+/* One SGN step at (d_x, d_p) as a replayed HIP graph: element kernel and
+ * assembly, the KKT right-hand side [-df/dx; -df/dp; 0] into d_rhs (same dp
+ * as the adjoint form, Appendix A, Theorem 2), supernodal LDL^T, the solve and
+ * exactly n_ir (0..16) refinement sweeps into d_sol ([N], block order), with
+ * the final equilibrated relative residual and a done flag computed on the
+ * device.  The first call (and any call with other pointers or n_ir) captures
+ * the whole sequence once on a context-owned stream; later calls replay it
+ * (the values behind the pointers may change between calls).  No host
+ * synchronisation happens inside; the call waits for the context's stream
+ * first and for the replay at the end.  *h_rel (optional) receives the
+ * residual; SGN_E_REFINE if it exceeds solve_rtol, SGN_E_INVERTED if (x, p)
+ * inverts an element.  Meant for batches of small problems (n_components),
+ * where launch overhead dominates. */
+sgn_status sgn_graph_step(sgn_ctx ctx, const double* d_x, const double* d_p, double* d_rhs, double* d_sol, int n_ir,
+                          double* h_rel);
 
 /* Sizes of a system: N, nnz of the lower CSR, number of supernodes, factor
  * entries sum(m*s) and dense front flops of one factorisation. */

@@ -17,6 +17,8 @@
 #include "../../include/sgn.h"
 #include "gnn.h"
 #include "kernels.h"
+
+static_assert(sgn::kTile == sgn::kUpdTile, "the schedule counts the update kernel's tiles");
 #include "symbolic.h"
 
 using namespace sgn;
@@ -164,6 +166,12 @@ struct sgn_ctx_s {
     float *dec, *emb, *dh[2], *de[2], *dz, *dx, *dagg, *ddec, *demb, *part;
   } g{};
   bool gnn_fwd_done = false;
+  bool capturing = false;             // enqueueing into a graph: no host syncs, flags reset per sweep
+  hipStream_t gstream = nullptr;      // stream of the captured step graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_key[4] = {};      // (x, p, rhs, sol) the graph was captured for
+  int graph_nir = -1;
   const float* pc_weights = nullptr;  // caller-owned network weights (null: corrections as set)
   bool use_own = false;               // the preconditioner reads own_cn / own_cp
   float* own_cn = nullptr;            // corrections computed by the network
@@ -183,6 +191,9 @@ struct sgn_ctx_s {
   std::vector<hipEvent_t> ev_pool;  // per-launch timing events (profile = 1)
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   ~sgn_ctx_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (ev_a) (void)hipEventDestroy(ev_a);
     if (ev_b) (void)hipEventDestroy(ev_b);
@@ -404,7 +415,7 @@ void dev_dot(sgn_ctx c, int64_t n, const double* a, const double* b, int slot, i
 // ------------------------------------------------------------------ element + assembly
 sgn_status run_element(sgn_ctx c, const double* x, const double* p, int mode, int* inverted) {
   const Analysis& A = c->A;
-  HIPCHK(hipMemsetAsync(c->d_cnt + 8, 0, sizeof(int), c->stream));
+  launch_fill_i32(1, 0, c->d_cnt + 8, c->stream);
   ElemArgs ea;
   ea.dim = A.mesh.dim;
   ea.ne = A.mesh.n_elems;
@@ -468,7 +479,7 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   launch_fill_bytes(((int64_t)(S.front_total * sizeof(T)) + 15) / 16 * 16, front, st);
   launch_csr_to_fronts<T>((int64_t)S.colind.size(), D.slot_row, D.colind, D.csr_front_pos, D.vals, D.scale, front,
                           st);
-  HIPCHK(hipMemsetAsync(c->d_cnt, 0, 4 * sizeof(int), st));
+  launch_fill_i32(4, 0, c->d_cnt, st);
   FrontArgs f;
   f.sn_begin = D.sn_begin;
   f.sn_m = D.sn_m;
@@ -536,7 +547,7 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
     c->stats.update_flops = upd_flops;
     c->stats.update_launches = (int64_t)(nev / 2);
   }
-  HIPCHK(hipMemsetAsync(c->d_ull, 0, 4 * sizeof(unsigned long long), st));
+  launch_fill_i32(8, 0, c->d_ull, st);
   launch_inertia(S.N, D.dpiv, D.epiv, D.pivtype, c->d_ull, c->d_part, st);
   HIPCHK(hipGetLastError());
   D.factored = true;
@@ -623,7 +634,8 @@ sgn_status fwd_sweep_t(sgn_ctx c, int si, const double* b_new) {
   hipStream_t st = c->stream;
   const SolveArgs a = solve_args(c, si);
   const T* front = reinterpret_cast<const T*>(D.front);
-  HIPCHK(hipMemsetAsync(D.solve_ctr, 0, 2 * (size_t)S.nlevels * sizeof(int), st));
+  launch_fill_i32(2 * (int64_t)S.nlevels, 0, D.solve_ctr, st);
+  if (c->capturing) launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
   int* err = c->d_cnt + 12;
   const int e_fwd = ++D.epoch;
   for (int L = 0; L < S.nlevels; ++L) {
@@ -644,7 +656,9 @@ sgn_status bwd_sweep_t(sgn_ctx c, int si, double* x_new, const double* wd) {
   SolveArgs a = solve_args(c, si);
   a.wd = wd;
   const T* front = reinterpret_cast<const T*>(D.front);
-  HIPCHK(hipMemsetAsync(D.solve_ctr, 0, 2 * (size_t)S.nlevels * sizeof(int), st));  // tickets start at 0
+  launch_fill_i32(2 * (int64_t)S.nlevels, 0, D.solve_ctr, st);  // tickets start at 0
+  // a replayed graph reuses its epochs: flags from the previous replay must not count as ready
+  if (c->capturing) launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
   int* err = c->d_cnt + 12;
   const int e_bwd = ++D.epoch;
   for (int L = S.nlevels - 1; L >= 0; --L) {
@@ -728,7 +742,7 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
   DevSys& D = c->sys[si];
   const double t0 = now_ms();
-  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+  launch_fill_i32(1, 0, c->d_cnt + 12, c->stream);
   TRY(solve_once(c, si, b_new, z_new));
   scale_vec(c, S.N, D.scale, b_new, D.ir_s);
   dev_dot(c, S.N, D.ir_s, D.ir_s, 1);
@@ -1160,7 +1174,7 @@ sgn_status minres_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solv
       TRY(gnn_forward_impl(c, c->pc_weights, c->d_x_fac, c->d_p_fac, c->d_x_asm, c->d_p_asm, c->own_cn, c->own_cp));
       c->use_own = true;
     }
-    HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+    launch_fill_i32(1, 0, c->d_cnt + 12, c->stream);
     int it = 0;
     double rel = 1.0;
     TRY(minres_new(c, c->d_old2, zn, c->opt.max_minres, 50, &it, &rel, &conv));
@@ -1380,7 +1394,7 @@ sgn_status pc_train_loss_impl(sgn_ctx c, const float* w, const double* probes, i
   c->use_own = true;
   launch_fill_f32((int64_t)c->A.mesh.n_nodes * c->G.tri, 0.0f, c->g_cn, st);
   launch_fill_f32(c->A.mesh.n_p, 0.0f, c->g_cp, st);
-  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), st));
+  launch_fill_i32(1, 0, c->d_cnt + 12, st);
   double *a = D.mr[0], *b = D.mr[1], *e = D.mr[2], *f = D.mr[3], *g = D.mr[4], *z = D.mr[5], *q = D.mr[6];
   const PcArgs pa = pc_args(c);
   const double wt = 1.0 / (double)nprobe;
@@ -1416,6 +1430,69 @@ sgn_status pc_train_loss_impl(sgn_ctx c, const float* w, const double* probes, i
   HIPCHK(hipStreamSynchronize(st));
   if (timeout) return fail(c, SGN_E_HIP, "a pipelined triangular solve timed out waiting for a panel");
   *loss = total * wt;
+  return SGN_OK;
+}
+
+// One SGN step at (x, p) enqueued without host synchronisation, for graph capture: element kernel and
+// SGN assembly, the KKT right-hand side [-df/dx; -df/dp; 0] (same dp as the adjoint form, Appendix A),
+// supernodal LDL^T, the solve and n_ir FP64 refinement sweeps; the final equilibrated relative residual
+// and its done flag (<= solve_rtol) land in d_scal[32], d_scal[33]; inverted elements are counted in
+// d_cnt[8], timed-out waits flagged in d_cnt[12].
+sgn_status enqueue_step(sgn_ctx c, const double* x, const double* p, double* rhs, double* sol, int n_ir) {
+  const Analysis& A = c->A;
+  const System& S = A.sgn;
+  DevSys& D = c->sys[0];
+  const int64_t nx = A.mesh.n_x, np = A.mesh.n_p, N = S.N;
+  hipStream_t st = c->stream;
+  launch_fill_i32(1, 0, c->d_cnt + 8, st);
+  launch_fill_i32(1, 0, c->d_cnt + 12, st);
+  ElemArgs ea;
+  ea.dim = A.mesh.dim;
+  ea.ne = A.mesh.n_elems;
+  ea.param_kind = A.mesh.param_kind;
+  ea.mode = 2;
+  ea.elems = c->d_elems;
+  ea.efdof = c->d_efdof;
+  ea.rest = c->d_rest;
+  ea.x = x;
+  ea.p = p;
+  ea.mu0 = c->mu0;
+  ea.lam0 = c->lam0;
+  ea.ebuf = c->d_ebuf;
+  ea.stride = A.stride;
+  ea.off_grad = A.off_grad;
+  ea.off_kp = A.off_kp;
+  ea.off_energy = A.off_energy;
+  ea.inverted = c->d_cnt + 8;
+  launch_element(ea, st);
+  assemble_sgn(c);
+  launch_fill(nx, 0.0, c->d_fx, st);
+  launch_objective_fx((int64_t)c->target_dof.size(), c->d_tdof, c->d_tval, x, c->target_w / (c->ell * c->ell),
+                      c->d_fx, st);
+  launch_axpby(np, c->mu_reg, p, -c->mu_reg, c->d_pref, c->d_fp, st);
+  launch_axpby(nx, -1.0, c->d_fx, 0.0, nullptr, rhs, st);
+  launch_axpby(np, -1.0, c->d_fp, 0.0, nullptr, rhs + nx, st);
+  launch_fill(nx, 0.0, rhs + nx + np, st);
+  const double tol = D.prec ? 1e-12 : 1e-14;
+  if (D.prec) TRY(factor_system<float>(c, 0, tol));
+  else TRY(factor_system<double>(c, 0, tol));
+  double* b = c->d_old2;
+  double* z = c->d_old;
+  launch_gather_perm(N, D.perm, nullptr, rhs, b, st);
+  TRY(solve_once(c, 0, b, z));
+  for (int k = 0; k < n_ir; ++k) {
+    launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, z, b, D.ir_r, st);
+    TRY(solve_once(c, 0, D.ir_r, D.ir_d));
+    launch_axpby(N, 1.0, z, 1.0, D.ir_d, z, st);
+  }
+  scale_vec(c, N, D.scale, b, D.ir_s);
+  dev_dot(c, N, D.ir_s, D.ir_s, 31);
+  launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, z, b, D.ir_r, st);
+  scale_vec(c, N, D.scale, D.ir_r, D.ir_s);
+  dev_dot(c, N, D.ir_s, D.ir_s, 30);
+  launch_rel_flag(c->d_scal + 30, c->d_scal + 31, c->opt.solve_rtol, c->d_scal + 32, st);
+  launch_scatter_perm(N, D.perm, nullptr, z, sol, st);
+  HIPCHK(hipGetLastError());
   return SGN_OK;
 }
 
@@ -1476,6 +1553,23 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
     if (v < 0 || v >= pr->n_nodes) return fail(c, SGN_E_ARG, "element references a node out of range");
   for (int32_t g : m.grid)
     if (g < 0 || g > 1000000) return fail(c, SGN_E_ARG, "grid coordinate out of range");
+  if (pr->n_components > 1) {
+    if (!pr->component_ptr) return fail(c, SGN_E_ARG, "component_ptr missing");
+    m.comp_ptr.assign(pr->component_ptr, pr->component_ptr + pr->n_components + 1);
+    if (m.comp_ptr.front() != 0 || m.comp_ptr.back() != pr->n_nodes)
+      return fail(c, SGN_E_ARG, "component_ptr must run from 0 to n_nodes");
+    for (int k = 0; k < pr->n_components; ++k)
+      if (m.comp_ptr[k + 1] <= m.comp_ptr[k]) return fail(c, SGN_E_ARG, "empty or unordered component");
+    std::vector<int32_t> comp(pr->n_nodes);
+    for (int k = 0; k < pr->n_components; ++k)
+      for (int v = m.comp_ptr[k]; v < m.comp_ptr[k + 1]; ++v) comp[v] = k;
+    for (int e = 0; e < pr->n_elems; ++e)
+      for (int a = 1; a < nv; ++a)
+        if (comp[m.elems[(size_t)e * nv + a]] != comp[m.elems[(size_t)e * nv]])
+          return fail(c, SGN_E_ARG, "an element spans two components");
+  } else {
+    m.comp_ptr = {0, pr->n_nodes};
+  }
   if (!(pr->E0 > 0) || !(pr->nu > -1.0 && pr->nu < 0.5)) return fail(c, SGN_E_ARG, "invalid material");
   std::string err = analyse(c->A);
   if (!err.empty()) return fail(c, SGN_E_ARG, "symbolic analysis: " + err);
@@ -1572,7 +1666,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
       HIPCHK(up(D.grp_node, S.grp_node, st));
       HIPCHK(up(D.grp_vec, S.grp_vec, st));
     }
-    HIPCHK(hipMemsetAsync(D.solve_flags, 0xff, std::max<int64_t>(1, S.n_panels) * sizeof(int), st));
+    launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
     D.epoch = 0;
     if (D.n_const) {
       std::vector<int64_t> cs(D.n_const);
@@ -1765,7 +1859,7 @@ sgn_status sgn_pc_apply(sgn_ctx c, const double* d_in, double* d_out, double* d_
   if (!d_in || !d_out) return fail(c, SGN_E_ARG, "null vector");
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;
-  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+  launch_fill_i32(1, 0, c->d_cnt + 12, c->stream);
   launch_gather_perm(N, D.perm, nullptr, d_in, c->d_old2, c->stream);
   TRY(pc_apply_new(c, c->d_old2, c->d_old, d_fwd));
   launch_scatter_perm(N, D.perm, nullptr, c->d_old, d_out, c->stream);
@@ -1781,7 +1875,7 @@ sgn_status sgn_pc_forward(sgn_ctx c, const double* d_in, double* d_fwd) {
   if (!d_in || !d_fwd) return fail(c, SGN_E_ARG, "null vector");
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;
-  HIPCHK(hipMemsetAsync(c->d_cnt + 12, 0, sizeof(int), c->stream));
+  launch_fill_i32(1, 0, c->d_cnt + 12, c->stream);
   launch_gather_perm(N, D.perm, nullptr, d_in, c->d_old2, c->stream);
   TRY(pc_forward_new(c, c->d_old2, d_fwd));
   int timeout = 0;
@@ -1864,6 +1958,66 @@ sgn_status sgn_pc_train_loss(sgn_ctx c, const float* d_w, const double* d_probes
   sgn_status s = pc_train_loss_impl(c, d_w, d_probes, n_probes, log_form, d_gw, h_loss);
   c->use_own = keep && c->pc_weights;
   return s;
+}
+
+sgn_status sgn_graph_step(sgn_ctx c, const double* d_x, const double* d_p, double* d_rhs, double* d_sol, int n_ir,
+                          double* h_rel) {
+  TRY(check_ready(c));
+  if (!d_x || !d_p || !d_rhs || !d_sol || n_ir < 0 || n_ir > 16) return fail(c, SGN_E_ARG, "invalid argument");
+  hipStream_t user = c->stream;
+  if (!c->gstream) HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+  const void* key[4] = {d_x, d_p, d_rhs, d_sol};
+  const bool same = c->graph_exec && c->graph_nir == n_ir && std::equal(key, key + 4, c->graph_key);
+  HIPCHK(hipStreamSynchronize(user));  // inputs written on the caller's stream are complete
+  if (!same) {
+    if (c->graph_exec) HIPCHK(hipGraphExecDestroy(c->graph_exec));
+    if (c->graph) HIPCHK(hipGraphDestroy(c->graph));
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    const int keep_prof = c->opt.profile;
+    c->opt.profile = 0;
+    c->stream = c->gstream;
+    c->capturing = true;
+    sgn_status s = SGN_OK;
+    hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      s = enqueue_step(c, d_x, d_p, d_rhs, d_sol, n_ir);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(c->gstream, &g);
+      if (e == hipSuccess) e = e2;
+      c->graph = g;
+    }
+    c->capturing = false;
+    c->stream = user;
+    c->opt.profile = keep_prof;
+    if (s != SGN_OK) return s;
+    if (e != hipSuccess) return fail(c, SGN_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    HIPCHK(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    std::copy(key, key + 4, c->graph_key);
+    c->graph_nir = n_ir;
+  }
+  const double t0 = now_ms();
+  HIPCHK(hipGraphLaunch(c->graph_exec, c->gstream));
+  double out[2];
+  int cnt[16];
+  HIPCHK(hipMemcpyAsync(out, c->d_scal + 32, 2 * sizeof(double), hipMemcpyDeviceToHost, c->gstream));
+  HIPCHK(hipMemcpyAsync(cnt, c->d_cnt, 16 * sizeof(int), hipMemcpyDeviceToHost, c->gstream));
+  HIPCHK(hipStreamSynchronize(c->gstream));
+  c->stats.solve_ms = now_ms() - t0;
+  c->sys[0].factored = true;
+  c->sys[0].current = true;
+  c->sgn_assembled = true;
+  if (h_rel) *h_rel = out[0];
+  if (cnt[12]) return fail(c, SGN_E_HIP, "a pipelined triangular solve timed out waiting for a panel");
+  if (cnt[8] > 0) {
+    c->err = "inverted element in the given state";
+    return SGN_E_INVERTED;
+  }
+  if (out[1] != 1.0) {
+    c->err = "fixed refinement stopped at equilibrated relative residual " + std::to_string(out[0]);
+    return SGN_E_REFINE;
+  }
+  return SGN_OK;
 }
 
 sgn_status sgn_get_sizes(sgn_ctx c, int which, int64_t* n, int64_t* nnz, int64_t* nsn, int64_t* fe, double* fl) {

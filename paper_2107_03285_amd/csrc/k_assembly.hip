@@ -358,6 +358,19 @@ __global__ void k_fill(int64_t n, double v, double* out) {
     out[k] = v;
 }
 
+__global__ void k_rel_flag(const double* r2, const double* b2, double rtol, double* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double rel = *b2 > 0.0 ? sqrt(*r2 / *b2) : 0.0;
+    out[0] = rel;
+    out[1] = rel <= rtol ? 1.0 : 0.0;
+  }
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t v, int32_t* out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = v;
+}
+
 __global__ void k_fill_bytes(int64_t n16, uint4* out) {
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n16; k += (int64_t)gridDim.x * blockDim.x)
@@ -468,6 +481,14 @@ void launch_scale(int64_t n, const double* sc, const double* in, double* out, hi
 
 void launch_fill(int64_t n, double v, double* out, hipStream_t s) {
   if (n > 0) k_fill<<<grid_for(n, 256), 256, 0, s>>>(n, v, out);
+}
+
+void launch_rel_flag(const double* r2, const double* b2, double rtol, double* out, hipStream_t s) {
+  k_rel_flag<<<1, 64, 0, s>>>(r2, b2, rtol, out);
+}
+
+void launch_fill_i32(int64_t n, int32_t v, void* out, hipStream_t s) {
+  if (n > 0) k_fill_i32<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, v, (int32_t*)out);
 }
 
 void launch_fill_bytes(int64_t nbytes, void* out, hipStream_t s) {

@@ -366,8 +366,14 @@ __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* __restrict__ tasks, FrontArgs f,
                                                 T* __restrict__ front) {
-  __shared__ T sL[16][68];
-  __shared__ T sW[16][68];
+  // 64 x 64 tile per block, 32 x 32 per wave (2 x 2 MFMA blocks of 16 x 16); the next k-chunk's loads
+  // are in flight while the current one runs on the matrix cores.  (A 128 x 128 tile halves the
+  // loads per flop but its register footprint halves the occupancy, which measured slower.)
+  constexpr int TM = kUpdTile;
+  constexpr int KC = 32;
+  constexpr int NQ = TM * KC / 256;  // loads per thread and chunk, each of L and W
+  __shared__ T sL[KC][TM + 4];
+  __shared__ T sW[KC][TM + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.x;
   int64_t lo = 0, hi = ntasks - 1;
@@ -381,8 +387,8 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   const int64_t k0 = tk[1], k1 = tk[2], cb = tk[3], ce = tk[4];
   const int64_t m = f.sn_m[sn];
   int64_t lt = b - tk[5];
-  const int64_t R = (m - cb + 63) / 64;
-  const int64_t ct = (ce - cb + 63) / 64;
+  const int64_t R = (m - cb + TM - 1) / TM;
+  const int64_t ct = (ce - cb + TM - 1) / TM;
   int64_t j = 0;
   while (j < ct && lt >= R - j) {
     lt -= R - j;
@@ -390,7 +396,7 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   }
   if (j >= ct) return;  // beyond the task's tiles (never for a consistent schedule)
   const int64_t i = j + lt;
-  const int64_t r0 = cb + 64 * i, cc0 = cb + 64 * j;
+  const int64_t r0 = cb + TM * i, cc0 = cb + TM * j;
   T* F = front + f.sn_front_off[sn];
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   dbl4 accd[2][2];
@@ -403,24 +409,37 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
       accf[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
     }
   const int64_t cmax = ce < m ? ce : m;
-  for (int64_t kb = k0; kb < k1; kb += 16) {
+  // per thread NQ entries of the L chunk (TM consecutive rows of one column) and NQ of the W^T chunk
+  // (KC consecutive k of one column)
+  T rl[NQ], rw[NQ];
+  auto load = [&](int64_t kb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int idx = tid + 256 * q;
       {
-        const int rr = idx & 63, kk = idx >> 6;  // 64 consecutive rows of one column of L
+        const int rr = idx % TM, kk = idx / TM;
         const int64_t k = kb + kk, r = r0 + rr;
-        sL[kk][rr] = (k < k1 && r < m) ? F[r + k * m] : (T)0;
+        rl[q] = (k < k1 && r < m) ? F[r + k * m] : (T)0;
       }
       {
-        const int kk = idx & 15, cc = idx >> 4;  // 16 consecutive k of one column of W^T
+        const int kk = idx % KC, cc = idx / KC;
         const int64_t k = kb + kk, c = cc0 + cc;
-        sW[kk][cc] = (k < k1 && c < cmax) ? F[k + c * m] : (T)0;
+        rw[q] = (k < k1 && c < cmax) ? F[k + c * m] : (T)0;
       }
     }
-    __syncthreads();
+  };
+  load(k0);
+  for (int64_t kb = k0; kb < k1; kb += KC) {
 #pragma unroll
-    for (int k4 = 0; k4 < 4; ++k4) {
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = tid + 256 * q;
+      sL[idx / TM][idx % TM] = rl[q];
+      sW[idx % KC][idx / KC] = rw[q];
+    }
+    __syncthreads();
+    if (kb + KC < k1) load(kb + KC);
+#pragma unroll
+    for (int k4 = 0; k4 < KC / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)

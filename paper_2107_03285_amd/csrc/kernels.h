@@ -8,6 +8,7 @@
 namespace sgn {
 
 constexpr int kRedBlocks = 1024;  // fixed partition of deterministic reductions
+constexpr int kUpdTile = 64;      // edge of the trailing-update tile (the symbolic schedule counts these tiles)
 
 // ---------------------------------------------------------------- element + assembly
 struct ElemArgs {
@@ -52,6 +53,10 @@ void launch_fill(int64_t n, double v, double* out, hipStream_t s);
 // out = s .* in (elementwise; out may alias in)
 void launch_scale(int64_t n, const double* s, const double* in, double* out, hipStream_t st);
 void launch_fill_bytes(int64_t nbytes, void* out, hipStream_t s);
+// out[0] = sqrt(r2 / b2), out[1] = (out[0] <= rtol): a device-side convergence flag
+void launch_rel_flag(const double* r2, const double* b2, double rtol, double* out, hipStream_t s);
+// out[0 .. n) = v (32-bit words; a kernel, so it may sit in a captured graph where memset nodes may not)
+void launch_fill_i32(int64_t n, int32_t v, void* out, hipStream_t s);
 // y = K x with the symmetric matrix stored as lower slots and addressed through the full CSR
 void launch_spmv(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
                  const double* vals, const double* x, double* y, hipStream_t s);

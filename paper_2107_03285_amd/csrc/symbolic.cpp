@@ -42,78 +42,83 @@ struct NdResult {
 
 NdResult nested_dissection(const Mesh& m) {
   const int d = m.dim;
-  int shape[3] = {1, 1, 1};
-  for (int v = 0; v < m.n_nodes; ++v)
-    for (int a = 0; a < d; ++a) shape[a] = std::max(shape[a], m.grid[(size_t)v * d + a] + 1);
-  // grid point -> node id (-1 if none)
-  int64_t npts = (int64_t)shape[0] * shape[1] * shape[2];
-  std::vector<int32_t> at(npts, -1);
-  for (int v = 0; v < m.n_nodes; ++v) {
-    int c[3] = {0, 0, 0};
-    for (int a = 0; a < d; ++a) c[a] = m.grid[(size_t)v * d + a];
-    at[((int64_t)c[2] * shape[1] + c[1]) * shape[0] + c[0]] = v;
-  }
   NdResult R;
-  auto emit = [&](const int* lo, const int* hi) {
-    int64_t n0 = (int64_t)R.order.size();
-    int lo2 = d == 3 ? lo[2] : 0, hi2 = d == 3 ? hi[2] : 1;
-    for (int k = lo2; k < hi2; ++k)
-      for (int j = lo[1]; j < hi[1]; ++j)
-        for (int i = lo[0]; i < hi[0]; ++i) {
-          int32_t v = at[((int64_t)k * shape[1] + j) * shape[0] + i];
-          if (v >= 0 && !m.fixed[v]) R.order.push_back(v);
-        }
-    return std::make_pair(n0, (int64_t)R.order.size());
-  };
-  auto make = [&](std::pair<int64_t, int64_t> r, std::vector<int> ch) {
-    TreeNode t;
-    t.nb = r.first;
-    t.ne = r.second;
-    t.children = std::move(ch);
-    R.tree.push_back(t);
-    return (int)R.tree.size() - 1;
-  };
-  // returns tree node ids that are the roots of this box's subtree
-  std::function<std::vector<int>(const int*, const int*)> rec = [&](const int* lo, const int* hi) {
-    int ext[3] = {1, 1, 1};
-    int64_t prod = 1;
-    int mx = 0;
-    for (int a = 0; a < d; ++a) {
-      ext[a] = hi[a] - lo[a];
-      if (ext[a] <= 0) return std::vector<int>();
-      prod *= ext[a];
-      mx = std::max(mx, ext[a]);
+  const int ncomp = m.comp_ptr.size() > 1 ? (int)m.comp_ptr.size() - 1 : 1;
+  for (int comp = 0; comp < ncomp; ++comp) {
+    const int v0 = m.comp_ptr.size() > 1 ? m.comp_ptr[comp] : 0;
+    const int v1 = m.comp_ptr.size() > 1 ? m.comp_ptr[comp + 1] : m.n_nodes;
+    int shape[3] = {1, 1, 1};
+    for (int v = v0; v < v1; ++v)
+      for (int a = 0; a < d; ++a) shape[a] = std::max(shape[a], m.grid[(size_t)v * d + a] + 1);
+    // grid point -> node id (-1 if none)
+    int64_t npts = (int64_t)shape[0] * shape[1] * shape[2];
+    std::vector<int32_t> at(npts, -1);
+    for (int v = v0; v < v1; ++v) {
+      int c[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) c[a] = m.grid[(size_t)v * d + a];
+      at[((int64_t)c[2] * shape[1] + c[1]) * shape[0] + c[0]] = v;
     }
-    if (prod <= 8 || mx <= 2) {
-      auto r = emit(lo, hi);
-      if (r.second == r.first) return std::vector<int>();
-      return std::vector<int>{make(r, {})};
-    }
-    int ax = 0;
-    for (int a = 1; a < d; ++a)
-      if (ext[a] > ext[ax]) ax = a;
-    int mid = lo[ax] + ext[ax] / 2;
-    int hi1[3], lo2[3], los[3], his[3];
-    for (int a = 0; a < 3; ++a) {
-      hi1[a] = hi[a];
-      lo2[a] = lo[a];
-      los[a] = lo[a];
-      his[a] = hi[a];
-    }
-    hi1[ax] = mid;
-    lo2[ax] = mid + 1;
-    los[ax] = mid;
-    his[ax] = mid + 1;
-    std::vector<int> ch = rec(lo, hi1);
-    std::vector<int> ch2 = rec(lo2, hi);
-    ch.insert(ch.end(), ch2.begin(), ch2.end());
-    auto r = emit(los, his);
-    if (r.second == r.first) return ch;  // empty separator: pass the subtrees up
-    return std::vector<int>{make(r, ch)};
-  };
-  int lo[3] = {0, 0, 0};
-  int hi[3] = {shape[0], shape[1], shape[2]};
-  rec(lo, hi);
+    auto emit = [&](const int* lo, const int* hi) {
+      int64_t n0 = (int64_t)R.order.size();
+      int lo2 = d == 3 ? lo[2] : 0, hi2 = d == 3 ? hi[2] : 1;
+      for (int k = lo2; k < hi2; ++k)
+        for (int j = lo[1]; j < hi[1]; ++j)
+          for (int i = lo[0]; i < hi[0]; ++i) {
+            int32_t v = at[((int64_t)k * shape[1] + j) * shape[0] + i];
+            if (v >= 0 && !m.fixed[v]) R.order.push_back(v);
+          }
+      return std::make_pair(n0, (int64_t)R.order.size());
+    };
+    auto make = [&](std::pair<int64_t, int64_t> r, std::vector<int> ch) {
+      TreeNode t;
+      t.nb = r.first;
+      t.ne = r.second;
+      t.children = std::move(ch);
+      R.tree.push_back(t);
+      return (int)R.tree.size() - 1;
+    };
+    // returns tree node ids that are the roots of this box's subtree
+    std::function<std::vector<int>(const int*, const int*)> rec = [&](const int* lo, const int* hi) {
+      int ext[3] = {1, 1, 1};
+      int64_t prod = 1;
+      int mx = 0;
+      for (int a = 0; a < d; ++a) {
+        ext[a] = hi[a] - lo[a];
+        if (ext[a] <= 0) return std::vector<int>();
+        prod *= ext[a];
+        mx = std::max(mx, ext[a]);
+      }
+      if (prod <= 8 || mx <= 2) {
+        auto r = emit(lo, hi);
+        if (r.second == r.first) return std::vector<int>();
+        return std::vector<int>{make(r, {})};
+      }
+      int ax = 0;
+      for (int a = 1; a < d; ++a)
+        if (ext[a] > ext[ax]) ax = a;
+      int mid = lo[ax] + ext[ax] / 2;
+      int hi1[3], lo2[3], los[3], his[3];
+      for (int a = 0; a < 3; ++a) {
+        hi1[a] = hi[a];
+        lo2[a] = lo[a];
+        los[a] = lo[a];
+        his[a] = hi[a];
+      }
+      hi1[ax] = mid;
+      lo2[ax] = mid + 1;
+      los[ax] = mid;
+      his[ax] = mid + 1;
+      std::vector<int> ch = rec(lo, hi1);
+      std::vector<int> ch2 = rec(lo2, hi);
+      ch.insert(ch.end(), ch2.begin(), ch2.end());
+      auto r = emit(los, his);
+      if (r.second == r.first) return ch;  // empty separator: pass the subtrees up
+      return std::vector<int>{make(r, ch)};
+    };
+    int lo[3] = {0, 0, 0};
+    int hi[3] = {shape[0], shape[1], shape[2]};
+    rec(lo, hi);
+  }
   for (int t = 0; t < (int)R.tree.size(); ++t)
     for (int c : R.tree[t].children) R.tree[c].parent = t;
   return R;

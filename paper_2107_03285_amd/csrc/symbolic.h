@@ -12,7 +12,7 @@ namespace sgn {
 
 constexpr int kPanel = 64;        // panel width of the blocked front factorisation
 constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
-constexpr int kTile = 64;         // update tile edge
+constexpr int kTile = 64;         // update tile edge (equal to the kernels' kUpdTile)
 constexpr int kSolveKC = 256;     // k-chunk of the split-k L21 y product in the forward solve
 
 enum SystemKind { SYS_SGN = 0, SYS_KX = 1 };
@@ -24,6 +24,7 @@ struct Mesh {
   std::vector<int32_t> grid;      // [n_nodes*dim]
   std::vector<uint8_t> fixed;     // [n_nodes]
   std::vector<double> fext;       // [n_nodes*dim]
+  std::vector<int32_t> comp_ptr;  // node ranges of independent components ({0, n_nodes} for one)
   int param_kind = 0;
   // derived
   std::vector<int32_t> fdof;      // node -> first free DOF (-1 fixed)

@@ -31,7 +31,7 @@ EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_w
            "sgn_get_symbolic", "sgn_get_values", "sgn_get_stats", "sgn_selftest_mfma", "sgn_last_error",
            "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
            "sgn_solve_minres", "sgn_gnn_num_weights", "sgn_gnn_init", "sgn_gnn_forward", "sgn_gnn_backward",
-           "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss"]
+           "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss", "sgn_graph_step"]
 
 
 class sgn_problem(C.Structure):
@@ -41,7 +41,8 @@ class sgn_problem(C.Structure):
                 ("f_ext", C.POINTER(C.c_double)), ("E0", C.c_double), ("nu", C.c_double),
                 ("param_kind", C.c_int), ("n_targets", C.c_int), ("target_dof", C.POINTER(C.c_int32)),
                 ("target_val", C.POINTER(C.c_double)), ("target_w", C.c_double),
-                ("length_scale", C.c_double), ("reg_mu", C.c_double), ("p_ref", C.POINTER(C.c_double))]
+                ("length_scale", C.c_double), ("reg_mu", C.c_double), ("p_ref", C.POINTER(C.c_double)),
+                ("n_components", C.c_int), ("component_ptr", C.POINTER(C.c_int32))]
 
 
 class sgn_options(C.Structure):
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_gnn_forward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "sgn_gnn_backward": (C.c_int, [vp, vp, vp, vp, vp]),
         "sgn_set_pc_weights": (C.c_int, [vp, vp]),
+        "sgn_graph_step": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, dp]),
         "sgn_pc_train_loss": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp, dp]),
         "sgn_adam": (C.c_int, [C.c_int64, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
                                vp]),
@@ -183,6 +185,8 @@ class Context:
                                       else np.zeros(len(prob.target_dof)), dtype=np.float64),
             pref=np.ascontiguousarray(prob.p_ref if prob.p_ref is not None else np.zeros(prob.n_p),
                                       dtype=np.float64),
+            comp=np.ascontiguousarray(getattr(prob, "components", None) if getattr(prob, "components", None)
+                                      is not None else [0, prob.n_nodes], dtype=np.int32),
         )
         k = self._keep
         P = sgn_problem(dim=d, n_nodes=prob.n_nodes, n_elems=prob.n_elems,
@@ -193,7 +197,8 @@ class Context:
                         target_dof=_ptr(k["tdof"], C.c_int32), target_val=_ptr(k["tval"], C.c_double),
                         target_w=prob.target_w,
                         length_scale=prob.length_scale if prob.length_scale else 1.0,
-                        reg_mu=prob.reg_mu, p_ref=_ptr(k["pref"], C.c_double))
+                        reg_mu=prob.reg_mu, p_ref=_ptr(k["pref"], C.c_double),
+                        n_components=len(k["comp"]) - 1, component_ptr=_ptr(k["comp"], C.c_int32))
         self._stream = stream
         h = C.c_void_p()
         st = lib.sgn_create(C.byref(P), C.byref(self.options), self._stream_ptr(), C.byref(h))
@@ -336,6 +341,13 @@ class Context:
         self._check(self.lib.sgn_pc_train_loss(self.h, _dev_ptr(w), _dev_ptr(probes), int(probes.shape[0]),
                                                int(bool(log_form)), _dev_ptr(gw), C.byref(loss)))
         return loss.value
+
+    def graph_step(self, x, p, rhs, sol, n_ir=2):
+        """Captured-graph step (KKT right-hand side, n_ir refinement sweeps); returns the final residual."""
+        rel = C.c_double()
+        self._check(self.lib.sgn_graph_step(self.h, _dev_ptr(x), _dev_ptr(p), _dev_ptr(rhs), _dev_ptr(sol),
+                                            int(n_ir), C.byref(rel)))
+        return rel.value
 
     def step(self, p, x):
         info = sgn_step_info()

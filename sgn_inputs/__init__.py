@@ -68,6 +68,9 @@ class Problem:
     target_noise: Optional[np.ndarray] = None  # [n_t] additive noise on x(p0)
     seed: int = 0
     grid: tuple = ()
+    # a batch of independent problems: node ranges of the components and their own grid coordinates
+    components: Optional[np.ndarray] = None
+    node_grid_override: Optional[np.ndarray] = None
 
     @property
     def n_nodes(self) -> int:
@@ -100,6 +103,8 @@ class Problem:
 
     def node_grid(self) -> np.ndarray:
         """[n_nodes, dim] integer grid coordinates of every node (axis 0 fastest in the node id)."""
+        if self.node_grid_override is not None:
+            return self.node_grid_override
         ids = np.arange(self.n_nodes)
         if self.dim == 2:
             n = self.grid[0]
@@ -296,6 +301,37 @@ def learned_pc_problem(seed: int) -> Problem:
     nz = s if seed % 2 == 0 else max(2, -(-s // 4))
     return problem_3d(4 * s, s, nz, 1.0 / s, seed=seed, param_kind=P_LOGE,
                       name=f"{'cantilever' if seed % 2 == 0 else 'plate'}_{4*s}x{s}x{nz}_s{seed}")
+
+
+def union_problem(problems, name: str = "batch") -> Problem:
+    """The disjoint union of independent problems of one family as a single problem: nodes, elements,
+    free DOFs, parameters, targets and fields concatenated in order; ``components`` marks each
+    problem's node range and ``node_grid_override`` keeps each problem's own grid coordinates.
+    Problems must share dim, parameter kind, material constants, target weight, ell and mu."""
+    first = problems[0]
+    for q in problems[1:]:
+        assert (q.dim, q.param_kind, q.E0, q.nu, q.target_w, q.reg_mu) == \
+            (first.dim, first.param_kind, first.E0, first.nu, first.target_w, first.reg_mu)
+    node_off = np.concatenate([[0], np.cumsum([q.n_nodes for q in problems])])
+    x_off = np.concatenate([[0], np.cumsum([q.n_x for q in problems])])
+
+    def cat(field):
+        vals = [getattr(q, field) for q in problems]
+        return None if any(v is None for v in vals) else np.concatenate(vals)
+    u = Problem(
+        name=name, dim=first.dim,
+        rest_pos=np.concatenate([q.rest_pos for q in problems]),
+        elems=np.concatenate([q.elems + node_off[i] for i, q in enumerate(problems)]).astype(np.int32),
+        fixed=np.concatenate([q.fixed for q in problems]),
+        f_ext=np.concatenate([q.f_ext for q in problems]),
+        E0=first.E0, nu=first.nu, param_kind=first.param_kind,
+        target_dof=np.concatenate([q.target_dof + x_off[i] for i, q in enumerate(problems)]).astype(np.int32),
+        target_val=cat("target_val"), target_w=first.target_w, length_scale=first.length_scale,
+        reg_mu=first.reg_mu, p_ref=cat("p_ref"), p_star=cat("p_star"), target_noise=cat("target_noise"),
+        seed=first.seed, grid=(),
+        components=node_off.astype(np.int32),
+        node_grid_override=np.concatenate([q.node_grid() for q in problems]).astype(np.int32))
+    return u
 
 
 def batch_problems(count: int = 256, base_seed: int = 10000, lo: int = 8, hi: int = 48):
