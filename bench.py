@@ -108,6 +108,80 @@ def copy_calibration():
     torch.cuda.empty_cache()
 
 
+def batch_leg(steps: int, warmup: int, dev: str = "cuda:0"):
+    """256 independent 2D membranes (8..48 nodes per side, seeds 10000..10255) as one disjoint union:
+    the captured-graph step (level-batched FP32 factorisation, 3 refinement sweeps) against solving
+    the same problems one at a time with their own FP64 contexts (assemble, factor, solve)."""
+    import torch
+
+    from paper_2107_03285_amd import sgn
+    probs = si.batch_problems(256, base_seed=10000, lo=8, hi=48)
+    u = si.union_problem(probs, name="membranes_2d_256")
+    N = 2 * u.n_x + u.n_p
+    # set-up (untimed): ell from x(p0) of the union, targets x(p*) on each top row
+    ref = sgn.Context(u, sgn.default_options()).allocate(dev)
+    p0 = torch.tensor(u.p_init(), dtype=torch.float64, device=dev)
+    x0 = torch.tensor(u.x_rest(), dtype=torch.float64, device=dev)
+    ref.equilibrium(p0, x0)
+    ell = float((x0.cpu() - torch.tensor(u.x_rest())).abs().max())
+    xs = x0.clone()
+    ref.equilibrium(torch.tensor(u.p_star, dtype=torch.float64, device=dev), xs)
+    u.length_scale = ell
+    u.target_val = xs.cpu().numpy()[u.target_dof]
+    del ref
+    torch.cuda.empty_cache()
+    o = sgn.default_options(precision=sgn.SGN_FP32_IR, rhs_kind=sgn.SGN_RHS_KKT)
+    ctx = sgn.Context(u, o).allocate(dev)
+    rhs = torch.zeros(N, dtype=torch.float64, device=dev)
+    sol = torch.zeros(N, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        ctx.graph_step(x0, p0, rhs, sol, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rel = 0.0
+    for _ in range(steps):
+        rel = max(rel, ctx.graph_step(x0, p0, rhs, sol, 3))
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    dp_batch = sol.cpu().numpy()[u.n_x:u.n_x + u.n_p]
+    del ctx
+    torch.cuda.empty_cache()
+    # one at a time, FP64, each problem in its own context at the union's state and targets
+    xh = x0.cpu().numpy()
+    x_off = np.concatenate([[0], np.cumsum([q.n_x for q in probs])])
+    p_off = np.concatenate([[0], np.cumsum([q.n_p for q in probs])])
+    t_off = np.concatenate([[0], np.cumsum([len(q.target_dof) for q in probs])])
+    singles = []
+    for i, q in enumerate(probs):
+        q.length_scale = ell
+        q.target_val = u.target_val[t_off[i]:t_off[i + 1]]
+        c = sgn.Context(q, sgn.default_options(rhs_kind=sgn.SGN_RHS_KKT)).allocate(dev)
+        n = 2 * q.n_x + q.n_p
+        singles.append((c, torch.tensor(xh[x_off[i]:x_off[i + 1]], device=dev),
+                        torch.tensor(q.p_init(), dtype=torch.float64, device=dev),
+                        torch.zeros(n, dtype=torch.float64, device=dev), torch.zeros(n, dtype=torch.float64, device=dev)))
+    for c, x, p, r, z in singles:  # warm-up
+        c.assemble(x, p, r)
+        c.factor()
+        c.solve(r, z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, x, p, r, z in singles:
+        c.assemble(x, p, r)
+        c.factor()
+        c.solve(r, z)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    err = max(float(np.linalg.norm(z.cpu().numpy()[q.n_x:q.n_x + q.n_p] - dp_batch[p_off[i]:p_off[i + 1]]) /
+                    max(1e-300, np.linalg.norm(z.cpu().numpy()[q.n_x:q.n_x + q.n_p])))
+              for i, (q, (c, x, p, r, z)) in enumerate(zip(probs, singles)))
+    return {"problems": len(probs), "N_union": N, "graph_step_ms": 1e3 * t_graph,
+            "problem_steps_per_s_batched": len(probs) / t_graph, "one_at_a_time_fp64_ms": 1e3 * t_single,
+            "problem_steps_per_s_one_at_a_time": len(probs) / t_single, "speedup": t_single / t_graph,
+            "max_rel_residual": rel, "max_dp_rel_diff_vs_single_fp64": err,
+            "graph": "assemble + KKT rhs + FP32 LDL^T + solve + 3 FP64 refinement sweeps, replayed"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +191,7 @@ def main():
     ap.add_argument("--paths", default="fp32ir,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events on the update kernel")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-problem leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB copy first (for scaling hardware byte counters)")
     args = ap.parse_args()
@@ -244,6 +319,11 @@ def main():
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_update (MFMA trailing update of the fronts)",
                 "avg_launch_us": r["update_avg_us"], "flops_per_launch": r["update_flops_per_launch"]}
+    batch = None
+    if not args.no_batch:
+        log("[bench] batched leg: 256 2D problems, captured-graph step vs one at a time")
+        batch = batch_leg(max(3, args.steps // 2), 1, dev)
+        log(f"[bench] batched: {batch}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
@@ -264,6 +344,7 @@ def main():
         "speedup_fp32ir_vs_fp64": (results["fp32ir"]["steps_per_s"] / results["fp64"]["steps_per_s"]
                                    if "fp32ir" in results and "fp64" in results else None),
         "roofline": roof,
+        "batched_2d_256": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
