@@ -93,3 +93,42 @@ def test_symbolic_structure_is_bit_exact_at_200k_dof():
     assert np.array_equal(perm, operm) and np.array_equal(rowptr, orp) and np.array_equal(colind, oci)
     assert np.array_equal(etree, S.etree_liu(orp, oci))
     assert rowptr[-1] == 12_043_982
+
+
+def test_union_orders_each_problem_on_its_own():
+    """A batch (disjoint union) is ordered problem by problem: the union's perm restricted to each
+    problem is that problem's own perm shifted into the union's numbering (block order
+    [x; p; lambda] of the union), and the elimination tree is a forest with one root per problem."""
+    _lib()
+    probs = si.batch_problems(5, base_seed=10000, lo=4, hi=9)
+    u = si.union_problem(probs)
+    cu = sgn.Context(u)
+    pu, eu, _, _ = cu.symbolic()
+    nxu, npu = u.n_x, u.n_p
+    xo = np.concatenate([[0], np.cumsum([q.n_x for q in probs])])
+    po = np.concatenate([[0], np.cumsum([q.n_p for q in probs])])
+    pos = 0
+    for i, q in enumerate(probs):
+        pq, eq, _, _ = sgn.Context(q).symbolic()
+        nx, npar = q.n_x, q.n_p
+        # map the problem's old index (block order) into the union's old index
+        mapped = np.where(pq < nx, pq + xo[i],
+                          np.where(pq < nx + npar, nxu + po[i] + (pq - nx), nxu + npu + xo[i] + (pq - nx - npar)))
+        n = pq.size
+        assert np.array_equal(pu[pos:pos + n], mapped)
+        e_local = np.where(eq >= 0, eq + pos, -1)
+        assert np.array_equal(eu[pos:pos + n], e_local)
+        pos += n
+    assert pos == pu.size
+    assert int(np.sum(eu < 0)) == len(probs)
+
+
+def test_single_component_is_the_plain_problem():
+    _lib()
+    q = si.config_2d()
+    a = sgn.Context(q).symbolic()
+    q1 = q.copy()
+    q1.components = np.array([0, q.n_nodes], dtype=np.int32)
+    b = sgn.Context(q1).symbolic()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

@@ -215,3 +215,73 @@ def test_factor_and_solve_are_bitwise_reproducible():
         ctx.solve(rhs, sol)
         sols.append(_host(sol))
     assert np.array_equal(sols[0].view(np.uint64), sols[1].view(np.uint64))
+
+
+def test_outer_iterations_kkt_rhs_match_adjoint():
+    """sgn_step with the KKT right-hand side (no adjoint solve) follows the adjoint-form trajectory:
+    same dp (Appendix A, Theorem 2), same slope, hence the same step lengths."""
+    prob = D.setup_targets(si.problem_3d(4, 2, 2, 0.25, seed=1))
+    out = {}
+    for kind in (sgn.SGN_RHS_ADJOINT, sgn.SGN_RHS_KKT):
+        ctx = _ctx(prob, rhs_kind=kind)
+        p = _cuda(prob.p_init())
+        x = _cuda(prob.x_rest())
+        ctx.equilibrium(p, x)
+        tr = []
+        for _ in range(3):
+            info = ctx.step(p, x)
+            tr.append((info.alpha, info.gtdp, info.f1))
+        out[kind] = (tr, _host(p))
+    (ta, pa), (tk, pk) = out[sgn.SGN_RHS_ADJOINT], out[sgn.SGN_RHS_KKT]
+    assert [a for a, _, _ in ta] == [a for a, _, _ in tk]
+    assert np.allclose([g for _, g, _ in ta], [g for _, g, _ in tk], rtol=1e-8)
+    assert np.allclose([f for _, _, f in ta], [f for _, _, f in tk], rtol=1e-10)
+    assert np.linalg.norm(pk - pa) <= 1e-8 * np.linalg.norm(pa)
+
+
+def test_nodal_force_parameters_closed_form_step():
+    """Nodal-force parameters (c = grad E - f_ext - p, so Kp = -I): with every DOF a target, A = I and no
+    regulariser the Gauss-Newton step is dp = -Kx (x - t) in closed form; the GPU step must match it
+    and the oracle's dense step."""
+    prob = si.problem_2d(5, seed=2, param_kind=si.P_NODAL_FORCE)
+    p = np.zeros(prob.n_x)
+    x, info = D.equilibrium(prob, p, rtol=1e-11)
+    assert info.converged
+    prob.target_dof = np.arange(prob.n_x, dtype=np.int32)
+    prob.target_val = x + 1e-3 * np.sin(np.arange(prob.n_x))
+    prob.length_scale = 1.0
+    prob.reg_mu = 0.0
+    prob.p_ref = np.zeros(prob.n_x)
+    ctx = _ctx(prob)
+    xd, pd = _cuda(x), _cuda(p)
+    ctx.equilibrium(pd, xd)
+    N = 2 * prob.n_x + prob.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.assemble(xd, pd, rhs)
+    ctx.factor()
+    sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.solve(rhs, sol)
+    _, dp, _ = _blocks(prob, _host(sol))
+    xg = _host(xd)
+    ref = -D.stiffness(prob, xg, p).toarray() @ (xg - prob.target_val)
+    assert _rel(dp, ref) <= 1e-9
+    assert _rel(dp, D.dense_gn_step(prob, xg, p).dp) <= 1e-9
+
+
+def test_zero_right_hand_side_gives_zero_step():
+    """At p = p_ref with targets equal to x(p) the gradient vanishes: the step is exactly zero, and the
+    MINRES path returns at once."""
+    prob, p, x = _problem("tiny")
+    prob = prob.copy()
+    prob.target_val = x[prob.target_dof].copy()
+    prob.p_ref = p.copy()
+    ctx = _ctx(prob)
+    xd, pd = _cuda(x), _cuda(p)
+    ctx.equilibrium(pd, xd)
+    N = 2 * prob.n_x + prob.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.assemble(xd, pd, rhs)
+    ctx.factor()
+    sol = torch.ones(N, dtype=torch.float64, device="cuda")
+    info = ctx.solve_minres(torch.zeros(N, dtype=torch.float64, device="cuda"), sol)
+    assert info.fallback == 0 and float(sol.abs().max()) == 0.0
