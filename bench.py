@@ -1,10 +1,12 @@
 """Benchmark: SGN search directions per second on one MI355X.
 
 One "step" is the paper's timed unit, the computation of one search
-direction at a fixed equilibrium (x, p): right-hand side (adjoint solve with
-the Kx factor), assembly of the saddle-point matrix from per-element blocks,
-supernodal LDL^T, and the solve with FP64 refinement to an equilibrated
-relative residual of 1e-10.  The headline path factorises in FP32 on the
+direction at a fixed equilibrium (x, p): assembly of the saddle-point matrix
+from per-element blocks with its right-hand side, supernodal LDL^T, and the
+solve with FP64 refinement to an equilibrated relative residual of 1e-10.  The
+right-hand side is the KKT form [-df/dx; -df/dp; 0], which gives the same dp
+as [0; -g; 0] without the adjoint solve that forms g (Appendix A, Theorem 2);
+the adjoint form is timed too (path fp32ir_adjoint).  The headline path factorises in FP32 on the
 matrix cores and refines in FP64; the plain FP64 factorisation is timed beside
 it on identical inputs and its step is the reference the FP32 step is
 compared with.
@@ -188,7 +190,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cantilever_100x25x25", choices=sorted(WORKLOADS))
-    ap.add_argument("--paths", default="fp32ir,fp64")
+    ap.add_argument("--paths", default="fp32ir_graph,fp32ir,fp64,fp32ir_adjoint",
+                    help="fp32ir / fp64: KKT right-hand side, eager launches; fp32ir_graph: the same step captured "
+                         "once into a HIP graph and replayed; fp32ir_adjoint: adjoint right-hand side (one Kx solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events on the update kernel")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-problem leg")
@@ -211,9 +215,10 @@ def main():
     log(f"[bench] workload {prob.name}: n_x={prob.n_x} n_p={prob.n_p} N={2 * prob.n_x + prob.n_p}")
     paths = [s.strip() for s in args.paths.split(",") if s.strip()]
 
-    def make_ctx(precision):
+    def make_ctx(precision, rhs_kind=None):
         t0 = time.perf_counter()
-        o = sgn.default_options(precision=precision, profile=0 if args.no_profile else 1)
+        o = sgn.default_options(precision=precision, profile=0 if args.no_profile else 1,
+                                rhs_kind=sgn.SGN_RHS_KKT if rhs_kind is None else rhs_kind)
         ctx = sgn.Context(prob, o).allocate(dev)
         log(f"[bench] context precision={precision} ready in {time.perf_counter() - t0:.1f} s "
             f"(workspace {ctx.workspace_size() / 1e9:.1f} GB)")
@@ -242,19 +247,37 @@ def main():
         si_ = ctx.solve(rhs, sol)
         return fi, si_
 
+    class GraphInfo:  # what the graph step reports in place of the eager factor / solve infos
+        def __init__(self, rel, n_ir):
+            self.rel_res, self.sweeps, self.ms = rel, n_ir, 0.0
+            self.n_pos = self.n_neg = self.n_zero = self.n_perturbed = -1
+
     results = {}
     sols = {}
     for path in paths:
-        prec = {"fp32ir": sgn.SGN_FP32_IR, "fp64": sgn.SGN_FP64}[path]
-        ctx = ref_ctx if prec == f64 else make_ctx(prec)
+        prec = {"fp32ir": sgn.SGN_FP32_IR, "fp64": sgn.SGN_FP64, "fp32ir_adjoint": sgn.SGN_FP32_IR,
+                "fp32ir_graph": sgn.SGN_FP32_IR}[path]
+        adj = path.endswith("_adjoint")
+        graph = path.endswith("_graph")
+        ctx = ref_ctx if (prec == f64 and not adj) else make_ctx(prec, sgn.SGN_RHS_ADJOINT if adj else None)
         if ctx is not ref_ctx:
             ctx.set_targets(prob.target_val, ell)
             xe = x.clone()
             ctx.equilibrium(p, xe)
         rhs = torch.zeros(N, dtype=torch.float64, device=dev)
         sol = torch.zeros(N, dtype=torch.float64, device=dev)
+        step_fn = run_step
+        if graph:
+            # the eager step tells how many refinement sweeps reach 1e-10; the graph replays exactly that
+            # many and checks the residual on the device at every replay (an error if it is not met)
+            _, si0 = run_step(ctx, rhs, sol)
+            n_ir = int(si0.sweeps)
+
+            def step_fn(ctx, rhs, sol, n_ir=n_ir):
+                rel = ctx.graph_step(x, p, rhs, sol, n_ir)
+                return GraphInfo(rel, n_ir), GraphInfo(rel, n_ir)
         for w in range(args.warmup):
-            fi, si_ = run_step(ctx, rhs, sol)
+            fi, si_ = step_fn(ctx, rhs, sol)
             log(f"[bench] {path} warmup {w}: factor {fi.ms:.1f} ms, solve {si_.ms:.1f} ms "
                 f"({si_.sweeps} refinement sweeps, res {si_.rel_res:.1e})")
         torch.cuda.synchronize()
@@ -267,7 +290,7 @@ def main():
         step_ms = []
         for k in range(args.steps):
             ts = time.perf_counter()
-            fi, si_ = run_step(ctx, rhs, sol)
+            fi, si_ = step_fn(ctx, rhs, sol)
             torch.cuda.synchronize()
             step_ms.append(1e3 * (time.perf_counter() - ts))
             st = ctx.stats()
@@ -292,6 +315,11 @@ def main():
             update_ms=upd_ms / K, update_tflops=(upd_fl / (upd_ms * 1e-3) / 1e12) if upd_ms > 0 else None,
             update_launches=upd_n // K, update_avg_us=(1e3 * upd_ms / upd_n) if upd_n else None,
             update_flops_per_launch=(upd_fl / upd_n) if upd_n else None)
+        if graph:  # one replay covers every stage: per-stage host timings do not exist
+            for key in ("factor_ms", "solve_ms", "assemble_ms", "assemble_gbs", "factor_tflops", "inertia",
+                        "perturbed"):
+                results[path][key] = None
+            results[path]["graph_refine_sweeps"] = n_ir
         sols[path] = sol.cpu().numpy()
         log(f"[bench] {path}: {results[path]}")
         if ctx is not ref_ctx:
@@ -305,14 +333,22 @@ def main():
         a, b = sols["fp32ir"], sols["fp64"]
         err = {blk: float(np.linalg.norm(a[s] - b[s]) / np.linalg.norm(b[s]))
                for blk, s in (("dx", slice(0, nx)), ("dp", slice(nx, nx + npar)), ("dlambda", slice(nx + npar, N)))}
+        if "fp32ir_graph" in sols:
+            g = sols["fp32ir_graph"]
+            err["dp_graph_vs_fp64"] = float(np.linalg.norm(g[nx:nx + npar] - b[nx:nx + npar]) /
+                                            np.linalg.norm(b[nx:nx + npar]))
+        if "fp32ir_adjoint" in sols:  # same dx and dp from the two right-hand sides (Appendix A)
+            c = sols["fp32ir_adjoint"]
+            err["dp_adjoint_vs_kkt"] = float(np.linalg.norm(c[nx:nx + npar] - b[nx:nx + npar]) /
+                                             np.linalg.norm(b[nx:nx + npar]))
         log(f"[bench] FP32+IR step vs FP64 step: {err}")
 
-    head = "fp32ir" if "fp32ir" in results else paths[0]
+    head = next((h for h in ("fp32ir_graph", "fp32ir") if h in results), paths[0])
     r = results[head]
-    peak = PEAK["fp32" if head == "fp32ir" else "fp64"]
+    peak = PEAK["fp32" if head.startswith("fp32") else "fp64"]
     roof = None
     if r["update_tflops"] is not None:
-        rec = recorded_traffic(prob.name) if head == "fp32ir" else None
+        rec = recorded_traffic(prob.name) if head.startswith("fp32") else None
         roof = {"bound": "mfma", "achieved": round(r["update_tflops"], 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(r["update_tflops"] / peak, 4),
                 "traffic": rec["bytes_per_launch"] if rec else None,
@@ -335,14 +371,15 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(r["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 factor + f64 refinement" if head == "fp32ir" else "f64",
+        "dtype": "f32 factor + f64 refinement" if head.startswith("fp32") else "f64",
         "data": "synthetic",
         "config": {"workload": prob.name, "n_x": prob.n_x, "n_p": prob.n_p, "N": N,
-                   "path": head, "solve_rtol": 1e-10},
+                   "path": head, "rhs": "KKT form [-df/dx; -df/dp; 0] (Appendix A, Theorem 2: same dp as [0; -g; 0])",
+                   "solve_rtol": 1e-10},
         "paths": results,
         "fp32_vs_fp64_step": err,
-        "speedup_fp32ir_vs_fp64": (results["fp32ir"]["steps_per_s"] / results["fp64"]["steps_per_s"]
-                                   if "fp32ir" in results and "fp64" in results else None),
+        "speedup_vs_fp64": (results[head]["steps_per_s"] / results["fp64"]["steps_per_s"]
+                            if "fp64" in results else None),
         "roofline": roof,
         "batched_2d_256": batch,
         "cpu_baseline": cpu,

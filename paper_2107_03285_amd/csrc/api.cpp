@@ -60,7 +60,7 @@ struct DevSys {
   int32_t* solve_bwd_tasks = nullptr;
   int64_t* sn_part_off = nullptr;
   double* part = nullptr;      // split-k partial sums of the forward solve
-  int* solve_ctr = nullptr;    // [2 * nlevels] ticket counters of the pipelined solve launches
+  int* solve_ctr = nullptr;    // [2 * nsn] per-front ticket counters of the forward / backward pipelined solves
   int* solve_flags = nullptr;  // [n_panels] ready flags (epoch numbers)
   int epoch = 0;
   int64_t* const_slots = nullptr;
@@ -172,6 +172,9 @@ struct sgn_ctx_s {
   hipGraphExec_t graph_exec = nullptr;
   const void* graph_key[4] = {};      // (x, p, rhs, sol) the graph was captured for
   int graph_nir = -1;
+  bool graph_prof = false;            // the graph holds event records around the update launches
+  size_t prof_nev = 0;                // event pairs of the last (or captured) factorisation
+  double prof_flops = 0.0;
   const float* pc_weights = nullptr;  // caller-owned network weights (null: corrections as set)
   bool use_own = false;               // the preconditioner reads own_cn / own_cp
   float* own_cn = nullptr;            // corrections computed by the network
@@ -283,7 +286,7 @@ size_t layout(sgn_ctx c, char* base) {
     D.vec_src = L.take<int32_t>(S.vec_src.size());
     D.solve_fwd_tasks = L.take<int32_t>(S.solve_fwd_tasks.size());
     D.solve_bwd_tasks = L.take<int32_t>(S.solve_bwd_tasks.size());
-    D.solve_ctr = L.take<int>(2 * (size_t)S.nlevels);
+    D.solve_ctr = L.take<int>(2 * (size_t)S.nsn);
     D.sn_part_off = L.take<int64_t>(S.sn_part_off.size());
     D.part = L.take<double>(S.part_total);
     D.solve_flags = L.take<int>(S.n_panels);
@@ -469,6 +472,21 @@ void residual_vec(sgn_ctx c, const double* p, double* out) {
 }
 
 // ------------------------------------------------------------------ factorisation
+// update-kernel timing of the last factorisation from its event pairs (ev_pool[0 .. prof_nev))
+sgn_status read_update_events(sgn_ctx c) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double ms = 0.0;
+  for (size_t k = 0; k < c->prof_nev; k += 2) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, c->ev_pool[k], c->ev_pool[k + 1]));
+    ms += t;
+  }
+  c->stats.update_ms = ms;
+  c->stats.update_flops = c->prof_flops;
+  c->stats.update_launches = (int64_t)(c->prof_nev / 2);
+  return SGN_OK;
+}
+
 template <typename T>
 sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
@@ -536,16 +554,9 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   }
   HIPCHK(hipGetLastError());
   if (prof) {
-    HIPCHK(hipStreamSynchronize(st));
-    double ms = 0.0;
-    for (size_t k = 0; k < nev; k += 2) {
-      float t = 0.f;
-      HIPCHK(hipEventElapsedTime(&t, c->ev_pool[k], c->ev_pool[k + 1]));
-      ms += t;
-    }
-    c->stats.update_ms = ms;
-    c->stats.update_flops = upd_flops;
-    c->stats.update_launches = (int64_t)(nev / 2);
+    c->prof_nev = nev;
+    c->prof_flops = upd_flops;
+    if (!c->capturing) TRY(read_update_events(c));  // captured events are read after each replay
   }
   launch_fill_i32(8, 0, c->d_ull, st);
   launch_inertia(S.N, D.dpiv, D.epiv, D.pivtype, c->d_ull, c->d_part, st);
@@ -634,14 +645,14 @@ sgn_status fwd_sweep_t(sgn_ctx c, int si, const double* b_new) {
   hipStream_t st = c->stream;
   const SolveArgs a = solve_args(c, si);
   const T* front = reinterpret_cast<const T*>(D.front);
-  launch_fill_i32(2 * (int64_t)S.nlevels, 0, D.solve_ctr, st);
+  launch_fill_i32(2 * (int64_t)S.nsn, 0, D.solve_ctr, st);
   if (c->capturing) launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
   int* err = c->d_cnt + 12;
   const int e_fwd = ++D.epoch;
   for (int L = 0; L < S.nlevels; ++L) {
     const LevelPlan& P = S.levels[L];
     launch_fwd_level<T>(P.sn_end - P.sn_begin, P.max_u, P.max_s, D.level_sn + P.sn_begin, D.solve_fwd_tasks + 2 * P.fwd_begin,
-                        P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr + 2 * L, D.solve_flags, e_fwd, err, st);
+                        P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr, D.solve_flags, e_fwd, err, st);
   }
   HIPCHK(hipGetLastError());
   return SGN_OK;
@@ -656,7 +667,7 @@ sgn_status bwd_sweep_t(sgn_ctx c, int si, double* x_new, const double* wd) {
   SolveArgs a = solve_args(c, si);
   a.wd = wd;
   const T* front = reinterpret_cast<const T*>(D.front);
-  launch_fill_i32(2 * (int64_t)S.nlevels, 0, D.solve_ctr, st);  // tickets start at 0
+  launch_fill_i32(2 * (int64_t)S.nsn, 0, D.solve_ctr, st);  // tickets start at 0
   // a replayed graph reuses its epochs: flags from the previous replay must not count as ready
   if (c->capturing) launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
   int* err = c->d_cnt + 12;
@@ -664,7 +675,7 @@ sgn_status bwd_sweep_t(sgn_ctx c, int si, double* x_new, const double* wd) {
   for (int L = S.nlevels - 1; L >= 0; --L) {
     const LevelPlan& P = S.levels[L];
     launch_bwd_level<T>(P.sn_end - P.sn_begin, P.max_s, D.level_sn + P.sn_begin, D.solve_bwd_tasks + 2 * P.bwd_begin,
-                        P.bwd_end - P.bwd_begin, a, front, x_new, D.solve_ctr + 2 * L + 1, D.solve_flags, e_bwd, err,
+                        P.bwd_end - P.bwd_begin, a, front, x_new, D.solve_ctr + S.nsn, D.solve_flags, e_bwd, err,
                         st);
   }
   HIPCHK(hipGetLastError());
@@ -783,7 +794,9 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
     info->ms = now_ms() - t0;
   }
   if (!(rel <= c->opt.solve_rtol)) {
-    c->err = "refinement stopped at equilibrated relative residual " + std::to_string(rel);
+    char buf[96];
+    snprintf(buf, sizeof(buf), "refinement stopped at equilibrated relative residual %.3e", rel);
+    c->err = buf;
     return SGN_E_REFINE;
   }
   return SGN_OK;
@@ -1750,7 +1763,7 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p;
   sgn_step_info si{};
   double t0 = now_ms();
-  if (c->opt.rhs_kind != SGN_RHS_ADJOINT) return fail(c, SGN_E_ARG, "sgn_step uses the adjoint right-hand side");
+  const bool kkt = c->opt.rhs_kind == SGN_RHS_KKT;
   if (!c->kx_valid) {
     sgn_status s = equilibrium_impl(c, d_p, d_x, nullptr);
     if (s != SGN_OK) return fail(c, s, c->err);
@@ -1759,7 +1772,7 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   double* rhs = c->d_srhs;
   double* sol = c->d_ssol;
   {
-    sgn_status s = assemble_impl(c, d_x, d_p, rhs, c->d_g, &f0);
+    sgn_status s = assemble_impl(c, d_x, d_p, rhs, kkt ? nullptr : c->d_g, &f0);
     if (s != SGN_OK) return fail(c, s, c->err);
   }
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1782,16 +1795,24 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   }
   double t3 = now_ms();
   si.ms_solve = t3 - t2;
-  // dp = sol[nx : nx+np]; g^T dp and |g|
-  dev_dot(c, np, c->d_g, sol + nx, 12);
-  dev_dot(c, np, c->d_g, c->d_g, 13);
+  // slope g^T dp: adjoint form from g; KKT form as df/dx dx + df/dp dp, equal because the step
+  // satisfies Kx dx + Kp dp = 0 and g = df/dp^T + Kp^T lam with Kx^T lam = -df/dx^T
   double v[2];
-  {
+  if (kkt) {
+    dev_dot(c, nx, c->d_fx, sol, 12);
+    dev_dot(c, np, c->d_fp, sol + nx, 13);
+    sgn_status s = read_scalars(c, 12, 2, v);
+    if (s != SGN_OK) return s;
+    v[0] += v[1];
+    v[1] = -1.0;
+  } else {
+    dev_dot(c, np, c->d_g, sol + nx, 12);
+    dev_dot(c, np, c->d_g, c->d_g, 13);
     sgn_status s = read_scalars(c, 12, 2, v);
     if (s != SGN_OK) return s;
   }
   const double gtdp = v[0];
-  si.grad_norm = std::sqrt(v[1]);
+  si.grad_norm = v[1] >= 0.0 ? std::sqrt(v[1]) : -1.0;
   si.gtdp = gtdp;
   si.f0 = f0;
   // backtracking with one equilibrium per trial
@@ -1974,10 +1995,19 @@ sgn_status sgn_graph_step(sgn_ctx c, const double* d_x, const double* d_p, doubl
     if (c->graph) HIPCHK(hipGraphDestroy(c->graph));
     c->graph_exec = nullptr;
     c->graph = nullptr;
-    const int keep_prof = c->opt.profile;
-    c->opt.profile = 0;
     c->stream = c->gstream;
     c->capturing = true;
+    if (c->opt.profile) {  // create the update events before capture; their records become graph nodes
+      size_t need = 0;
+      for (const LevelPlan& P : c->A.sgn.levels)
+        for (const PanelStep& ps : P.steps) need += 2 * ((ps.upd_tiles > 0) + (ps.outer_tiles > 0));
+      hipError_t e0 = ensure_events(c, need);
+      if (e0 != hipSuccess) {
+        c->capturing = false;
+        c->stream = user;
+        return fail(c, SGN_E_HIP, std::string("events: ") + hipGetErrorString(e0));
+      }
+    }
     sgn_status s = SGN_OK;
     hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -1989,7 +2019,7 @@ sgn_status sgn_graph_step(sgn_ctx c, const double* d_x, const double* d_p, doubl
     }
     c->capturing = false;
     c->stream = user;
-    c->opt.profile = keep_prof;
+    c->graph_prof = c->opt.profile != 0;
     if (s != SGN_OK) return s;
     if (e != hipSuccess) return fail(c, SGN_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     HIPCHK(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
@@ -2004,6 +2034,13 @@ sgn_status sgn_graph_step(sgn_ctx c, const double* d_x, const double* d_p, doubl
   HIPCHK(hipMemcpyAsync(cnt, c->d_cnt, 16 * sizeof(int), hipMemcpyDeviceToHost, c->gstream));
   HIPCHK(hipStreamSynchronize(c->gstream));
   c->stats.solve_ms = now_ms() - t0;
+  if (c->graph_prof) {
+    hipStream_t keep = c->stream;
+    c->stream = c->gstream;
+    const sgn_status s = read_update_events(c);
+    c->stream = keep;
+    TRY(s);
+  }
   c->sys[0].factored = true;
   c->sys[0].current = true;
   c->sgn_assembled = true;
@@ -2014,7 +2051,9 @@ sgn_status sgn_graph_step(sgn_ctx c, const double* d_x, const double* d_p, doubl
     return SGN_E_INVERTED;
   }
   if (out[1] != 1.0) {
-    c->err = "fixed refinement stopped at equilibrated relative residual " + std::to_string(out[0]);
+    char buf[96];
+    snprintf(buf, sizeof(buf), "fixed refinement stopped at equilibrated relative residual %.3e", out[0]);
+    c->err = buf;
     return SGN_E_REFINE;
   }
   return SGN_OK;

@@ -189,8 +189,27 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
       const double id = 1.0 / d;
       if (lane > k && lane < w) {
         const double li = A[lane][k] * id;
-        for (int j = k + 1 + wave; j < w; j += 4) A[lane][j] -= li * A[j][k];  // Schur complement
-        for (int j = wave; j < k; j += 4) A[j][lane] -= li * A[j][k];        // X <- L_k^-1 X
+        // Schur complement and X <- L_k^-1 X; four columns per round keep four LDS loads in flight
+        int j = k + 1 + wave;
+        for (; j + 12 < w; j += 16) {
+          const double b0 = A[j][k], b1 = A[j + 4][k], b2 = A[j + 8][k], b3 = A[j + 12][k];
+          const double a0 = A[lane][j], a1 = A[lane][j + 4], a2 = A[lane][j + 8], a3 = A[lane][j + 12];
+          A[lane][j] = a0 - li * b0;
+          A[lane][j + 4] = a1 - li * b1;
+          A[lane][j + 8] = a2 - li * b2;
+          A[lane][j + 12] = a3 - li * b3;
+        }
+        for (; j < w; j += 4) A[lane][j] -= li * A[j][k];
+        j = wave;
+        for (; j + 12 < k; j += 16) {
+          const double b0 = A[j][k], b1 = A[j + 4][k], b2 = A[j + 8][k], b3 = A[j + 12][k];
+          const double a0 = A[j][lane], a1 = A[j + 4][lane], a2 = A[j + 8][lane], a3 = A[j + 12][lane];
+          A[j][lane] = a0 - li * b0;
+          A[j + 4][lane] = a1 - li * b1;
+          A[j + 8][lane] = a2 - li * b2;
+          A[j + 12][lane] = a3 - li * b3;
+        }
+        for (; j < k; j += 4) A[j][lane] -= li * A[j][k];
       }
       __syncthreads();
       if (tid > k && tid < w) {
@@ -212,8 +231,32 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
       if (lane > k + 1 && lane < w) {
         const double ui0 = A[lane][k], ui1 = A[lane][k + 1];
         const double l0 = ui0 * i00 + ui1 * i01, l1 = ui0 * i01 + ui1 * i11;
-        for (int j = k + 2 + wave; j < w; j += 4) A[lane][j] -= l0 * A[j][k] + l1 * A[j][k + 1];
-        for (int j = wave; j < k; j += 4) A[j][lane] -= l0 * A[j][k] + l1 * A[j][k + 1];
+        int j = k + 2 + wave;
+        for (; j + 12 < w; j += 16) {
+          double b0[4], b1[4], a[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            b0[q] = A[j + 4 * q][k];
+            b1[q] = A[j + 4 * q][k + 1];
+            a[q] = A[lane][j + 4 * q];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) A[lane][j + 4 * q] = a[q] - (l0 * b0[q] + l1 * b1[q]);
+        }
+        for (; j < w; j += 4) A[lane][j] -= l0 * A[j][k] + l1 * A[j][k + 1];
+        j = wave;
+        for (; j + 12 < k; j += 16) {
+          double b0[4], b1[4], a[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            b0[q] = A[j + 4 * q][k];
+            b1[q] = A[j + 4 * q][k + 1];
+            a[q] = A[j + 4 * q][lane];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) A[j + 4 * q][lane] = a[q] - (l0 * b0[q] + l1 * b1[q]);
+        }
+        for (; j < k; j += 4) A[j][lane] -= l0 * A[j][k] + l1 * A[j][k + 1];
       }
       __syncthreads();
       if (tid > k + 1 && tid < w) {

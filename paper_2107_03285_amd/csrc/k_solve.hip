@@ -19,9 +19,10 @@
 //      preconditioner supplies its own block solve of D in place of D^-1 y;
 //   B2 (one block per panel, pipelined in reverse): z_R -= sum_{Q>R} L_QR^T v_Q,
 //      solve the panel's L^T block, undo its permutation.
-// Pipelined blocks take ordered tickets from an atomic counter, so a block
-// only ever waits for blocks that started before it; every wait is bounded
-// and reports a timeout through an error flag instead of hanging.  Vectors
+// Pipelined blocks take ordered tickets from their front's atomic counter, so
+// a block only ever waits for blocks of its front that started before it;
+// every wait is bounded and reports a timeout through an error flag instead of
+// hanging.  Vectors
 // are FP64 whatever the factor precision, and every sum has a fixed order,
 // so solves are bitwise reproducible.
 #include <hip/hip_runtime.h>
@@ -89,9 +90,11 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
   __shared__ double part[4][64];
   __shared__ double Ld[64][65];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int t = ticket(counter);
-  if (t >= ntasks) return;
-  const int J = tasks[2 * t], pi = tasks[2 * t + 1];
+  if (blockIdx.x >= ntasks) return;
+  // the task list holds one entry per panel of each front; the block serves that front and takes
+  // the front's next panel in start order, so it only ever waits for blocks that started before it
+  const int J = tasks[2 * blockIdx.x];
+  const int pi = ticket(counter + J);
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], m = f.sn_m[J];
   const int32_t pbase = a.panel_ptr[J];
@@ -137,36 +140,40 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
   }
 }
 
-// Split-k partial sums of L21 y: block (front, 64-row chunk, k-chunk of kSolveKC columns);
-// wave w takes 64 of the chunk's columns, lane = row, the four waves are summed in order.
+// Split-k partial sums of L21 y: block (front, 256-row strip, k-chunk of 256 columns), one row per
+// thread; each column of the strip is one contiguous 1 KB (FP32) piece, read 64 columns at a time
+// with all loads in flight; the sum over k runs in ascending order.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_rect(const int32_t* __restrict__ level_sn, SolveArgs a,
                                                   const T* __restrict__ front) {
-  __shared__ double red[4][64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int J = level_sn[blockIdx.x];
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J], u = m - s;
-  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int64_t r0 = (int64_t)blockIdx.y * 256;
   const int64_t kb = (int64_t)blockIdx.z * 256;
   if (r0 >= u || kb >= s) return;
   const double* tp = a.tp + a.sn_vec_off[J];
   const T* F = front + f.sn_front_off[J];
-  const int64_t r = r0 + lane;
-  const int64_t k0 = kb + 64 * wave;
-  const int nk = k0 >= s ? 0 : (int)((s - k0) < 64 ? (s - k0) : 64);
-  const T* rowp = F + s + (r < u ? r : 0) + k0 * m;
-  double fv[64];
-#pragma unroll
-  for (int k = 0; k < 64; ++k) fv[k] = (k < nk && r < u) ? (double)rowp[(int64_t)k * m] : 0.0;
-  const double tk = lane < nk ? tp[k0 + lane] : 0.0;
+  const int64_t r = r0 + tid;
+  const int64_t kend = kb + 256 < s ? kb + 256 : s;
+  const T* rowp = F + s + (r < u ? r : 0);
   double acc = 0.0;
+#pragma unroll 1
+  for (int64_t k0 = kb; k0 < kend; k0 += 64) {
+    const int nk = (int)(kend - k0 < 64 ? kend - k0 : 64);
+    const double tk = lane < nk ? tp[k0 + lane] : 0.0;
+    const T* cp = rowp + k0 * m;
+#pragma unroll 1
+    for (int kk = 0; kk < 64; kk += 16) {  // 16 loads in flight per lane keep the register count low
+      T fv[16];
 #pragma unroll
-  for (int k = 0; k < 64; ++k) acc += fv[k] * __shfl(tk, k, 64);
-  red[wave][lane] = acc;
-  __syncthreads();
-  if (wave == 0 && r < u)
-    a.part[a.sn_part_off[J] + blockIdx.z * u + r] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+      for (int k = 0; k < 16; ++k) fv[k] = (kk + k < nk && r < u) ? cp[(int64_t)(kk + k) * m] : (T)0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += (double)fv[k] * __shfl(tk, kk + k, 64);
+    }
+  }
+  if (r < u) a.part[a.sn_part_off[J] + blockIdx.z * u + r] = acc;
 }
 
 // t_u = tv_u - sum over k-chunks (ascending) of the partial sums
@@ -234,13 +241,13 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
   __shared__ double part[4][64];
   __shared__ double Ld[64][65];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int t = ticket(counter);
-  if (t >= ntasks) return;
-  const int J = tasks[2 * t], pi = tasks[2 * t + 1];
+  if (blockIdx.x >= ntasks) return;
+  const int J = tasks[2 * blockIdx.x];
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], m = f.sn_m[J];
   const int32_t pbase = a.panel_ptr[J];
   const int np = a.panel_ptr[J + 1] - pbase - 1;
+  const int pi = np - 1 - ticket(counter + J);  // the front's panels in reverse start order
   const int c0 = a.panel_col[pbase + pi], c1 = a.panel_col[pbase + pi + 1], w = c1 - c0;
   const double* tv = a.tv + a.sn_vec_off[J];
   const T* F = front + f.sn_front_off[J];
@@ -290,7 +297,7 @@ void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* 
   if (ntasks > 0) k_fwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, counter, flags, epoch, err);
   if (max_u > 0) {
     if (max_s > 0) {
-      dim3 g((unsigned)nsn, (unsigned)((max_u + 63) / 64), (unsigned)((max_s + 255) / 256));
+      dim3 g((unsigned)nsn, (unsigned)((max_u + 255) / 256), (unsigned)((max_s + 255) / 256));
       k_fwd_rect<T><<<g, 256, 0, s>>>(level_sn, a, front);
     }
     dim3 g2((unsigned)nsn, (unsigned)((max_u + 255) / 256));

@@ -119,9 +119,10 @@ struct SolveArgs {
   double* tp;  // per-front permuted working vectors
   const double* wd;  // null: the backward solve applies D^-1; else it takes D^-1 y from here (pivot order)
 };
-// One tree level of the forward / backward solve.  tasks: (front, panel) pairs in
-// pipeline order; counter: zeroed ticket counter of this launch; flags: per-panel
-// ready flags compared against epoch; err: set when a bounded wait runs out.
+// One tree level of the forward / backward solve.  tasks: (front, panel) pairs, one per panel of
+// each front of the level (the block serves the front, the panel comes from the front's ticket);
+// counter: zeroed per-front ticket counters [nsn]; flags: per-panel ready flags compared against
+// epoch; err: set when a bounded wait runs out.
 template <typename T>
 void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
                       const SolveArgs& a, const T* front, const double* b, int* counter, int* flags, int epoch,
