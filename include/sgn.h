@@ -187,7 +187,9 @@ sgn_status sgn_solve(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_
  * acceptance f(alpha) <= f(0) + 1e-4 alpha g^T dp.  (d_p, d_x) must be an
  * equilibrium on entry and are updated in place.  With rhs_kind = SGN_RHS_KKT
  * the step needs no adjoint solve (same dp, Appendix A, Theorem 2) and the
- * slope is df/dx dx + df/dp dp; info->grad_norm is then -1. */
+ * slope is df/dx dx + df/dp dp; info->grad_norm is then -1.  When every
+ * trial fails while |g^T dp| <= 1e-12 |f(0)| (stationary to working
+ * precision) the call succeeds with alpha = 0 and leaves (p, x) unchanged. */
 sgn_status sgn_step(sgn_ctx ctx, double* d_p, double* d_x, sgn_step_info* info);
 
 /* ---- Learned-preconditioner path.  The paper names preconditioning of the

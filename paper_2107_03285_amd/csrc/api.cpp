@@ -1840,8 +1840,16 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
     ++si.halvings;
   }
   si.ms_linesearch = now_ms() - t3;
-  si.alpha = alpha;
   si.newton_iters = nt_iters;
+  if (!ok && std::fabs(gtdp) <= 1e-12 * std::fabs(f0)) {
+    // the predicted decrease of the whole step is below the objective's rounding: the iterate is
+    // stationary to working precision and Armijo decisions are noise; stay (alpha = 0)
+    si.alpha = 0.0;
+    si.f1 = f0;
+    if (info) *info = si;
+    return SGN_OK;
+  }
+  si.alpha = alpha;
   if (info) *info = si;
   if (!ok) {
     c->kx_valid = false;

@@ -11,14 +11,16 @@
 //      and the children's contribution vectors (fixed child order);
 //   F1 (one block per panel, pipelined): t_R -= sum_{Q<R} L_RQ y_Q as soon as
 //      each earlier panel Q of the same front has published y_Q, then permute
-//      and solve the panel's unit lower block in one wavefront;
+//      and multiply by the inverse of the panel's unit lower block (kept by the
+//      factorisation), one wavefront;
 //   F2 (many blocks per front): contribution to the parent, t_u - L21 y.
 // Backward (root to leaves):
 //   B1 (many blocks per front): z = D^-1 y - L21^T v_u, one wavefront per
 //      column, v_u read from the solution vector (ancestors are solved); a
 //      preconditioner supplies its own block solve of D in place of D^-1 y;
 //   B2 (one block per panel, pipelined in reverse): z_R -= sum_{Q>R} L_QR^T v_Q,
-//      solve the panel's L^T block, undo its permutation.
+//      multiply by the transposed inverse of the panel's block, undo its
+//      permutation.
 // Pipelined blocks take ordered tickets from their front's atomic counter, so
 // a block only ever waits for blocks of its front that started before it;
 // every wait is bounded and reports a timeout through an error flag instead of
@@ -102,11 +104,16 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
   const double* tv = a.tv + a.sn_vec_off[J];
   double* tp = a.tp + a.sn_vec_off[J];
   const T* F = front + f.sn_front_off[J];
-  // the panel's own block does not depend on other panels: load it before waiting
+  // the panel's own block does not depend on other panels: load it before waiting.  The factor keeps
+  // the inverse of the panel's unit lower block in the diagonal block's upper triangle, transposed:
+  // Ld[j][i] = (L11^-1)[i][j] for j < i
   for (int idx = tid; idx < w * w; idx += 256) {
     const int i = idx % w, j = idx / w;
-    Ld[i][j] = i > j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
+    Ld[i][j] = i < j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
   }
+  // values of this panel that no other panel produces: read before any wait
+  const double tvl = lane < w ? tv[c0 + lane] : 0.0;
+  const int src = lane < w ? f.lperm[g0 + c0 + lane] - c0 : 0;
   // contributions of the earlier panels, panel Q handled by wave Q % 4
   double acc = 0.0;
   const T* rowbase = F + (c0 + (lane < w ? lane : 0));
@@ -126,14 +133,15 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
   part[wave][lane] = acc;
   __syncthreads();
   if (wave == 0) {
-    // u in original row order, then the panel permutation, then the unit lower solve
+    // u in original row order, then the panel permutation, then y = L11^-1 (P u): independent
+    // products instead of a dependent substitution
     double u = 0.0;
-    if (lane < w) u = tv[c0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
-    const int src = lane < w ? f.lperm[g0 + c0 + lane] - c0 : 0;
-    double y = __shfl(u, src, 64);
-    for (int k = 0; k < w; ++k) {
-      const double yk = __shfl(y, k, 64);
-      if (lane > k && lane < w) y -= Ld[lane][k] * yk;
+    if (lane < w) u = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    const double z = __shfl(u, src, 64);
+    double y = z;
+    for (int j = 0; j < w; ++j) {
+      const double zj = __shfl(z, j, 64);
+      if (j < lane) y += Ld[j][lane] * zj;
     }
     if (lane < w) tp[c0 + lane] = y;
     if (lane == 0) publish(flags + pbase + pi, epoch);
@@ -251,10 +259,12 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
   const int c0 = a.panel_col[pbase + pi], c1 = a.panel_col[pbase + pi + 1], w = c1 - c0;
   const double* tv = a.tv + a.sn_vec_off[J];
   const T* F = front + f.sn_front_off[J];
-  for (int idx = tid; idx < w * w; idx += 256) {
+  for (int idx = tid; idx < w * w; idx += 256) {  // Ld[i][j] = (L11^-1)[j][i] for i < j (see the forward solve)
     const int i = idx % w, j = idx / w;
-    Ld[i][j] = i > j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
+    Ld[i][j] = i < j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
   }
+  const double tvl = lane < w ? tv[c0 + lane] : 0.0;  // read before any wait
+  const int dst = lane < w ? f.lperm[g0 + c0 + lane] : 0;
   // contributions of the later panels Q (every fourth one per wave, in the order they are
   // solved): lane = column c0+lane of panel R, summing L[q0 + k', c0 + lane] v[q0 + k']
   double acc = 0.0;
@@ -276,12 +286,13 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
   __syncthreads();
   if (wave == 0) {
     double z = 0.0;
-    if (lane < w) z = tv[c0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
-    for (int k = w - 1; k >= 0; --k) {
-      const double vk = __shfl(z, k, 64);
-      if (lane < k) z -= Ld[k][lane] * vk;
+    if (lane < w) z = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    double v = z;  // v = L11^-T z
+    for (int j = 0; j < w; ++j) {
+      const double zj = __shfl(z, j, 64);
+      if (j > lane) v += Ld[lane][j] * zj;
     }
-    if (lane < w) x[g0 + f.lperm[g0 + c0 + lane]] = z;
+    if (lane < w) x[g0 + dst] = v;
     if (lane == 0) publish(flags + pbase + pi, epoch);
   }
 }

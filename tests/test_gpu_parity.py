@@ -217,26 +217,27 @@ def test_factor_and_solve_are_bitwise_reproducible():
     assert np.array_equal(sols[0].view(np.uint64), sols[1].view(np.uint64))
 
 
-def test_outer_iterations_kkt_rhs_match_adjoint():
-    """sgn_step with the KKT right-hand side (no adjoint solve) follows the adjoint-form trajectory:
-    same dp (Appendix A, Theorem 2), same slope, hence the same step lengths."""
+def test_outer_step_kkt_rhs_matches_adjoint():
+    """sgn_step with the KKT right-hand side (no adjoint solve) takes the adjoint-form step: same dp
+    (Appendix A, Theorem 2), same slope, hence the same step length and new iterate.  Compared one
+    step at a time from two states (along a trajectory a borderline Armijo trial can be decided by
+    rounding differently by the two forms)."""
     prob = D.setup_targets(si.problem_3d(4, 2, 2, 0.25, seed=1))
-    out = {}
-    for kind in (sgn.SGN_RHS_ADJOINT, sgn.SGN_RHS_KKT):
-        ctx = _ctx(prob, rhs_kind=kind)
-        p = _cuda(prob.p_init())
-        x = _cuda(prob.x_rest())
-        ctx.equilibrium(p, x)
-        tr = []
-        for _ in range(3):
+    rng = np.random.default_rng(4)
+    for p_start in (prob.p_init(), prob.p_init() + 0.05 * rng.standard_normal(prob.n_p)):
+        out = {}
+        for kind in (sgn.SGN_RHS_ADJOINT, sgn.SGN_RHS_KKT):
+            ctx = _ctx(prob, rhs_kind=kind)
+            p = _cuda(p_start)
+            x = _cuda(prob.x_rest())
+            ctx.equilibrium(p, x)
             info = ctx.step(p, x)
-            tr.append((info.alpha, info.gtdp, info.f1))
-        out[kind] = (tr, _host(p))
-    (ta, pa), (tk, pk) = out[sgn.SGN_RHS_ADJOINT], out[sgn.SGN_RHS_KKT]
-    assert [a for a, _, _ in ta] == [a for a, _, _ in tk]
-    assert np.allclose([g for _, g, _ in ta], [g for _, g, _ in tk], rtol=1e-8)
-    assert np.allclose([f for _, _, f in ta], [f for _, _, f in tk], rtol=1e-10)
-    assert np.linalg.norm(pk - pa) <= 1e-8 * np.linalg.norm(pa)
+            out[kind] = (info.alpha, info.gtdp, info.f1, _host(p))
+        (aa, ga, fa, pa), (ak, gk, fk, pk) = out[sgn.SGN_RHS_ADJOINT], out[sgn.SGN_RHS_KKT]
+        assert aa == ak
+        assert abs(ga - gk) <= 1e-8 * abs(ga)
+        assert abs(fa - fk) <= 1e-10 * abs(fa)
+        assert np.linalg.norm(pk - pa) <= 1e-8 * np.linalg.norm(pa - p_start)
 
 
 def test_nodal_force_parameters_closed_form_step():
