@@ -385,6 +385,9 @@ def sgn_iterations(prob: Problem, p: np.ndarray, x: np.ndarray, iters: int = 10,
 
     Armijo acceptance f(a) <= f(0) + c1 a g^T dp, halving a (a reading: the
     paper only states that steps are accepted or rejected by the objective).
+    When every trial fails while the predicted decrease |g^T dp| is below
+    1e-12 |f(0)| the iterate is stationary to working precision (the Armijo
+    test compares rounding noise) and the iteration stays put (alpha = 0).
     Returns the trace [(f, |g|, alpha)] and the final (p, x).
     """
     trace = []
@@ -402,7 +405,10 @@ def sgn_iterations(prob: Problem, p: np.ndarray, x: np.ndarray, iters: int = 10,
                     break
             a *= 0.5
         else:
-            raise RuntimeError("line search failed")
+            if abs(slope) > 1e-12 * abs(f0):
+                raise RuntimeError("line search failed")
+            trace.append((f0, float(np.linalg.norm(st.grad)), 0.0))
+            continue
         trace.append((f0, float(np.linalg.norm(st.grad)), a))
         p, x = pt, xt
     return trace, p, x
