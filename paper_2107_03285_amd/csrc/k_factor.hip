@@ -32,6 +32,22 @@ constexpr double kAlphaBK = 0.6403882032022076;  // (1 + sqrt(17)) / 8
 // and B[lane/16][lane%16] for both types, the column is lane%16.  Measured on
 // gfx950 (the self-test entry point checks it): the FP64 product interleaves
 // rows across registers, the FP32 one keeps four consecutive rows per lane.
+// Raw buffer loads: a per-lane 32-bit byte offset plus a uniform one from a uniform base held in a
+// buffer resource of `bytes` bytes (offsets at or past it read 0; 0x00020000 is the gfx9 descriptor
+// word 3 for untyped dword access).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ inline rsrc_t buffer_rsrc(const void* p, int32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline T buffer_load(rsrc_t r, uint32_t voff, int32_t soff) {
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+  }
+}
+
 template <typename T>
 __device__ inline int mfma_row(int lane, int reg) {
   return sizeof(T) == 8 ? (lane >> 4) + 4 * reg : 4 * (lane >> 4) + reg;
@@ -412,11 +428,21 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   // 64 x 64 tile per block, 32 x 32 per wave (2 x 2 MFMA blocks of 16 x 16); the next k-chunk's loads
   // are in flight while the current one runs on the matrix cores.  (A 128 x 128 tile halves the
   // loads per flop but its register footprint halves the occupancy, which measured slower.)
+  // The sum over k is taken in a permuted order: at step s of a chunk, lanes 16 g .. 16 g + 15 feed
+  // k = (KC/4) g + s to both operands, so each lane reads its KC/4 W values of a chunk with 16-byte
+  // LDS loads.
   constexpr int TM = kUpdTile;
-  constexpr int KC = 32;
-  constexpr int NQ = TM * KC / 256;  // loads per thread and chunk, each of L and W
-  __shared__ T sL[KC][TM + 4];
-  __shared__ T sW[KC][TM + 4];
+  constexpr int KC = sizeof(T) == 8 ? 16 : 32;  // k per chunk (FP64 halves it to keep the occupancy)
+  constexpr int KS = KC / 4;                  // MFMA steps per chunk
+  constexpr int NQ = TM * KC / 256;           // loads per thread and chunk, each of L and W
+  constexpr int CQ = 256 / KC;                // W columns covered by one load instruction of the block
+  // sL rows KS apart (one lane group to the next) start 16 (FP32) or 32 (FP64) banks apart
+  constexpr int SL = sizeof(T) == 8 ? TM + 4 : TM + 2;
+  constexpr int SW = KC + 16 / (int)sizeof(T);  // 16-byte rows; 16 lanes reading 16 B each cover all banks
+  constexpr int VW = 16 / (int)sizeof(T);     // elements per 16-byte LDS read
+  typedef T vecw __attribute__((ext_vector_type(VW)));
+  __shared__ T sL[KC][SL];                    // sL[k][r]
+  __shared__ __attribute__((aligned(16))) T sW[TM][SW];  // sW[c][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.x;
   int64_t lo = 0, hi = ntasks - 1;
@@ -432,16 +458,51 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   int64_t lt = b - tk[5];
   const int64_t R = (m - cb + TM - 1) / TM;
   const int64_t ct = (ce - cb + TM - 1) / TM;
-  int64_t j = 0;
-  while (j < ct && lt >= R - j) {
-    lt -= R - j;
-    ++j;
-  }
+  // Tiles run column block by column block, rows j .. R-1 in column block j, so S(j) = j R - j (j-1) / 2
+  // tiles precede column block j; j is the root of S(j) = lt rounded down, corrected for rounding.
+  auto S = [R](int64_t jj) { return jj * R - jj * (jj - 1) / 2; };
+  const double b2 = 2.0 * (double)R + 1.0;
+  int64_t j = (int64_t)(0.5 * (b2 - sqrt(fmax(0.0, b2 * b2 - 8.0 * (double)lt))));
+  if (j < 0) j = 0;
+  if (j > ct) j = ct;
+  while (j > 0 && S(j) > lt) --j;
+  while (j < ct && S(j + 1) <= lt) ++j;
   if (j >= ct) return;  // beyond the task's tiles (never for a consistent schedule)
-  const int64_t i = j + lt;
+  const int64_t i = j + (lt - S(j));
   const int64_t r0 = cb + TM * i, cc0 = cb + TM * j;
   T* F = front + f.sn_front_off[sn];
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int64_t cmax = ce < m ? ce : m;
+  // Loads: L entries (r0 + rr, kb + kl + 4 q) and W^T entries (kb + kw, cc0 + cw + CQ q), as one
+  // per-thread byte offset from a per-chunk base plus a uniform per-q stride.  Rows and columns past
+  // the tile's end land on other entries of the front (finite; they only feed outputs that are not
+  // stored) or past its end, where the buffer's range check returns 0.
+  const int rr = tid & 63, kl = tid >> 6, kw = tid % KC, cw = tid / KC;
+  const int64_t szT = (int64_t)sizeof(T);
+  const uint32_t offL = (uint32_t)((r0 + rr + (int64_t)kl * m) * szT);
+  const uint32_t offW = (uint32_t)((kw + (int64_t)cw * m) * szT);
+  const int32_t strL = (int32_t)(4 * m * szT), strW = (int32_t)(CQ * m * szT);
+  const int64_t fend = m * m;  // entries in the front
+  auto range = [&](int64_t base) -> int32_t {
+    const int64_t bytes = (fend - base) * szT;
+    return bytes >= 0xffffffffll ? (int32_t)-1 : (int32_t)bytes;
+  };
+  T rl[NQ], rw[NQ];
+  auto load = [&](int64_t kb) {
+    const rsrc_t bL = buffer_rsrc(F + kb * m, range(kb * m));
+    const rsrc_t bW = buffer_rsrc(F + kb + cc0 * m, range(kb + cc0 * m));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      rl[q] = buffer_load<T>(bL, offL, q * strL);
+      rw[q] = buffer_load<T>(bW, offW, q * strW);
+    }
+    if (kb + KC > k1 && kw >= (int)(k1 - kb)) {
+      // last, partial chunk: k >= k1 contributes zero (its L entries are finite front entries, or 0
+      // past the front's end, so zeroing the W side suffices)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) rw[q] = (T)0;
+    }
+  };
   dbl4 accd[2][2];
   flt4 accf[2][2];
 #pragma unroll
@@ -451,49 +512,38 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
       accd[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
       accf[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
     }
-  const int64_t cmax = ce < m ? ce : m;
-  // per thread NQ entries of the L chunk (TM consecutive rows of one column) and NQ of the W^T chunk
-  // (KC consecutive k of one column)
-  T rl[NQ], rw[NQ];
-  auto load = [&](int64_t kb) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int idx = tid + 256 * q;
-      {
-        const int rr = idx % TM, kk = idx / TM;
-        const int64_t k = kb + kk, r = r0 + rr;
-        rl[q] = (k < k1 && r < m) ? F[r + k * m] : (T)0;
-      }
-      {
-        const int kk = idx % KC, cc = idx / KC;
-        const int64_t k = kb + kk, c = cc0 + cc;
-        rw[q] = (k < k1 && c < cmax) ? F[k + c * m] : (T)0;
-      }
-    }
-  };
+  const int g = lane >> 4, li = lane & 15;
   load(k0);
   for (int64_t kb = k0; kb < k1; kb += KC) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int idx = tid + 256 * q;
-      sL[idx / TM][idx % TM] = rl[q];
-      sW[idx % KC][idx / KC] = rw[q];
+      sL[kl + 4 * q][rr] = rl[q];
+      sW[cw + CQ * q][kw] = rw[q];
     }
     __syncthreads();
     if (kb + KC < k1) load(kb + KC);
+    T aw[2][KS];
 #pragma unroll
-    for (int k4 = 0; k4 < KC / 4; ++k4) {
-      const int kr = k4 * 4 + (lane >> 4);
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < KS / VW; ++v) {
+        const vecw x = *(const vecw*)&sW[wc + bj * 16 + li][KS * g + VW * v];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) aw[bj][VW * v + e] = x[e];
+      }
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      T bv[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) bv[bi] = sL[KS * g + st][wr + bi * 16 + li];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          const T av = sW[kr][wc + bj * 16 + (lane & 15)];
-          const T bv = sL[kr][wr + bi * 16 + (lane & 15)];
           if constexpr (sizeof(T) == 8) {
-            accd[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accd[bi][bj], 0, 0, 0);
+            accd[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[bj][st], bv[bi], accd[bi][bj], 0, 0, 0);
           } else {
-            accf[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, accf[bi][bj], 0, 0, 0);
+            accf[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[bj][st], bv[bi], accf[bi][bj], 0, 0, 0);
           }
         }
     }
