@@ -44,11 +44,23 @@ __device__ inline int ticket(int* counter) {
   return t;
 }
 
+// Panel results pass between blocks of one launch through device-coherent accesses only: the
+// producer writes them with device-scope atomic stores (written through the per-die caches), waits
+// for their completion and then sets the panel's flag; the consumer polls the flag and reads them
+// with device-scope atomic loads.  No whole-cache write-back or invalidation is needed, so blocks
+// that wait do not evict the factor data other blocks are streaming.
+__device__ inline double ld_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // true once flag == epoch; false (and err set) when the bounded wait runs out or an
 // earlier wait of the same solve already timed out (so a failure ends every wait fast)
 __device__ inline bool wait_ready(const int* flag, int epoch, int* err) {
   for (long it = 0; it < kSpinLimit; ++it) {
-    if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch) return true;
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) return true;
     if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     __builtin_amdgcn_s_sleep(2);
   }
@@ -56,9 +68,13 @@ __device__ inline bool wait_ready(const int* flag, int epoch, int* err) {
   return false;
 }
 
-__device__ inline void publish(int* flag, int epoch) {
-  __threadfence();
-  __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Called by the whole wavefront after its st_dev stores of the panel: waits until they have
+// completed, then the leader lane sets the flag.
+__device__ inline void publish(int* flag, int epoch, bool leader) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (leader) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -120,15 +136,15 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
   for (int q = wave; q < pi; q += 4) {
     const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
     // the factor entries do not depend on the other panel: issue their loads first
-    double fv[64];
+    T fv[64];  // factor precision in registers, widened at use
 #pragma unroll
-    for (int k = 0; k < 64; ++k) fv[k] = (k < nq && lane < w) ? (double)rowbase[(int64_t)(q0 + k) * m] : 0.0;
+    for (int k = 0; k < 64; ++k) fv[k] = (k < nq && lane < w) ? rowbase[(int64_t)(q0 + k) * m] : (T)0;
     if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
     __builtin_amdgcn_wave_barrier();
-    __threadfence();
-    const double tk = lane < nq ? tp[q0 + lane] : 0.0;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const double tk = lane < nq ? ld_dev(tp + q0 + lane) : 0.0;
 #pragma unroll
-    for (int k = 0; k < 64; ++k) acc += fv[k] * __shfl(tk, k, 64);
+    for (int k = 0; k < 64; ++k) acc += (double)fv[k] * __shfl(tk, k, 64);
   }
   part[wave][lane] = acc;
   __syncthreads();
@@ -143,8 +159,8 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
       const double zj = __shfl(z, j, 64);
       if (j < lane) y += Ld[j][lane] * zj;
     }
-    if (lane < w) tp[c0 + lane] = y;
-    if (lane == 0) publish(flags + pbase + pi, epoch);
+    if (lane < w) st_dev(tp + c0 + lane, y);
+    publish(flags + pbase + pi, epoch, lane == 0);
   }
 }
 
@@ -272,15 +288,15 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
   for (int q = np - 1 - wave; q > pi; q -= 4) {  // completion order: last panel first
     const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
     const T* col = colbase + q0;
-    double fv[64];
+    T fv[64];  // factor precision in registers, widened at use
 #pragma unroll
-    for (int kk = 0; kk < 64; ++kk) fv[kk] = (kk < nq && lane < w) ? (double)col[kk] : 0.0;
+    for (int kk = 0; kk < 64; ++kk) fv[kk] = (kk < nq && lane < w) ? col[kk] : (T)0;
     if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
     __builtin_amdgcn_wave_barrier();
-    __threadfence();
-    const double vl = lane < nq ? x[g0 + q0 + lane] : 0.0;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const double vl = lane < nq ? ld_dev(x + g0 + q0 + lane) : 0.0;
 #pragma unroll
-    for (int kk = 0; kk < 64; ++kk) acc += fv[kk] * __shfl(vl, kk, 64);
+    for (int kk = 0; kk < 64; ++kk) acc += (double)fv[kk] * __shfl(vl, kk, 64);
   }
   part[wave][lane] = acc;
   __syncthreads();
@@ -292,8 +308,8 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
       const double zj = __shfl(z, j, 64);
       if (j > lane) v += Ld[lane][j] * zj;
     }
-    if (lane < w) x[g0 + dst] = v;
-    if (lane == 0) publish(flags + pbase + pi, epoch);
+    if (lane < w) st_dev(x + g0 + dst, v);
+    publish(flags + pbase + pi, epoch, lane == 0);
   }
 }
 
