@@ -87,224 +87,233 @@ __global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, const int64_
   for (int64_t r = c + threadIdx.x; r < uC; r += 256) dst[rel[r] + Cc * mP] += src[r];
 }
 
-// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, by one
-// wavefront: lane i owns row i of the (symmetric, fully stored) block.
-// Bunch-Kaufman 1x1/2x2 pivoting is restricted to the rows of one node group.
-// Besides L11 and D it forms X = L11^-1 (unit lower) and stores it transposed
-// in the block's unused upper triangle, so the rows below the panel are solved
-// by independent dot products instead of a sequential substitution.
 // Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, 256 threads.
-// Bunch-Kaufman 1x1/2x2 pivoting restricted to the rows of one node group.  The
-// pivot search is one LDS atomic max per candidate set (|a| bits with the row
-// index in the low bits, so ties go to the lower row), taken by wavefront 0;
-// the symmetric updates use lane = row, wavefront = every fourth column.
+// Bunch-Kaufman 1x1/2x2 pivoting restricted to the rows of one node group.  Every
+// wavefront reads the pivot column into registers and takes the same pivot decision
+// (argmax by a shuffle butterfly over |a| bits with the row index in the low bits, so
+// near-ties go to the lower row); the multipliers of the update come from that register
+// copy by lane broadcasts, so the step needs one barrier (two more for an interchange).
+// The symmetric updates use lane = row, wavefront = every fourth column.
 // Alongside L11 the block accumulates X = L11^-1 (unit lower) from the
 // elementary column inverses, X <- L_k^-1 X, stored transposed in the upper
 // part of the finished rows (X[i][j] at A[j][i]); symmetric interchanges swap
 // those entries exactly as X's rows must be swapped.  The rows below the panel
 // are then solved by a matrix-core product against X.
+__device__ inline double lane_bcast(double v, int src) {  // src uniform across the wavefront
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Maximum over the wavefront: data-parallel-primitive moves within rows of 16 lanes (swap adjacent
+// lanes, adjacent pairs, mirrored half rows, mirrored rows), then the four row maxima by lane reads.
+template <int CTRL>
+__device__ inline unsigned long long dpp_u64(unsigned long long x) {
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_update_dpp(0, (int)(unsigned int)x, CTRL, 0xF, 0xF, false);
+  const unsigned int hi =
+      (unsigned int)__builtin_amdgcn_update_dpp(0, (int)(unsigned int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+__device__ inline unsigned long long wave_max_u64(unsigned long long x) {
+  x = umax64(x, dpp_u64<0xB1>(x));   // quad_perm [1, 0, 3, 2]
+  x = umax64(x, dpp_u64<0x4E>(x));   // quad_perm [2, 3, 0, 1]
+  x = umax64(x, dpp_u64<0x141>(x));  // row_half_mirror
+  x = umax64(x, dpp_u64<0x140>(x));  // row_mirror
+  unsigned long long r = 0;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(x >> 32), 16 * row);
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)x, 16 * row);
+    r = umax64(r, ((unsigned long long)hi << 32) | lo);
+  }
+  return r;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
                                                     T* __restrict__ front) {
   __shared__ double A[64][65];
-  __shared__ int s_kind, s_p, s_q, s_pert;
-  __shared__ unsigned long long s_key, s_key2;
-  __shared__ int pos[64], ptype[64], gend_l[64];
-  __shared__ double dval[64], eval[64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int pos[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = uniform_i(tid >> 6);
   const int sn = (int)tasks[blockIdx.x * 3];
   const int c0 = (int)tasks[blockIdx.x * 3 + 1], c1 = (int)tasks[blockIdx.x * 3 + 2];
   const int w = c1 - c0;
   const int64_t m = f.sn_m[sn];
   const int64_t gbase = f.sn_begin[sn] + c0;
   T* F = front + f.sn_front_off[sn];
+  const double tol = f.piv_tol;
   for (int j = wave; j < w; j += 4)
     if (lane >= j && lane < w) {
       const double v = (double)F[(c0 + lane) + (int64_t)(c0 + j) * m];
       A[lane][j] = v;
       A[j][lane] = v;
     }
-  if (tid < 64) {
-    pos[tid] = tid;
-    gend_l[tid] = tid < w ? (int)(f.var_group_end[gbase + tid] - gbase) : w;
-  }
+  if (tid < 64) pos[tid] = tid;
+  const int gend_r = lane < w ? (int)(f.var_group_end[gbase + lane] - gbase) : w;
+  int ptype = 0;
+  double dv = 0.0, ev = 0.0;
   __syncthreads();
   int npert = 0;
   int k = 0;
   while (k < w) {
-    if (wave == 0) {
-      const int gend = gend_l[k];
-      if (lane == 0) {
-        s_key = 0ull;
-        s_key2 = 0ull;
+    double v = A[lane][k];
+    const int gend = __builtin_amdgcn_readlane(gend_r, k);
+    const double cand = (lane > k && lane < gend) ? fabs(v) : 0.0;
+    const unsigned long long key =
+        wave_max_u64(cand > 0.0 ? (((unsigned long long)__double_as_longlong(cand) & ~63ull) |
+                                   (unsigned long long)(63 - lane))
+                                : 0ull);
+    const int imax = key ? 63 - (int)(key & 63ull) : k;
+    const double colmax = key ? fabs(lane_bcast(v, imax)) : 0.0;
+    const double absakk = fabs(lane_bcast(v, k));
+    int kind = 1, p = -1, q = -1;
+    bool pert = false;
+    if (fmax(absakk, colmax) <= tol) {
+      pert = true;
+    } else if (absakk < kAlphaBK * colmax) {
+      const double u = A[imax][lane];  // row imax
+      const double c2 = (lane >= k && lane < gend && lane != imax) ? fabs(u) : 0.0;
+      const double rowmax = __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(c2)));
+      if (absakk * rowmax >= kAlphaBK * colmax * colmax) {
+        kind = 1;
+      } else if (fabs(lane_bcast(u, imax)) >= kAlphaBK * rowmax) {
+        kind = 1;
+        p = k;
+        q = imax;
+      } else {
+        kind = 2;
+        p = k + 1;
+        q = imax;
       }
-      __builtin_amdgcn_wave_barrier();
-      const double v = (lane > k && lane < gend) ? fabs(A[lane][k]) : 0.0;
-      if (v > 0.0) atomicMax(&s_key, (__double_as_longlong(v) & ~63ull) | (unsigned long long)(63 - lane));
-      __builtin_amdgcn_wave_barrier();
-      const unsigned long long key = s_key;
-      const int imax = key ? 63 - (int)(key & 63ull) : k;
-      const double colmax = key ? fabs(A[imax][k]) : 0.0;
-      const double absakk = fabs(A[k][k]);
-      int kind = 1, p = -1, q = -1, pert = 0;
-      if (fmax(absakk, colmax) <= f.piv_tol) {
-        pert = 1;
-      } else if (absakk < kAlphaBK * colmax) {
-        const double v2 = (lane >= k && lane < gend && lane != imax) ? fabs(A[imax][lane]) : 0.0;
-        if (v2 > 0.0) atomicMax(&s_key2, (unsigned long long)__double_as_longlong(v2));
-        __builtin_amdgcn_wave_barrier();
-        const double rowmax = __longlong_as_double((long long)s_key2);
-        if (absakk * rowmax >= kAlphaBK * colmax * colmax) {
-          kind = 1;
-        } else if (fabs(A[imax][imax]) >= kAlphaBK * rowmax) {
-          kind = 1;
-          p = k;
-          q = imax;
-        } else {
-          kind = 2;
-          p = k + 1;
-          q = imax;
+    }
+    if (p >= 0 && p != q) {
+      // symmetric interchange p <-> q in one pass: thread t moves the entries (p,t), (q,t), (t,p), (t,q)
+      __syncthreads();  // every wavefront has read column k and row imax
+      if (tid < w) {
+        const int t = tid;
+        if (t != p && t != q) {
+          const double apt = A[p][t], aqt = A[q][t], atp = A[t][p], atq = A[t][q];
+          A[p][t] = aqt;
+          A[q][t] = apt;
+          A[t][p] = atq;
+          A[t][q] = atp;
+        } else if (t == p) {
+          const double app = A[p][p], aqq = A[q][q], apq = A[p][q], aqp = A[q][p];
+          A[p][p] = aqq;
+          A[q][q] = app;
+          A[p][q] = aqp;
+          A[q][p] = apq;
+          const int tp = pos[p];
+          pos[p] = pos[q];
+          pos[q] = tp;
         }
       }
-      if (lane == 0) {
-        s_kind = kind;
-        s_p = p;
-        s_q = q;
-        s_pert = pert;
-        if (pert) A[k][k] = A[k][k] >= 0.0 ? f.piv_tol : -f.piv_tol;
-      }
-    }
-    __syncthreads();
-    const int kind = s_kind, p = s_p, q = s_q;
-    if (s_pert) ++npert;
-    if (p >= 0 && p != q) {
-      for (int j = tid; j < w; j += 256) {
-        const double t = A[p][j];
-        A[p][j] = A[q][j];
-        A[q][j] = t;
-      }
       __syncthreads();
-      for (int i = tid; i < w; i += 256) {
-        const double t = A[i][p];
-        A[i][p] = A[i][q];
-        A[i][q] = t;
-      }
-      if (tid == 0) {
-        const int t = pos[p];
-        pos[p] = pos[q];
-        pos[q] = t;
-      }
-      __syncthreads();
+      v = A[lane][k];
     }
     if (kind == 1) {
-      double d = A[k][k];
-      if (fabs(d) < f.piv_tol) {
-        d = d >= 0.0 ? f.piv_tol : -f.piv_tol;
+      double d = lane_bcast(v, k);
+      if (pert) {
+        d = d >= 0.0 ? tol : -tol;
+        ++npert;
+      } else if (fabs(d) < tol) {
+        d = d >= 0.0 ? tol : -tol;
         ++npert;
       }
       const double id = 1.0 / d;
       if (lane > k && lane < w) {
-        const double li = A[lane][k] * id;
-        // Schur complement and X <- L_k^-1 X; four columns per round keep four LDS loads in flight
+        const double li = v * id;
+        // Schur complement and X <- L_k^-1 X; the multipliers A[j][k] are lane j's copy of column k
         int j = k + 1 + wave;
         for (; j + 12 < w; j += 16) {
-          const double b0 = A[j][k], b1 = A[j + 4][k], b2 = A[j + 8][k], b3 = A[j + 12][k];
           const double a0 = A[lane][j], a1 = A[lane][j + 4], a2 = A[lane][j + 8], a3 = A[lane][j + 12];
-          A[lane][j] = a0 - li * b0;
-          A[lane][j + 4] = a1 - li * b1;
-          A[lane][j + 8] = a2 - li * b2;
-          A[lane][j + 12] = a3 - li * b3;
+          A[lane][j] = a0 - li * lane_bcast(v, j);
+          A[lane][j + 4] = a1 - li * lane_bcast(v, j + 4);
+          A[lane][j + 8] = a2 - li * lane_bcast(v, j + 8);
+          A[lane][j + 12] = a3 - li * lane_bcast(v, j + 12);
         }
-        for (; j < w; j += 4) A[lane][j] -= li * A[j][k];
+        for (; j < w; j += 4) A[lane][j] -= li * lane_bcast(v, j);
         j = wave;
         for (; j + 12 < k; j += 16) {
-          const double b0 = A[j][k], b1 = A[j + 4][k], b2 = A[j + 8][k], b3 = A[j + 12][k];
           const double a0 = A[j][lane], a1 = A[j + 4][lane], a2 = A[j + 8][lane], a3 = A[j + 12][lane];
-          A[j][lane] = a0 - li * b0;
-          A[j + 4][lane] = a1 - li * b1;
-          A[j + 8][lane] = a2 - li * b2;
-          A[j + 12][lane] = a3 - li * b3;
+          A[j][lane] = a0 - li * lane_bcast(v, j);
+          A[j + 4][lane] = a1 - li * lane_bcast(v, j + 4);
+          A[j + 8][lane] = a2 - li * lane_bcast(v, j + 8);
+          A[j + 12][lane] = a3 - li * lane_bcast(v, j + 12);
         }
-        for (; j < k; j += 4) A[j][lane] -= li * A[j][k];
+        for (; j < k; j += 4) A[j][lane] -= li * lane_bcast(v, j);
+        if (wave == 0) {  // column k and row k are read by nobody in this step
+          A[lane][k] = li;
+          A[k][lane] = -li;
+        }
       }
-      __syncthreads();
-      if (tid > k && tid < w) {
-        const double li = A[tid][k] * id;
-        A[tid][k] = li;
-        A[k][tid] = -li;
+      if (lane == k) {
+        ptype = 0;
+        dv = d;
+        ev = 0.0;
       }
-      if (tid == 0) {
-        ptype[k] = 0;
-        dval[k] = d;
-        eval[k] = 0.0;
-      }
-      __syncthreads();
       k += 1;
     } else {
-      const double a = A[k][k], b = A[k + 1][k], c = A[k + 1][k + 1];
+      const double w2 = A[lane][k + 1];
+      const double a = lane_bcast(v, k), b = lane_bcast(v, k + 1), c = lane_bcast(w2, k + 1);
       const double det = a * c - b * b;
       const double i00 = c / det, i01 = -b / det, i11 = a / det;
       if (lane > k + 1 && lane < w) {
-        const double ui0 = A[lane][k], ui1 = A[lane][k + 1];
-        const double l0 = ui0 * i00 + ui1 * i01, l1 = ui0 * i01 + ui1 * i11;
+        const double l0 = v * i00 + w2 * i01, l1 = v * i01 + w2 * i11;
         int j = k + 2 + wave;
         for (; j + 12 < w; j += 16) {
-          double b0[4], b1[4], a[4];
+          double a4[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            b0[q] = A[j + 4 * q][k];
-            b1[q] = A[j + 4 * q][k + 1];
-            a[q] = A[lane][j + 4 * q];
-          }
+          for (int t = 0; t < 4; ++t) a4[t] = A[lane][j + 4 * t];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) A[lane][j + 4 * q] = a[q] - (l0 * b0[q] + l1 * b1[q]);
+          for (int t = 0; t < 4; ++t)
+            A[lane][j + 4 * t] = a4[t] - (l0 * lane_bcast(v, j + 4 * t) + l1 * lane_bcast(w2, j + 4 * t));
         }
-        for (; j < w; j += 4) A[lane][j] -= l0 * A[j][k] + l1 * A[j][k + 1];
+        for (; j < w; j += 4) A[lane][j] -= l0 * lane_bcast(v, j) + l1 * lane_bcast(w2, j);
         j = wave;
         for (; j + 12 < k; j += 16) {
-          double b0[4], b1[4], a[4];
+          double a4[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            b0[q] = A[j + 4 * q][k];
-            b1[q] = A[j + 4 * q][k + 1];
-            a[q] = A[j + 4 * q][lane];
-          }
+          for (int t = 0; t < 4; ++t) a4[t] = A[j + 4 * t][lane];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) A[j + 4 * q][lane] = a[q] - (l0 * b0[q] + l1 * b1[q]);
+          for (int t = 0; t < 4; ++t)
+            A[j + 4 * t][lane] = a4[t] - (l0 * lane_bcast(v, j + 4 * t) + l1 * lane_bcast(w2, j + 4 * t));
         }
-        for (; j < k; j += 4) A[j][lane] -= l0 * A[j][k] + l1 * A[j][k + 1];
-      }
-      __syncthreads();
-      if (tid > k + 1 && tid < w) {
-        const double u0 = A[tid][k], u1 = A[tid][k + 1];
-        const double l0 = u0 * i00 + u1 * i01, l1 = u0 * i01 + u1 * i11;
-        A[tid][k] = l0;
-        A[tid][k + 1] = l1;
-        A[k][tid] = -l0;
-        A[k + 1][tid] = -l1;
+        for (; j < k; j += 4) A[j][lane] -= l0 * lane_bcast(v, j) + l1 * lane_bcast(w2, j);
+        if (wave == 0) {
+          A[lane][k] = l0;
+          A[lane][k + 1] = l1;
+          A[k][lane] = -l0;
+          A[k + 1][lane] = -l1;
+        }
       }
       if (tid == 0) {
-        ptype[k] = 1;
-        ptype[k + 1] = 2;
-        dval[k] = a;
-        dval[k + 1] = c;
-        eval[k] = b;
-        eval[k + 1] = 0.0;
         A[k + 1][k] = 0.0;  // L and X are the identity inside a 2x2 block
         A[k][k + 1] = 0.0;
       }
-      __syncthreads();
+      if (lane == k) {
+        ptype = 1;
+        dv = a;
+        ev = b;
+      } else if (lane == k + 1) {
+        ptype = 2;
+        dv = c;
+        ev = 0.0;
+      }
       k += 2;
     }
+    __syncthreads();
   }
   // A holds L below the diagonal and X[j][i] at (i, j) above it: the transposed
   // placement the rows-below solve reads
   for (int j = wave; j < w; j += 4)
     if (lane < w) F[(c0 + lane) + (int64_t)(c0 + j) * m] = (T)(lane == j ? 1.0 : A[lane][j]);
   if (tid < w) {
-    f.dpiv[gbase + tid] = dval[tid];
-    f.epiv[gbase + tid] = eval[tid];
-    f.pivtype[gbase + tid] = ptype[tid];
+    f.dpiv[gbase + tid] = dv;
+    f.epiv[gbase + tid] = ev;
+    f.pivtype[gbase + tid] = ptype;
     f.lperm[gbase + tid] = c0 + pos[tid];
   }
   if (tid == 0 && npert) atomicAdd(&f.counters[0], npert);
