@@ -116,6 +116,8 @@ typedef struct {
   double eps_x, eps_lambda;     /* optional diagonal stabilisation (Sec. 5), default 0 */
   int max_newton, max_ir, max_minres, max_halvings;
   int profile;                  /* 1: time every trailing-update launch with HIP events */
+  int max_gmres;                /* restart cycles of the FGMRES(30) escalation of the saddle-point
+                                   solves' refinement, 0: none */
 } sgn_options;
 
 typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;
@@ -132,6 +134,7 @@ typedef struct {
   double rel_res;               /* equilibrated relative residual (solve_rtol measure) */
   double raw_rel_res;           /* |b - K z|_2 / |b|_2 on the unscaled matrix */
   double ms;
+  int gmres_iters;              /* Arnoldi steps of the FGMRES escalation (0: refinement sufficed) */
 } sgn_solve_info;
 typedef struct {
   double alpha, f0, f1, grad_norm, gtdp;
@@ -180,7 +183,12 @@ sgn_status sgn_assemble(sgn_ctx ctx, const double* d_x, const double* d_p,
  * to each mesh node's variable group).  Checks the inertia (n_x+n_p, n_x, 0). */
 sgn_status sgn_factor(sgn_ctx ctx, sgn_factor_info* info);
 /* Solve K_SGN sol = rhs with the current factor plus FP64 iterative
- * refinement to solve_rtol (both device arrays, [N], block order). */
+ * refinement to solve_rtol (both device arrays, [N], block order).  When a
+ * refinement sweep shrinks the equilibrated residual by less than half, or
+ * max_ir sweeps did not reach solve_rtol, the solve continues with restarted
+ * flexible GMRES(30) in FP64 on the equilibrated system, right-preconditioned
+ * by the factor (at most max_gmres cycles).  SGN_E_REFINE if solve_rtol is
+ * still not met. */
 sgn_status sgn_solve(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_info* info);
 /* One outer iteration: assemble + factor + solve for the step, then
  * backtracking p + alpha dp with one equilibrium per trial and Armijo

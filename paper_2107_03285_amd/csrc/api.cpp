@@ -82,6 +82,9 @@ struct DevSys {
   double* ir_r = nullptr;  // internal to refined_solve: residual
   double* ir_d = nullptr;  // internal to refined_solve: correction
   double* ir_s = nullptr;  // internal to refined_solve: scaled residual
+  double* gm_V = nullptr;  // FGMRES escalation: Arnoldi basis [(kGmresM + 1) x N]
+  double* gm_Z = nullptr;  // preconditioned basis [kGmresM x N]
+  double* gm_t = nullptr;  // correction [N]
   // node-block preconditioner (SGN system only)
   int32_t* grp_ptr = nullptr;
   int32_t* grp_node = nullptr;
@@ -118,6 +121,8 @@ double now_ms() {
 }
 
 }  // namespace
+
+constexpr int kGmresM = 30;  // FGMRES restart length of the refinement escalation
 
 struct sgn_ctx_s {
   Analysis A;
@@ -156,6 +161,8 @@ struct sgn_ctx_s {
   double* d_ssol = nullptr;  // [N] step solution (boundary order)
   double* d_part = nullptr;
   double* d_scal = nullptr;
+  double* d_gm = nullptr;             // FGMRES coefficients: two Gram-Schmidt passes, |w|^2, solution
+  std::vector<double> gm_host;        // host copy of the FGMRES solution coefficients
   int* d_cnt = nullptr;
   unsigned long long* d_ull = nullptr;
   // preconditioner network: graph tables and activations (FP32)
@@ -311,6 +318,9 @@ size_t layout(sgn_ctx c, char* base) {
     D.ir_r = L.take<double>(S.N);
     D.ir_d = L.take<double>(S.N);
     D.ir_s = L.take<double>(S.N);
+    D.gm_V = L.take<double>((int64_t)(kGmresM + 1) * S.N);
+    D.gm_Z = L.take<double>((int64_t)kGmresM * S.N);
+    D.gm_t = L.take<double>(S.N);
     if (si == 0) {
       D.ngroups = (int64_t)S.grp_node.size();
       D.grp_ptr = L.take<int32_t>(S.grp_ptr.size());
@@ -391,6 +401,7 @@ size_t layout(sgn_ctx c, char* base) {
   c->d_ssol = L.take<double>(A.sgn.N);
   c->d_part = L.take<double>(4 * kRedBlocks);
   c->d_scal = L.take<double>(64);
+  c->d_gm = L.take<double>(256);
   c->d_cnt = L.take<int>(64);
   c->d_ull = L.take<unsigned long long>(16);
   return L.off + 256;
@@ -413,6 +424,11 @@ void dev_dot(sgn_ctx c, int64_t n, const double* a, const double* b, int slot, i
              int absval = 0) {
   launch_dot_partials(n, a, b, stride, absval, c->d_part, c->stream);
   launch_final_sum(c->d_part, kRedBlocks, c->d_scal + slot, c->stream);
+}
+
+void dev_dot_to(sgn_ctx c, int64_t n, const double* a, const double* b, double* out) {
+  launch_dot_partials(n, a, b, 1, 0, c->d_part, c->stream);
+  launch_final_sum(c->d_part, kRedBlocks, out, c->stream);
 }
 
 // ------------------------------------------------------------------ element + assembly
@@ -747,8 +763,85 @@ void scale_vec(sgn_ctx c, int64_t n, const double* s, const double* in, double* 
   launch_scale(n, s, in, out, c->stream);
 }
 
+// One cycle of restarted flexible GMRES (Saad's FGMRES(m)) in FP64 on the equilibrated system
+// (S K S) u = S b with z = S u, right-preconditioned by the stored factor (the forward and backward
+// sweeps approximate (S K S)^-1), starting from z_new whose equilibrated residual is rs = S (b - K z)
+// with norm beta.  The Arnoldi vectors are orthogonalised by two passes of classical Gram-Schmidt
+// (dot products on the device, one read-back per step); the least-squares problem is reduced by
+// Givens rotations on the host.  Stops when the residual estimate falls to `stop` or after m steps;
+// z_new += S sum_i y_i Z_i.
+sgn_status fgmres_cycle(sgn_ctx c, int si, double* z_new, const double* rs, double beta, double stop, int* iters) {
+  const System& S = si == 0 ? c->A.sgn : c->A.kx;
+  DevSys& D = c->sys[si];
+  const int64_t N = S.N;
+  const int m = kGmresM;
+  hipStream_t st = c->stream;
+  double* V = D.gm_V;
+  double* Z = D.gm_Z;
+  launch_axpby(N, 1.0 / beta, rs, 0.0, nullptr, V, st);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+  auto h = [&](int i, int j) -> double& { return H[(size_t)j * (m + 1) + i]; };
+  g[0] = beta;
+  int k = 0;  // basis vectors used
+  std::vector<double> hb(2 * 64 + 1);
+  while (k < m) {
+    const int j = k;
+    double* vj = V + (int64_t)j * N;
+    double* zj = Z + (int64_t)j * N;
+    double* vn = V + (int64_t)(j + 1) * N;
+    TRY(fwd_sweep(c, si, vj));
+    TRY(bwd_sweep(c, si, zj, nullptr));
+    scale_vec(c, N, D.scale, zj, D.sv);
+    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, D.sv, vn, st);
+    scale_vec(c, N, D.scale, vn, vn);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i <= j; ++i) dev_dot_to(c, N, V + (int64_t)i * N, vn, c->d_gm + 64 * pass + i);
+      launch_multi_axpy(N, j + 1, V, N, c->d_gm + 64 * pass, -1.0, vn, st);
+    }
+    dev_dot_to(c, N, vn, vn, c->d_gm + 128);
+    HIPCHK(hipMemcpyAsync(hb.data(), c->d_gm, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i <= j; ++i) h(i, j) = hb[i] + hb[64 + i];
+    const double hn = std::sqrt(std::max(hb[128], 0.0));
+    h(j + 1, j) = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = h(i, j), b = h(i + 1, j);
+      h(i, j) = cs[i] * a + sn[i] * b;
+      h(i + 1, j) = -sn[i] * a + cs[i] * b;
+    }
+    const double den = std::hypot(h(j, j), h(j + 1, j));
+    if (!(den > 0.0)) break;  // the preconditioned operator is singular on this space
+    cs[j] = h(j, j) / den;
+    sn[j] = h(j + 1, j) / den;
+    h(j, j) = den;
+    h(j + 1, j) = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    k = j + 1;
+    ++*iters;
+    if (std::fabs(g[j + 1]) <= stop || !(hn > 0.0)) break;
+    launch_axpby(N, 1.0 / hn, vn, 0.0, nullptr, vn, st);
+  }
+  if (k == 0) return SGN_OK;
+  c->gm_host.assign(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {  // back substitution with the rotated Hessenberg matrix
+    double t = g[i];
+    for (int l = i + 1; l < k; ++l) t -= h(i, l) * c->gm_host[l];
+    c->gm_host[i] = t / h(i, i);
+  }
+  HIPCHK(hipMemcpyAsync(c->d_gm + 192, c->gm_host.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_fill(N, 0.0, D.gm_t, st);
+  launch_multi_axpy(N, k, Z, N, c->d_gm + 192, 1.0, D.gm_t, st);
+  scale_vec(c, N, D.scale, D.gm_t, D.gm_t);
+  launch_axpby(N, 1.0, z_new, 1.0, D.gm_t, z_new, st);
+  HIPCHK(hipStreamSynchronize(st));  // gm_host is read by the copy
+  return SGN_OK;
+}
+
 // Refined solve in new order: K z = b (unscaled), FP64 residuals on the assembled
 // matrix.  b_new and z_new are caller buffers (distinct from the internal ones).
+// Refinement sweeps continue while each one at least halves the equilibrated residual;
+// otherwise (or after max_ir sweeps) FGMRES cycles take over from the current iterate.
 sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, sgn_solve_info* info) {
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
   DevSys& D = c->sys[si];
@@ -761,9 +854,13 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
   double bn[2];
   TRY(read_scalars(c, 1, 2, bn));
   const double sb = std::sqrt(bn[0]), rb = std::sqrt(bn[1]);
-  int sweeps = 0;
-  double rel = 0, raw = 0, prev = INFINITY;
+  int sweeps = 0, gm_iters = 0, cycles = 0;
+  double rel = 0, raw = 0, prev = INFINITY, gprev = INFINITY;
+  bool krylov = false;
   const int max_ir = std::max(0, c->opt.max_ir);
+  // the Newton solves with Kx need no 1e-10 accuracy (a stalled refinement is accepted there), so the
+  // Krylov escalation serves the saddle-point system only
+  const int max_gmres = si == 0 ? c->opt.max_gmres : 0;
   for (;;) {
     launch_residual(S.N, D.frowptr, D.fcol, D.fslot, D.vals, z_new, b_new, D.ir_r, c->stream);
     scale_vec(c, S.N, D.scale, D.ir_r, D.ir_s);
@@ -773,11 +870,24 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
     TRY(read_scalars(c, 1, 2, rn));
     rel = sb > 0 ? std::sqrt(rn[0]) / sb : 0.0;
     raw = rb > 0 ? std::sqrt(rn[1]) / rb : 0.0;
-    if (rel <= c->opt.solve_rtol || sweeps >= max_ir || !(rel < prev)) break;
-    prev = rel;
-    TRY(solve_once(c, si, D.ir_r, D.ir_d));
-    launch_axpby(S.N, 1.0, z_new, 1.0, D.ir_d, z_new, c->stream);
-    ++sweeps;
+    if (rel <= c->opt.solve_rtol) break;
+    if (!krylov) {
+      const bool slow = sweeps > 0 && !(rel <= 0.5 * prev);
+      if ((slow || sweeps >= max_ir) && max_gmres > 0) {
+        krylov = true;
+      } else {
+        if (sweeps >= max_ir || !(rel < prev)) break;
+        prev = rel;
+        TRY(solve_once(c, si, D.ir_r, D.ir_d));
+        launch_axpby(S.N, 1.0, z_new, 1.0, D.ir_d, z_new, c->stream);
+        ++sweeps;
+        continue;
+      }
+    }
+    if (cycles >= max_gmres || !(rel < gprev)) break;
+    gprev = rel;
+    TRY(fgmres_cycle(c, si, z_new, D.ir_s, rel * sb, 0.5 * c->opt.solve_rtol * sb, &gm_iters));
+    ++cycles;
   }
   int timeout = 0;
   HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -792,6 +902,7 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
     info->rel_res = rel;
     info->raw_rel_res = raw;
     info->ms = now_ms() - t0;
+    info->gmres_iters = gm_iters;
   }
   if (!(rel <= c->opt.solve_rtol)) {
     char buf[96];
@@ -1533,6 +1644,7 @@ void sgn_default_options(sgn_options* o) {
   o->eps_lambda = 0.0;
   o->max_newton = 50;
   o->max_ir = 10;
+  o->max_gmres = 10;
   o->max_minres = 500;
   o->max_halvings = 30;
   o->profile = 0;

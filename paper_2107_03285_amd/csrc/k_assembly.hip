@@ -348,6 +348,17 @@ __global__ void k_axpby(int64_t n, double a, const double* x, double b, const do
     out[k] = a * x[k] + (y ? b * y[k] : 0.0);
 }
 
+// w += sign * sum_{t < j} coef[t] V[t], the basis V stored as j vectors of stride ldv; the sum over t
+// runs in ascending order (bitwise reproducible)
+__global__ void k_multi_axpy(int64_t n, int j, const double* __restrict__ V, int64_t ldv,
+                             const double* __restrict__ coef, double sign, double* __restrict__ w) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int t = 0; t < j; ++t) acc += coef[t] * V[t * ldv + k];
+    w[k] += sign * acc;
+  }
+}
+
 __global__ void k_scale(int64_t n, const double* sc, const double* in, double* out) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     out[k] = sc[k] * in[k];
@@ -473,6 +484,11 @@ void launch_scatter_perm(int64_t n, const int32_t* perm, const double* scale, co
 
 void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t s) {
   if (n > 0) k_axpby<<<grid_for(n, 256), 256, 0, s>>>(n, a, x, b, y, out);
+}
+
+void launch_multi_axpy(int64_t n, int j, const double* V, int64_t ldv, const double* coef, double sign, double* w,
+                       hipStream_t s) {
+  if (n > 0 && j > 0) k_multi_axpy<<<grid_for(n, 256), 256, 0, s>>>(n, j, V, ldv, coef, sign, w);
 }
 
 void launch_scale(int64_t n, const double* sc, const double* in, double* out, hipStream_t s) {

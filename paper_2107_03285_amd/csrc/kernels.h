@@ -49,6 +49,9 @@ void launch_gather_perm(int64_t n, const int32_t* perm, const double* scale, con
 void launch_scatter_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out,
                          hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t s);
+// w += sign * sum_{t < j} coef[t] V[t * ldv + .] (coef on the device)
+void launch_multi_axpy(int64_t n, int j, const double* V, int64_t ldv, const double* coef, double sign, double* w,
+                       hipStream_t s);
 void launch_fill(int64_t n, double v, double* out, hipStream_t s);
 // out = s .* in (elementwise; out may alias in)
 void launch_scale(int64_t n, const double* s, const double* in, double* out, hipStream_t st);

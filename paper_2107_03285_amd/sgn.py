@@ -50,7 +50,7 @@ class sgn_options(C.Structure):
                 ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("solve_rtol", C.c_double),
                 ("eps_x", C.c_double), ("eps_lambda", C.c_double), ("max_newton", C.c_int),
                 ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int),
-                ("profile", C.c_int)]
+                ("profile", C.c_int), ("max_gmres", C.c_int)]
 
 
 class sgn_stats(C.Structure):
@@ -72,7 +72,7 @@ class sgn_factor_info(C.Structure):
 
 class sgn_solve_info(C.Structure):
     _fields_ = [("sweeps", C.c_int), ("fallback", C.c_int), ("rel_res", C.c_double),
-                ("raw_rel_res", C.c_double), ("ms", C.c_double)]
+                ("raw_rel_res", C.c_double), ("ms", C.c_double), ("gmres_iters", C.c_int)]
 
 
 class sgn_step_info(C.Structure):

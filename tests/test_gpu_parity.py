@@ -291,3 +291,61 @@ def test_zero_right_hand_side_gives_zero_step():
     sol = torch.ones(N, dtype=torch.float64, device="cuda")
     info = ctx.solve_minres(torch.zeros(N, dtype=torch.float64, device="cuda"), sol)
     assert info.fallback == 0 and float(sol.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("name", ["grid21", "cant8x3x3"])
+def test_fgmres_escalation_matches_dense_step(name):
+    """With no refinement sweeps allowed (max_ir = 0) the solve goes straight to the FGMRES(30)
+    escalation, preconditioned by the FP32 factor; its step must match the oracle's dense
+    Gauss-Newton step like the refined solve does."""
+    prob, p, x = _problem(name)
+    ctx = _ctx(prob, precision=sgn.SGN_FP32_IR, newton_rtol=1e-11, max_ir=0)
+    xd, pd = _cuda(x), _cuda(p)
+    ctx.equilibrium(pd, xd)
+    N = 2 * prob.n_x + prob.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.assemble(xd, pd, rhs)
+    ctx.factor()
+    sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+    info = ctx.solve(rhs, sol)
+    assert info.sweeps == 0 and info.gmres_iters > 0
+    assert info.rel_res <= 1e-10
+    st = D.dense_gn_step(prob, _host(xd), p)
+    dx, dp, dl = _blocks(prob, _host(sol))
+    assert _rel(dp, st.dp) <= 1e-8
+    assert _rel(dx, st.dx) <= 1e-8
+    assert _rel(dl, st.dlam) <= 1e-8
+
+
+def test_fgmres_escalation_rescues_diverging_fp32_refinement():
+    """A log-modulus field of standard deviation 4 (moduli spread over about e^{+-8}) leaves the
+    equilibrated system too ill-conditioned for refinement with the FP32 factor: the sweeps stop far
+    above 1e-10 (SGN_E_REFINE without the escalation).  With it, FGMRES preconditioned by the same
+    FP32 factor reaches 1e-10, and the direction matches the FP64 direct solve and the oracle's dense
+    Gauss-Newton step."""
+    prob = D.setup_targets(si.config_2d())
+    p = 4.0 * np.random.default_rng(7).standard_normal(prob.n_p)
+    N = 2 * prob.n_x + prob.n_p
+    out = {}
+    for key, opt in (("ir", dict(precision=sgn.SGN_FP32_IR, max_gmres=0)),
+                     ("fgmres", dict(precision=sgn.SGN_FP32_IR)), ("fp64", dict(precision=sgn.SGN_FP64))):
+        ctx = _ctx(prob, newton_rtol=1e-11, **opt)
+        xd, pd = _cuda(prob.x_rest()), _cuda(p)
+        ctx.equilibrium(pd, xd)
+        rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+        ctx.assemble(xd, pd, rhs)
+        ctx.factor()
+        sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+        try:
+            out[key] = (ctx.solve(rhs, sol), _host(sol), _host(xd))
+        except sgn.SgnError as e:
+            out[key] = e
+    assert isinstance(out["ir"], sgn.SgnError) and out["ir"].status == sgn.SGN_E_REFINE
+    info, z, xg = out["fgmres"]
+    assert info.gmres_iters > 0 and info.rel_res <= 1e-10
+    _, z64, _ = out["fp64"]
+    dx, dp, dl = _blocks(prob, z)
+    dx64, dp64, dl64 = _blocks(prob, z64)
+    assert _rel(dp, dp64) <= 1e-8 and _rel(dx, dx64) <= 1e-8
+    st = D.dense_gn_step(prob, xg, p)
+    assert _rel(dp, st.dp) <= 1e-8
