@@ -453,7 +453,16 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   __shared__ T sL[KC][SL];                    // sL[k][r]
   __shared__ __attribute__((aligned(16))) T sW[TM][SW];  // sW[c][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t b = blockIdx.x;
+  // Workgroups are handed to the 8 dies (each with its own L2) round-robin by index; renumber so that
+  // each die takes one contiguous run of tiles.  Consecutive tiles share their W column tile (and
+  // neighbouring runs their L row tiles), which then stays in that die's L2.
+  int64_t b;
+  {
+    const int64_t n = gridDim.x, x = blockIdx.x & 7;
+    int64_t before = 0;
+    for (int64_t y = 0; y < x; ++y) before += (n - y + 7) >> 3;
+    b = before + (blockIdx.x >> 3);
+  }
   int64_t lo = 0, hi = ntasks - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
