@@ -323,6 +323,23 @@ def sgn_matrix_dense(prob: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
                      [Kx, Kp, Z]])
 
 
+def sgn_matrix_sparse(prob: Problem, x: np.ndarray, p: np.ndarray) -> sp.csr_matrix:
+    """The same K_SGN (eq. sparseSystemGN) from the sparse blocks, for meshes where a dense matrix does
+    not fit; every block comes from the oracle's own element derivatives."""
+    Kx = stiffness(prob, x, p)
+    Kp = param_jacobian(prob, x, p)
+    _, _, A, B, C = objective_blocks(prob, x, p)
+    return sp.bmat([[A, B.T, Kx.T], [B, C, Kp.T], [Kx, Kp, None]], format="csr")
+
+
+def equilibrated_residual(K: sp.spmatrix, z: np.ndarray, b: np.ndarray) -> float:
+    """|S (b - K z)|_2 / |S b|_2 with S = diag(1 / sqrt(max_j |K_ij|)): the relative residual in the
+    one-pass symmetric equilibration the solves are judged in."""
+    rowmax = abs(sp.csr_matrix(K)).max(axis=1).toarray().ravel()
+    s = 1.0 / np.sqrt(rowmax)
+    return float(np.linalg.norm(s * (b - K @ z)) / np.linalg.norm(s * b))
+
+
 def sgn_dense_solve(prob: Problem, x: np.ndarray, p: np.ndarray, rhs_kind: str = "adjoint"):
     """Solve the saddle-point system directly with dense LU.
 

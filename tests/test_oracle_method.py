@@ -203,3 +203,30 @@ def test_gn_iterations_decrease_objective(tiny):
     fs = [t[0] for t in trace] + [D.objective(prob, xf, pf)]
     assert all(fs[i + 1] < fs[i] for i in range(len(fs) - 1))
     assert trace[-1][1] < 1e-2 * trace[0][1]
+
+
+@pytest.mark.parametrize("fixture", ["tiny", "rest"])
+def test_sparse_sgn_matrix_equals_dense_and_solves_theorem1_step(fixture, request):
+    """The sparse assembly of K_SGN (eq. sparseSystemGN) is entry for entry the dense one, and the dense
+    Gauss-Newton step [dx; dp; dlam] (Theorem 1) solves it to rounding in the equilibrated measure."""
+    prob = request.getfixturevalue(fixture)
+    p = prob.p_init()
+    x, _ = D.equilibrium(prob, p)
+    Ks = D.sgn_matrix_sparse(prob, x, p)
+    assert np.array_equal(Ks.toarray(), D.sgn_matrix_dense(prob, x, p))
+    st = D.dense_gn_step(prob, x, p)
+    z = np.concatenate([st.dx, st.dp, st.dlam])
+    b = D.sgn_rhs(prob, x, p)
+    assert D.equilibrated_residual(Ks, z, b) <= 1e-10
+    assert D.equilibrated_residual(Ks, np.zeros_like(z), b) == pytest.approx(1.0, rel=1e-15)
+
+
+def test_equilibrated_residual_hand_example():
+    """K = [[4, 1], [1, 9]]: row maxima 4 and 9, S = diag(1/2, 1/3); for b = (2, 3) and z = (1/2, 0)
+    the residual is (0, 5/2), scaled (0, 5/6), over |(1, 1)| = sqrt(2)."""
+    import scipy.sparse as sp
+    K = sp.csr_matrix(np.array([[4.0, 1.0], [1.0, 9.0]]))
+    got = D.equilibrated_residual(K, np.array([0.5, 0.0]), np.array([2.0, 3.0]))
+    assert got == pytest.approx((5.0 / 6.0) / np.sqrt(2.0), rel=1e-15)
+    # invariant under a common scale of matrix and right-hand side
+    assert D.equilibrated_residual(7.0 * K, np.array([0.5, 0.0]), np.array([14.0, 21.0])) == pytest.approx(got, rel=1e-14)
