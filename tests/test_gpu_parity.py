@@ -30,6 +30,7 @@ def _problem(name):
     if name not in _PROBS:
         mk = {
             "tiny": si.config_tiny,
+            "grid2": lambda: si.problem_2d(2, seed=3),  # smallest mesh: 2 triangles, 2 free nodes
             "grid21": si.config_2d,
             "cant4x2x2": lambda: si.problem_3d(4, 2, 2, 0.25, seed=1),
             "cant8x3x3": lambda: si.problem_3d(8, 3, 3, 1 / 3, seed=2),
@@ -110,7 +111,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("precision", [sgn.SGN_FP64, sgn.SGN_FP32_IR])
-@pytest.mark.parametrize("name", ["tiny", "grid21", "cant4x2x2", "cant8x3x3", "rest3x2x2"])
+@pytest.mark.parametrize("name", ["grid2", "tiny", "grid21", "cant4x2x2", "cant8x3x3", "rest3x2x2"])
 def test_step_matches_dense_gauss_newton(name, precision):
     prob, p, x = _problem(name)
     ctx = _ctx(prob, precision=precision, newton_rtol=1e-11)
@@ -349,3 +350,31 @@ def test_fgmres_escalation_rescues_diverging_fp32_refinement():
     assert _rel(dp, dp64) <= 1e-8 and _rel(dx, dx64) <= 1e-8
     st = D.dense_gn_step(prob, xg, p)
     assert _rel(dp, st.dp) <= 1e-8
+
+
+def test_no_targets_step_is_the_regulariser_step():
+    """Without targets A = 0 and df/dx = 0, so the reduced Hessian is C = mu I and g = mu (p - p_ref):
+    the step returns the parameters to p_ref exactly (dp = p_ref - p), with dx = S dp as in the
+    oracle's dense step."""
+    prob = si.problem_2d(6, seed=4)
+    prob.target_dof = np.zeros(0, np.int32)
+    prob.target_val = np.zeros(0)
+    prob.length_scale = 1.0
+    p = 0.1 * np.random.default_rng(5).standard_normal(prob.n_p)
+    x, info = D.equilibrium(prob, p, rtol=1e-11)
+    assert info.converged
+    for precision in (sgn.SGN_FP64, sgn.SGN_FP32_IR):
+        ctx = _ctx(prob, precision=precision, newton_rtol=1e-11)
+        xd, pd = _cuda(x), _cuda(p)
+        ctx.equilibrium(pd, xd)
+        N = 2 * prob.n_x + prob.n_p
+        rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+        ctx.assemble(xd, pd, rhs)
+        ctx.factor()
+        sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+        info = ctx.solve(rhs, sol)
+        assert info.rel_res <= 1e-10
+        dx, dp, _ = _blocks(prob, _host(sol))
+        assert _rel(dp, prob.p_ref - p) <= 1e-9
+        st = D.dense_gn_step(prob, _host(xd), p)
+        assert _rel(dx, st.dx) <= 1e-8

@@ -230,3 +230,17 @@ def test_equilibrated_residual_hand_example():
     assert got == pytest.approx((5.0 / 6.0) / np.sqrt(2.0), rel=1e-15)
     # invariant under a common scale of matrix and right-hand side
     assert D.equilibrated_residual(7.0 * K, np.array([0.5, 0.0]), np.array([14.0, 21.0])) == pytest.approx(got, rel=1e-14)
+
+
+def test_no_targets_gives_the_regulariser_step():
+    """No targets: A = 0 and df/dx = 0, the reduced Hessian is C = mu I and g = mu (p - p_ref), so the
+    dense Gauss-Newton step is dp = p_ref - p exactly."""
+    prob = si.problem_2d(5, seed=4)
+    prob.target_dof = np.zeros(0, np.int32)
+    prob.target_val = np.zeros(0)
+    prob.length_scale = 1.0
+    p = 0.1 * np.random.default_rng(5).standard_normal(prob.n_p)
+    x, info = D.equilibrium(prob, p, rtol=1e-11)
+    assert info.converged
+    st = D.dense_gn_step(prob, x, p)
+    assert np.linalg.norm(st.dp - (prob.p_ref - p)) <= 1e-12 * np.linalg.norm(p)
