@@ -63,12 +63,15 @@ __global__ void k_csr_to_fronts(int64_t nnz, const int32_t* __restrict__ slot_ro
   }
 }
 
-// One block per child column: adds the child's Schur complement column
-// (rows >= column) into the parent front through the child's relative map.
+// One wavefront per child column (four per block): adds the child's Schur complement column
+// (rows >= column) into the parent front through the child's relative map.  A wavefront rather than
+// a block per column keeps the lanes busy on the short columns of small fronts.
 template <typename T>
-__global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, const int64_t* __restrict__ tasks, FrontArgs f,
-                                                    T* __restrict__ front) {
-  const int64_t b = blockIdx.x;
+__global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, int64_t ncols, const int64_t* __restrict__ tasks,
+                                                    FrontArgs f, T* __restrict__ front) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= ncols) return;
   int64_t lo = 0, hi = ntasks - 1;
   while (lo < hi) {  // last task with prefix <= b
     const int64_t mid = (lo + hi + 1) >> 1;
@@ -81,10 +84,21 @@ __global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, const int64_
   if (c >= uC) return;
   const int64_t mP = f.sn_m[P];
   const T* src = front + f.sn_front_off[C] + sC + (sC + c) * mC;
-  T* dst = front + f.sn_front_off[P];
+  T* dst = front + f.sn_front_off[P] + (int64_t)f.relmap[f.relmap_off[C] + c] * mP;
   const int32_t* rel = f.relmap + f.relmap_off[C];
-  const int64_t Cc = rel[c];
-  for (int64_t r = c + threadIdx.x; r < uC; r += 256) dst[rel[r] + Cc * mP] += src[r];
+  int64_t r = c + lane;
+  for (; r + 192 < uC; r += 256) {  // four rows in flight per lane
+    T v[4];
+    int32_t d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = src[r + 64 * q];
+      d[q] = rel[r + 64 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[d[q]] += v[q];
+  }
+  for (; r < uC; r += 64) dst[rel[r]] += src[r];
 }
 
 // Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, 256 threads.
@@ -655,7 +669,8 @@ void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* c
 template <typename T>
 void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const FrontArgs& f, T* front,
                        hipStream_t s) {
-  if (ntasks > 0 && nblocks > 0) k_extend_add<T><<<(unsigned)nblocks, 256, 0, s>>>(ntasks, tasks, f, front);
+  // nblocks: child columns of the round, one wavefront each
+  if (ntasks > 0 && nblocks > 0) k_extend_add<T><<<(unsigned)((nblocks + 3) / 4), 256, 0, s>>>(ntasks, nblocks, tasks, f, front);
 }
 
 template <typename T>

@@ -77,6 +77,14 @@ __device__ inline void publish(int* flag, int epoch, bool leader) {
   if (leader) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// value of v in lane src (src the same for the whole wavefront): two lane reads into scalar registers
+__device__ inline double lane_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -144,7 +152,7 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const double tk = lane < nq ? ld_dev(tp + q0 + lane) : 0.0;
 #pragma unroll
-    for (int k = 0; k < 64; ++k) acc += (double)fv[k] * __shfl(tk, k, 64);
+    for (int k = 0; k < 64; ++k) acc += (double)fv[k] * lane_bcast(tk, k);
   }
   part[wave][lane] = acc;
   __syncthreads();
@@ -156,7 +164,7 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
     const double z = __shfl(u, src, 64);
     double y = z;
     for (int j = 0; j < w; ++j) {
-      const double zj = __shfl(z, j, 64);
+      const double zj = lane_bcast(z, j);
       if (j < lane) y += Ld[j][lane] * zj;
     }
     if (lane < w) st_dev(tp + c0 + lane, y);
@@ -296,7 +304,7 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const double vl = lane < nq ? ld_dev(x + g0 + q0 + lane) : 0.0;
 #pragma unroll
-    for (int kk = 0; kk < 64; ++kk) acc += (double)fv[kk] * __shfl(vl, kk, 64);
+    for (int kk = 0; kk < 64; ++kk) acc += (double)fv[kk] * lane_bcast(vl, kk);
   }
   part[wave][lane] = acc;
   __syncthreads();
@@ -305,7 +313,7 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
     if (lane < w) z = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
     double v = z;  // v = L11^-T z
     for (int j = 0; j < w; ++j) {
-      const double zj = __shfl(z, j, 64);
+      const double zj = lane_bcast(z, j);
       if (j > lane) v += Ld[lane][j] * zj;
     }
     if (lane < w) st_dev(x + g0 + dst, v);
