@@ -1021,8 +1021,9 @@ sgn_status potential(sgn_ctx c, const double* x, const double* p, double* pi, do
     return SGN_OK;
   }
   const Analysis& A = c->A;
-  dev_dot(c, A.mesh.n_elems, c->d_ebuf + A.off_energy, nullptr, 4, A.stride, 0);
-  dev_dot(c, A.mesh.n_elems, c->d_ebuf + A.off_energy, nullptr, 5, A.stride, 1);
+  const double* energy = c->d_ebuf + (int64_t)A.off_energy * A.mesh.n_elems;  // component-major buffer
+  dev_dot(c, A.mesh.n_elems, energy, nullptr, 4, 1, 0);
+  dev_dot(c, A.mesh.n_elems, energy, nullptr, 5, 1, 1);
   dev_dot(c, A.mesh.n_x, c->d_fext, x, 6);
   int ns = 3;
   if (A.mesh.param_kind == 2) {

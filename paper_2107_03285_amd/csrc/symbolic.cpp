@@ -623,18 +623,18 @@ std::string analyse(Analysis& A) {
               int64_t B_ = m.fdof[vb] + cb;
               int64_t sl = find_slot(S, S.iperm[lam0 + A_], S.iperm[B_]);
               if (sl < 0) return "missing Kx slot";
-              contrib.emplace_back(sl, (int32_t)((int64_t)e * A.stride + A.off_hess + la * A.nd + lb));
+              contrib.emplace_back(sl, (int32_t)((int64_t)(A.off_hess + la * A.nd + lb) * m.n_elems + e));
               if (m.param_kind == 1) {
                 int64_t s2 = find_slot(S, S.iperm[lam0 + A_], S.iperm[nx + B_]);
                 if (s2 < 0) return "missing Kp slot";
-                contrib.emplace_back(s2, (int32_t)((int64_t)e * A.stride + A.off_kp + la * A.nd + lb));
+                contrib.emplace_back(s2, (int32_t)((int64_t)(A.off_kp + la * A.nd + lb) * m.n_elems + e));
               }
             }
           }
           if (m.param_kind == 0) {
             int64_t sl = find_slot(S, S.iperm[lam0 + A_], S.iperm[nx + e]);
             if (sl < 0) return "missing Kp slot";
-            contrib.emplace_back(sl, (int32_t)((int64_t)e * A.stride + A.off_grad + la));
+            contrib.emplace_back(sl, (int32_t)((int64_t)(A.off_grad + la) * m.n_elems + e));
           }
         }
       }
@@ -727,7 +727,7 @@ std::string analyse(Analysis& A) {
               if (r < c) continue;  // each lower entry takes one of the two symmetric products
               int64_t sl = find_slot(S, r, c);
               if (sl < 0) return "missing Kx slot";
-              contrib.emplace_back(sl, (int32_t)((int64_t)e * A.stride + A.off_hess + (a * d + ca) * A.nd + b * d + cb));
+              contrib.emplace_back(sl, (int32_t)((int64_t)(A.off_hess + (a * d + ca) * A.nd + b * d + cb) * m.n_elems + e));
             }
         }
       }
@@ -756,7 +756,7 @@ std::string analyse(Analysis& A) {
           int va = m.elems[(size_t)e * nv + a];
           if (!m.fixed[va])
             for (int c = 0; c < d; ++c)
-              S.vec_src[fill[m.fdof[va] + c]++] = (int32_t)((int64_t)e * A.stride + A.off_grad + a * d + c);
+              S.vec_src[fill[m.fdof[va] + c]++] = (int32_t)((int64_t)(A.off_grad + a * d + c) * m.n_elems + e);
         }
     }
     S.diag_kind.assign(N, 3);

@@ -118,7 +118,7 @@ struct Analysis {
   Mesh mesh;
   std::vector<int64_t> node_order;  // free nodes in ND order
   System sgn, kx;
-  // element buffer layout
+  // element buffer layout: component-major, value j of element e at j * n_elems + e
   int nd = 0;              // dofs per element (d+1)*d
   int off_hess = 0, off_grad = 0, off_kp = 0, off_energy = 0, stride = 0;
 };
