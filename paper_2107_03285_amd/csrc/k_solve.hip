@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "symbolic.h"
 
 namespace sgn {
 
@@ -90,6 +91,53 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Raw buffer loads: a 128-bit resource (base, byte range) plus a per-lane and a scalar byte
+// offset; a load outside the range returns 0.  The resource is wavefront-uniform by construction;
+// taking base and range through lane reads tells the compiler so even where they were computed
+// from vector loads (after an atomic or a store it cannot use scalar loads), and spares a
+// per-load loop over distinct resource values.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ inline rsrc_t buffer_rsrc(const void* p, int32_t bytes) {
+  const uint64_t u = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(u & 0xffffffffu));
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32));
+  void* base = (void*)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+template <typename T>
+__device__ inline T buffer_load(rsrc_t r, uint32_t voff, int32_t soff) {
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+  }
+}
+
+// Ld[i][j] = F[c0 + i, c0 + j] for i < j < w, else 0 (the upper triangle of the panel's diagonal
+// block, where the factorisation keeps the transposed inverse of the unit lower block).  All 16
+// loads of a thread are issued before the first LDS store: one memory latency per block, not 16.
+template <typename T>
+__device__ inline void load_inverse_block(const T* __restrict__ F, int64_t m, int c0, int w, int tid,
+                                          double (*Ld)[65]) {
+  // every load is unconditional, at a clamped in-block address, and masked afterwards: a
+  // predicated load would become a branch with a wait of its own
+  const rsrc_t rs = buffer_rsrc(F + c0 + (int64_t)c0 * m, (int32_t)(((int64_t)(w - 1) * m + w) * (int64_t)sizeof(T)));
+  const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
+  T v[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int idx = tid + 256 * t, i = idx & 63, j = idx >> 6;
+    const int ic = i < w ? i : 0, jc = j < w ? j : 0;
+    const T val = buffer_load<T>(rs, (uint32_t)(ic * (int)sizeof(T) + jc * cstr), 0);
+    v[t] = (i < j && j < w) ? val : (T)0;
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int idx = tid + 256 * t;
+    Ld[idx & 63][idx >> 6] = (double)v[t];
+  }
+}
+
 __global__ void __launch_bounds__(256) k_fwd_gather(const int32_t* __restrict__ level_sn, SolveArgs a,
                                                     const double* __restrict__ b) {
   const int tid = threadIdx.x;
@@ -109,18 +157,136 @@ __global__ void __launch_bounds__(256) k_fwd_gather(const int32_t* __restrict__ 
   }
 }
 
+// Forward solve of a front with a short panel chain (at most kSolveSeqPanels panels) by one block:
+// the panels in order, the y of solved panels kept in LDS, so no flags and no waiting.  Each
+// panel's sums, their order and the substitution are those of the pipelined form, so both give
+// bitwise the same y.
+template <typename T>
+__device__ void fwd_front_in_block(int J, const SolveArgs& a, const T* __restrict__ front, double (*part)[64],
+                                   double (*Ld)[65], double* ys, int* err) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J], m = f.sn_m[J], s = f.sn_begin[J + 1] - g0;
+  const int32_t pbase = a.panel_ptr[J];
+  const int np = a.panel_ptr[J + 1] - pbase - 1;
+  if (np > kSolveSeqPanels || s > kSolveSeqPanels * 64) {  // the task table never makes such a task
+    if (tid == 0) atomicExch(err, 2);
+    return;
+  }
+  const double* tv = a.tv + a.sn_vec_off[J];
+  double* tp = a.tp + a.sn_vec_off[J];
+  const T* F = front + f.sn_front_off[J];
+  const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
+#pragma unroll 1
+  for (int pi = 0; pi < np; ++pi) {
+    const int c0 = a.panel_col[pbase + pi], w = a.panel_col[pbase + pi + 1] - c0;
+    load_inverse_block(F, m, c0, w, tid, Ld);
+    const double tvl = lane < w ? tv[c0 + lane] : 0.0;
+    const int src = lane < w ? f.lperm[g0 + c0 + lane] - c0 : 0;
+    const uint32_t voff = (uint32_t)((lane < w ? lane : 0) * (int)sizeof(T));
+    double acc = 0.0;
+#pragma unroll 1
+    for (int q = wave; q < pi; q += 4) {
+      const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
+      const rsrc_t rs = buffer_rsrc(F + c0 + (int64_t)q0 * m, (int32_t)(((int64_t)(nq - 1) * m + 64) * (int64_t)sizeof(T)));
+      T fv[64];
+#pragma unroll
+      for (int k = 0; k < 64; ++k) fv[k] = buffer_load<T>(rs, voff, (k < nq ? k : 0) * cstr);
+      const double tk = lane < nq ? ys[q0 + lane] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 64; ++k) acc += (double)fv[k] * lane_bcast(tk, k);
+    }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      double u = 0.0;
+      if (lane < w) u = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+      const double z = __shfl(u, src, 64);
+      double y = z;
+      for (int j = 0; j < w; ++j) {
+        const double zj = lane_bcast(z, j);
+        if (j < lane) y += Ld[j][lane] * zj;
+      }
+      if (lane < w) {
+        ys[c0 + lane] = y;
+        tp[c0 + lane] = y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Backward solve of a front with a short panel chain by one block: the panels in reverse order,
+// the solved values kept in LDS at their front positions; bitwise the pipelined form's results.
+template <typename T>
+__device__ void bwd_front_in_block(int J, const SolveArgs& a, const T* __restrict__ front, double* __restrict__ x,
+                                   double (*part)[64], double (*Ld)[65], double* xs, int* err) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J], m = f.sn_m[J], s = f.sn_begin[J + 1] - g0;
+  const int32_t pbase = a.panel_ptr[J];
+  const int np = a.panel_ptr[J + 1] - pbase - 1;
+  if (np > kSolveSeqPanels || s > kSolveSeqPanels * 64) {
+    if (tid == 0) atomicExch(err, 2);
+    return;
+  }
+  const double* tv = a.tv + a.sn_vec_off[J];
+  const T* F = front + f.sn_front_off[J];
+#pragma unroll 1
+  for (int pi = np - 1; pi >= 0; --pi) {
+    const int c0 = a.panel_col[pbase + pi], w = a.panel_col[pbase + pi + 1] - c0;
+    load_inverse_block(F, m, c0, w, tid, Ld);
+    const double tvl = lane < w ? tv[c0 + lane] : 0.0;
+    const int dst = lane < w ? f.lperm[g0 + c0 + lane] : 0;
+    double acc = 0.0;
+    const uint32_t voff = (uint32_t)((lane < w ? lane : 0) * m * (int64_t)sizeof(T));
+#pragma unroll 1
+    for (int q = np - 1 - wave; q > pi; q -= 4) {
+      const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
+      const rsrc_t rs = buffer_rsrc(F + q0 + (int64_t)c0 * m, (int32_t)(((int64_t)(w - 1) * m + nq) * (int64_t)sizeof(T)));
+      T fv[64];
+#pragma unroll
+      for (int kk = 0; kk < 64; ++kk) fv[kk] = buffer_load<T>(rs, voff, (kk < nq ? kk : 0) * (int)sizeof(T));
+      const double vl = lane < nq ? xs[q0 + lane] : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 64; ++kk) acc += (double)fv[kk] * lane_bcast(vl, kk);
+    }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      double z = 0.0;
+      if (lane < w) z = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+      double v = z;
+      for (int j = 0; j < w; ++j) {
+        const double zj = lane_bcast(z, j);
+        if (j > lane) v += Ld[lane][j] * zj;
+      }
+      if (lane < w) {
+        xs[dst] = v;
+        x[g0 + dst] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ tasks, int64_t ntasks, SolveArgs a,
                                                     const T* __restrict__ front, int* counter, int* flags,
                                                     int epoch, int* err) {
   __shared__ double part[4][64];
   __shared__ double Ld[64][65];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double ys[kSolveSeqPanels * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (blockIdx.x >= ntasks) return;
+  const int J = tasks[2 * blockIdx.x];
+  if (tasks[2 * blockIdx.x + 1] < 0) {
+    fwd_front_in_block<T>(J, a, front, part, Ld, ys, err);
+    return;
+  }
   // the task list holds one entry per panel of each front; the block serves that front and takes
   // the front's next panel in start order, so it only ever waits for blocks that started before it
-  const int J = tasks[2 * blockIdx.x];
-  const int pi = ticket(counter + J);
+  const int pi = __builtin_amdgcn_readfirstlane(ticket(counter + J));
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], m = f.sn_m[J];
   const int32_t pbase = a.panel_ptr[J];
@@ -131,22 +297,22 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
   // the panel's own block does not depend on other panels: load it before waiting.  The factor keeps
   // the inverse of the panel's unit lower block in the diagonal block's upper triangle, transposed:
   // Ld[j][i] = (L11^-1)[i][j] for j < i
-  for (int idx = tid; idx < w * w; idx += 256) {
-    const int i = idx % w, j = idx / w;
-    Ld[i][j] = i < j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
-  }
+  load_inverse_block(F, m, c0, w, tid, Ld);
   // values of this panel that no other panel produces: read before any wait
   const double tvl = lane < w ? tv[c0 + lane] : 0.0;
   const int src = lane < w ? f.lperm[g0 + c0 + lane] - c0 : 0;
   // contributions of the earlier panels, panel Q handled by wave Q % 4
   double acc = 0.0;
-  const T* rowbase = F + (c0 + (lane < w ? lane : 0));
+  const uint32_t voff = (uint32_t)((lane < w ? lane : 0) * (int)sizeof(T));
+  const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
   for (int q = wave; q < pi; q += 4) {
     const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
-    // the factor entries do not depend on the other panel: issue their loads first
+    // the factor entries do not depend on the other panel: issue their loads first (rows c0.. of
+    // columns q0..q0+nq-1 through one buffer resource, scalar column offsets)
+    const rsrc_t rs = buffer_rsrc(F + c0 + (int64_t)q0 * m, (int32_t)(((int64_t)(nq - 1) * m + 64) * (int64_t)sizeof(T)));
     T fv[64];  // factor precision in registers, widened at use
 #pragma unroll
-    for (int k = 0; k < 64; ++k) fv[k] = (k < nq && lane < w) ? rowbase[(int64_t)(q0 + k) * m] : (T)0;
+    for (int k = 0; k < 64; ++k) fv[k] = buffer_load<T>(rs, voff, (k < nq ? k : 0) * cstr);
     if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -173,12 +339,15 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
 }
 
 // Split-k partial sums of L21 y: block (front, 256-row strip, k-chunk of 256 columns), one row per
-// thread; each column of the strip is one contiguous 1 KB (FP32) piece, read 64 columns at a time
-// with all loads in flight; the sum over k runs in ascending order.
+// thread; each column of the strip is one contiguous 1 KB (FP32) piece.  A thread keeps kRectK
+// column loads in flight and reads the chunk's y values from LDS, where they are
+// staged once per block; the sum over k runs in ascending order.
+constexpr int kRectK = 32;
 template <typename T>
-__global__ void __launch_bounds__(256) k_fwd_rect(const int32_t* __restrict__ level_sn, SolveArgs a,
+__global__ void __launch_bounds__(256, 4) k_fwd_rect(const int32_t* __restrict__ level_sn, SolveArgs a,
                                                   const T* __restrict__ front) {
-  const int tid = threadIdx.x, lane = tid & 63;
+  __shared__ double yk[256];
+  const int tid = threadIdx.x;
   const int J = level_sn[blockIdx.x];
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J], u = m - s;
@@ -188,22 +357,22 @@ __global__ void __launch_bounds__(256) k_fwd_rect(const int32_t* __restrict__ le
   const double* tp = a.tp + a.sn_vec_off[J];
   const T* F = front + f.sn_front_off[J];
   const int64_t r = r0 + tid;
-  const int64_t kend = kb + 256 < s ? kb + 256 : s;
-  const T* rowp = F + s + (r < u ? r : 0);
+  const int nk = (int)(s - kb < 256 ? s - kb : 256);
+  yk[tid] = tid < nk ? tp[kb + tid] : 0.0;
+  // the strip's columns through one buffer resource: per-column offsets are scalar, so the
+  // loads in flight cost no address registers; rows past u read row r0 and are not stored
+  const rsrc_t rs = buffer_rsrc(F + s + r0 + kb * m, (int32_t)(((int64_t)(nk - 1) * m + 256) * (int64_t)sizeof(T)));
+  const uint32_t voff = (uint32_t)((r < u ? tid : 0) * (int)sizeof(T));
+  const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
+  __syncthreads();
   double acc = 0.0;
 #pragma unroll 1
-  for (int64_t k0 = kb; k0 < kend; k0 += 64) {
-    const int nk = (int)(kend - k0 < 64 ? kend - k0 : 64);
-    const double tk = lane < nk ? tp[k0 + lane] : 0.0;
-    const T* cp = rowp + k0 * m;
-#pragma unroll 1
-    for (int kk = 0; kk < 64; kk += 16) {  // 16 loads in flight per lane keep the register count low
-      T fv[16];
+  for (int k0 = 0; k0 < nk; k0 += kRectK) {
+    T fv[kRectK];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) fv[k] = (kk + k < nk && r < u) ? cp[(int64_t)(kk + k) * m] : (T)0;
+    for (int k = 0; k < kRectK; ++k) fv[k] = buffer_load<T>(rs, voff, (k0 + k < nk ? k0 + k : 0) * cstr);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc += (double)fv[k] * __shfl(tk, kk + k, 64);
-    }
+    for (int k = 0; k < kRectK; ++k) acc += (double)fv[k] * yk[k0 + k];
   }
   if (r < u) a.part[a.sn_part_off[J] + blockIdx.z * u + r] = acc;
 }
@@ -272,33 +441,36 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
                                                     int* counter, int* flags, int epoch, int* err) {
   __shared__ double part[4][64];
   __shared__ double Ld[64][65];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double xs[kSolveSeqPanels * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (blockIdx.x >= ntasks) return;
   const int J = tasks[2 * blockIdx.x];
+  if (tasks[2 * blockIdx.x + 1] < 0) {
+    bwd_front_in_block<T>(J, a, front, x, part, Ld, xs, err);
+    return;
+  }
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], m = f.sn_m[J];
   const int32_t pbase = a.panel_ptr[J];
   const int np = a.panel_ptr[J + 1] - pbase - 1;
-  const int pi = np - 1 - ticket(counter + J);  // the front's panels in reverse start order
+  const int pi = np - 1 - __builtin_amdgcn_readfirstlane(ticket(counter + J));  // the front's panels in reverse start order
   const int c0 = a.panel_col[pbase + pi], c1 = a.panel_col[pbase + pi + 1], w = c1 - c0;
   const double* tv = a.tv + a.sn_vec_off[J];
   const T* F = front + f.sn_front_off[J];
-  for (int idx = tid; idx < w * w; idx += 256) {  // Ld[i][j] = (L11^-1)[j][i] for i < j (see the forward solve)
-    const int i = idx % w, j = idx / w;
-    Ld[i][j] = i < j ? (double)F[(c0 + i) + (int64_t)(c0 + j) * m] : 0.0;
-  }
+  load_inverse_block(F, m, c0, w, tid, Ld);  // Ld[i][j] = (L11^-1)[j][i] for i < j (see the forward solve)
   const double tvl = lane < w ? tv[c0 + lane] : 0.0;  // read before any wait
   const int dst = lane < w ? f.lperm[g0 + c0 + lane] : 0;
   // contributions of the later panels Q (every fourth one per wave, in the order they are
   // solved): lane = column c0+lane of panel R, summing L[q0 + k', c0 + lane] v[q0 + k']
   double acc = 0.0;
-  const T* colbase = F + (int64_t)(c0 + (lane < w ? lane : 0)) * m;
+  const uint32_t voff = (uint32_t)((lane < w ? lane : 0) * m * (int64_t)sizeof(T));
   for (int q = np - 1 - wave; q > pi; q -= 4) {  // completion order: last panel first
     const int q0 = a.panel_col[pbase + q], nq = a.panel_col[pbase + q + 1] - q0;
-    const T* col = colbase + q0;
+    // rows q0.. of the panel's columns, unconditional loads at clamped rows (masked by v = 0)
+    const rsrc_t rs = buffer_rsrc(F + q0 + (int64_t)c0 * m, (int32_t)(((int64_t)(w - 1) * m + nq) * (int64_t)sizeof(T)));
     T fv[64];  // factor precision in registers, widened at use
 #pragma unroll
-    for (int kk = 0; kk < 64; ++kk) fv[kk] = (kk < nq && lane < w) ? col[kk] : (T)0;
+    for (int kk = 0; kk < 64; ++kk) fv[kk] = buffer_load<T>(rs, voff, (kk < nq ? kk : 0) * (int)sizeof(T));
     if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);

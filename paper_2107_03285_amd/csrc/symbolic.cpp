@@ -401,6 +401,13 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
       const int t = S.level_sn[q];
       const int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
+      if (np >= 1 && np <= kSolveSeqPanels) {  // short panel chain: one block walks it
+        S.solve_fwd_tasks.push_back(t);
+        S.solve_fwd_tasks.push_back(-1);
+        S.solve_bwd_tasks.push_back(t);
+        S.solve_bwd_tasks.push_back(-1);
+        continue;
+      }
       for (int k = 0; k < np; ++k) {
         S.solve_fwd_tasks.push_back(t);
         S.solve_fwd_tasks.push_back(k);

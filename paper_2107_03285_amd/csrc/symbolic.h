@@ -14,6 +14,7 @@ constexpr int kPanel = 64;        // panel width of the blocked front factorisat
 constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
 constexpr int kTile = 64;         // update tile edge (equal to the kernels' kUpdTile)
 constexpr int kSolveKC = 256;     // k-chunk of the split-k L21 y product in the forward solve
+constexpr int kSolveSeqPanels = 8;  // fronts with at most this many panels are solved by one block
 
 enum SystemKind { SYS_SGN = 0, SYS_KX = 1 };
 
@@ -98,7 +99,7 @@ struct System {
   std::vector<int64_t> panel_tasks;      // (sn, c0, c1) per task: 3 entries
   std::vector<int64_t> upd_tasks;        // (sn, k0, k1, cb, ce, tile_prefix): 6 entries
   std::vector<int64_t> ea_tasks;         // (child, parent, work_prefix): 3 entries
-  std::vector<int32_t> solve_fwd_tasks;  // (sn, panel index) pairs, per level
+  std::vector<int32_t> solve_fwd_tasks;  // (sn, panel index) pairs, per level; (sn, -1): whole front in one block
   std::vector<int32_t> solve_bwd_tasks;
   int64_t n_panels = 0;                  // total panels (ready flags of the pipelined solves)
   // element -> lower CSR slot contributions and their inverse (gather) map
