@@ -54,6 +54,7 @@ struct DevSys {
   int64_t* panel_tasks = nullptr;
   int64_t* upd_tasks = nullptr;
   int64_t* ea_tasks = nullptr;
+  int32_t* ea_col_task = nullptr;
   int64_t* vec_ptr = nullptr;
   int32_t* vec_src = nullptr;
   int32_t* solve_fwd_tasks = nullptr;
@@ -289,6 +290,7 @@ size_t layout(sgn_ctx c, char* base) {
     D.panel_tasks = L.take<int64_t>(S.panel_tasks.size());
     D.upd_tasks = L.take<int64_t>(S.upd_tasks.size());
     D.ea_tasks = L.take<int64_t>(S.ea_tasks.size());
+    D.ea_col_task = L.take<int32_t>(S.ea_col_task.size());
     D.vec_ptr = L.take<int64_t>(S.vec_ptr.size());
     D.vec_src = L.take<int32_t>(S.vec_src.size());
     D.solve_fwd_tasks = L.take<int32_t>(S.solve_fwd_tasks.size());
@@ -557,7 +559,8 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
     const LevelPlan& P = S.levels[L];
     for (size_t r = 0; r < P.ea_begin.size(); ++r) {
       const int64_t nt = P.ea_end[r] - P.ea_begin[r];
-      launch_extend_add<T>(nt, P.ea_work[r], D.ea_tasks + P.ea_begin[r] * 3, f, front, st);
+      launch_extend_add<T>(nt, P.ea_work[r], D.ea_tasks + P.ea_begin[r] * 3, D.ea_col_task + P.ea_col_begin[r], f,
+                           front, st);
     }
     for (const PanelStep& ps : P.steps) {
       const int64_t nt = ps.task_end - ps.task_begin;
@@ -1782,6 +1785,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.panel_tasks, S.panel_tasks, st));
     HIPCHK(up(D.upd_tasks, S.upd_tasks, st));
     HIPCHK(up(D.ea_tasks, S.ea_tasks, st));
+    HIPCHK(up(D.ea_col_task, S.ea_col_task, st));
     HIPCHK(up(D.vec_ptr, S.vec_ptr, st));
     HIPCHK(up(D.vec_src, S.vec_src, st));
     HIPCHK(up(D.solve_fwd_tasks, S.solve_fwd_tasks, st));

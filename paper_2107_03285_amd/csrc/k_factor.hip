@@ -65,19 +65,20 @@ __global__ void k_csr_to_fronts(int64_t nnz, const int32_t* __restrict__ slot_ro
 
 // One wavefront per child column (four per block): adds the child's Schur complement column
 // (rows >= column) into the parent front through the child's relative map.  A wavefront rather than
-// a block per column keeps the lanes busy on the short columns of small fronts.
+// a block per column keeps the lanes busy on the short columns of small fronts.  The column's task
+// comes from a per-column table; rows go eight per lane at a time, every load (clamped to the
+// column's first row past its end) issued before the first store.  The relative map is injective,
+// so the parent entries a wavefront reads and writes are distinct.
 template <typename T>
 __global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, int64_t ncols, const int64_t* __restrict__ tasks,
-                                                    FrontArgs f, T* __restrict__ front) {
+                                                    const int32_t* __restrict__ col_task, FrontArgs f,
+                                                    T* __restrict__ front) {
+  constexpr int R = 8;
   const int lane = threadIdx.x & 63;
   const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= ncols) return;
-  int64_t lo = 0, hi = ntasks - 1;
-  while (lo < hi) {  // last task with prefix <= b
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (tasks[mid * 3 + 2] <= b) lo = mid;
-    else hi = mid - 1;
-  }
+  const int lo = col_task[b];
+  if (lo < 0 || lo >= ntasks) return;  // the table never holds such an entry
   const int C = (int)tasks[lo * 3], P = (int)tasks[lo * 3 + 1];
   const int64_t c = b - tasks[lo * 3 + 2];
   const int64_t sC = f.sn_begin[C + 1] - f.sn_begin[C], mC = f.sn_m[C], uC = mC - sC;
@@ -86,19 +87,22 @@ __global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, int64_t ncol
   const T* src = front + f.sn_front_off[C] + sC + (sC + c) * mC;
   T* dst = front + f.sn_front_off[P] + (int64_t)f.relmap[f.relmap_off[C] + c] * mP;
   const int32_t* rel = f.relmap + f.relmap_off[C];
-  int64_t r = c + lane;
-  for (; r + 192 < uC; r += 256) {  // four rows in flight per lane
-    T v[4];
-    int32_t d[4];
+  for (int64_t r0 = c; r0 < uC; r0 += 64 * R) {
+    T v[R], o[R];
+    int32_t d[R];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      v[q] = src[r + 64 * q];
-      d[q] = rel[r + 64 * q];
+    for (int q = 0; q < R; ++q) {
+      const int64_t r = r0 + lane + 64 * q;
+      const int64_t rc = r < uC ? r : c;
+      v[q] = src[rc];
+      d[q] = rel[rc];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dst[d[q]] += v[q];
+    for (int q = 0; q < R; ++q) o[q] = dst[d[q]];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (r0 + lane + 64 * q < uC) dst[d[q]] = o[q] + v[q];
   }
-  for (; r < uC; r += 64) dst[rel[r]] += src[r];
 }
 
 // Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, 256 threads.
@@ -158,12 +162,26 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
   const int64_t gbase = f.sn_begin[sn] + c0;
   T* F = front + f.sn_front_off[sn];
   const double tol = f.piv_tol;
-  for (int j = wave; j < w; j += 4)
-    if (lane >= j && lane < w) {
-      const double v = (double)F[(c0 + lane) + (int64_t)(c0 + j) * m];
-      A[lane][j] = v;
-      A[j][lane] = v;
+  {
+    // the panel's lower triangle: all 16 loads of a thread issued unconditionally (clamped to the
+    // panel, masked when staged) before the first LDS store
+    const int lc = lane < w ? lane : 0;
+    T lv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int j = wave + 4 * t, jc = j < w ? j : 0;
+      lv[t] = F[(c0 + lc) + (int64_t)(c0 + jc) * m];
     }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int j = wave + 4 * t;
+      if (j < w && lane >= j && lane < w) {
+        const double v = (double)lv[t];
+        A[lane][j] = v;
+        A[j][lane] = v;
+      }
+    }
+  }
   if (tid < 64) pos[tid] = tid;
   const int gend_r = lane < w ? (int)(f.var_group_end[gbase + lane] - gbase) : w;
   int ptype = 0;
@@ -373,19 +391,34 @@ __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ 
       accd[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
       accf[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
     }
+  // every operand the block needs, loaded up front and unconditionally (clamped to in-front
+  // addresses, masked when staged): 32 loads in flight per thread instead of one at a time.
+  // Element q of a thread is (row rr = tid & 63, k = (tid + 256 q) >> 6).
+  T pv[16], px[16];
+  {
+    const int rr = tid & 63;
+    const int64_t rc = r0 + rr < m ? r0 + rr : r0;
+    const int cc = rr < w ? rr : 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = (tid + 256 * q) >> 6;
+      const int kc = k < w ? k : 0;
+      pv[q] = F[rc + (int64_t)(c0 + ps[k]) * m];  // ps[k] = 0 past w
+      px[q] = F[(c0 + kc) + (int64_t)(c0 + cc) * m];
+    }
+  }
+#pragma unroll
   for (int kb = 0; kb < 64; kb += 16) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q4 = 0; q4 < 4; ++q4) {
+      const int q = kb / 4 + q4;
       const int idx = tid + 256 * q;
-      const int rr = idx & 63, kk = idx >> 6;
-      const int k = kb + kk;
+      const int rr = idx & 63, k = idx >> 6, kk = k - kb;
       const int64_t r = r0 + rr;
-      sV[kk][rr] = (k < w && r < m) ? F[r + (int64_t)(c0 + ps[k]) * m] : (T)0;
+      sV[kk][rr] = (k < w && r < m) ? pv[q] : (T)0;
       // sX[kk][c] = X[c][k]: 1 on the diagonal, stored at (row c0+k, column c0+c) for c > k
       const int c = rr;
-      T xv = (T)0;
-      if (k < w && c < w) xv = c == k ? (T)1 : (c > k ? F[(c0 + k) + (int64_t)(c0 + c) * m] : (T)0);
-      sX[kk][c] = xv;
+      sX[kk][c] = (k < w && c < w) ? (c == k ? (T)1 : (c > k ? px[q] : (T)0)) : (T)0;
     }
     __syncthreads();
 #pragma unroll
@@ -667,10 +700,11 @@ void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* c
 }
 
 template <typename T>
-void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const FrontArgs& f, T* front,
-                       hipStream_t s) {
+void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const int32_t* col_task,
+                       const FrontArgs& f, T* front, hipStream_t s) {
   // nblocks: child columns of the round, one wavefront each
-  if (ntasks > 0 && nblocks > 0) k_extend_add<T><<<(unsigned)((nblocks + 3) / 4), 256, 0, s>>>(ntasks, nblocks, tasks, f, front);
+  if (ntasks > 0 && nblocks > 0)
+    k_extend_add<T><<<(unsigned)((nblocks + 3) / 4), 256, 0, s>>>(ntasks, nblocks, tasks, col_task, f, front);
 }
 
 template <typename T>
@@ -706,8 +740,10 @@ template void launch_csr_to_fronts<double>(int64_t, const int32_t*, const int32_
                                            const double*, double*, hipStream_t);
 template void launch_csr_to_fronts<float>(int64_t, const int32_t*, const int32_t*, const int64_t*, const double*,
                                           const double*, float*, hipStream_t);
-template void launch_extend_add<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
-template void launch_extend_add<float>(int64_t, int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+template void launch_extend_add<double>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, double*,
+                                        hipStream_t);
+template void launch_extend_add<float>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, float*,
+                                       hipStream_t);
 template void launch_panel_diag<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
 template void launch_panel_diag<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_panel_trsm<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);

@@ -378,6 +378,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.panel_tasks.clear();
   S.upd_tasks.clear();
   S.ea_tasks.clear();
+  S.ea_col_task.clear();
   S.solve_fwd_tasks.clear();
   S.solve_bwd_tasks.clear();
   S.n_panels = (int64_t)S.panel_col.size();
@@ -419,7 +420,9 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     P.bwd_end = (int64_t)S.solve_bwd_tasks.size() / 2;
     for (int r = 0; r < P.max_children; ++r) {
       P.ea_begin.push_back((int64_t)S.ea_tasks.size() / 3);
+      P.ea_col_begin.push_back((int64_t)S.ea_col_task.size());
       int64_t work = 0;
+      int32_t task = 0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
         int t = S.level_sn[q];
         if (S.child_ptr[t + 1] - S.child_ptr[t] > r) {
@@ -428,7 +431,8 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
           S.ea_tasks.push_back(c);
           S.ea_tasks.push_back(t);
           S.ea_tasks.push_back(work);
-          work += uc;  // one block per child column
+          S.ea_col_task.insert(S.ea_col_task.end(), (size_t)uc, task++);
+          work += uc;  // one wavefront per child column
         }
       }
       P.ea_end.push_back((int64_t)S.ea_tasks.size() / 3);
