@@ -55,6 +55,7 @@ struct DevSys {
   int64_t* upd_tasks = nullptr;
   int64_t* ea_tasks = nullptr;
   int32_t* ea_col_task = nullptr;
+  int32_t* fill_tasks = nullptr;
   int64_t* vec_ptr = nullptr;
   int32_t* vec_src = nullptr;
   int32_t* solve_fwd_tasks = nullptr;
@@ -291,6 +292,7 @@ size_t layout(sgn_ctx c, char* base) {
     D.upd_tasks = L.take<int64_t>(S.upd_tasks.size());
     D.ea_tasks = L.take<int64_t>(S.ea_tasks.size());
     D.ea_col_task = L.take<int32_t>(S.ea_col_task.size());
+    D.fill_tasks = L.take<int32_t>(S.fill_tasks.size());
     D.vec_ptr = L.take<int64_t>(S.vec_ptr.size());
     D.vec_src = L.take<int32_t>(S.vec_src.size());
     D.solve_fwd_tasks = L.take<int32_t>(S.solve_fwd_tasks.size());
@@ -512,10 +514,6 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   hipStream_t st = c->stream;
   T* front = reinterpret_cast<T*>(D.front);
   launch_row_scaling(S.N, D.frowptr, D.fslot, D.vals, D.scale, st);
-  launch_fill_bytes(((int64_t)(S.front_total * sizeof(T)) + 15) / 16 * 16, front, st);
-  launch_csr_to_fronts<T>((int64_t)S.colind.size(), D.slot_row, D.colind, D.csr_front_pos, D.vals, D.scale, front,
-                          st);
-  launch_fill_i32(4, 0, c->d_cnt, st);
   FrontArgs f;
   f.sn_begin = D.sn_begin;
   f.sn_m = D.sn_m;
@@ -531,6 +529,10 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   f.lperm = D.lperm;
   f.counters = c->d_cnt;
   f.piv_tol = piv_tol;
+  launch_zero_fronts<T>((int64_t)S.fill_tasks.size() / 2, D.fill_tasks, f, front, st);
+  launch_csr_to_fronts<T>((int64_t)S.colind.size(), D.slot_row, D.colind, D.csr_front_pos, D.vals, D.scale, front,
+                          st);
+  launch_fill_i32(4, 0, c->d_cnt, st);
   const bool prof = c->opt.profile != 0 && si == 0;
   size_t nev = 0;
   double upd_flops = 0.0;
@@ -1786,6 +1788,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.upd_tasks, S.upd_tasks, st));
     HIPCHK(up(D.ea_tasks, S.ea_tasks, st));
     HIPCHK(up(D.ea_col_task, S.ea_col_task, st));
+    HIPCHK(up(D.fill_tasks, S.fill_tasks, st));
     HIPCHK(up(D.vec_ptr, S.vec_ptr, st));
     HIPCHK(up(D.vec_src, S.vec_src, st));
     HIPCHK(up(D.solve_fwd_tasks, S.solve_fwd_tasks, st));

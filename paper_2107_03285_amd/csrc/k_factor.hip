@@ -63,6 +63,25 @@ __global__ void k_csr_to_fronts(int64_t nnz, const int32_t* __restrict__ slot_ro
   }
 }
 
+// Zeroes rows >= column - 63 of 64 columns of one front: the lower triangle, which the assembly
+// and the extend-add accumulate into, and a band of 63 entries above the diagonal.  The trailing
+// update reads that band (its diagonal tiles, and the L columns of a partial last k-chunk, which
+// are multiplied by zeroed W entries), so the band must hold finite values; entries further above
+// the diagonal are never read before the factorisation writes them (the panels' diagonal blocks
+// and the W rows of the panel solve), so the rest of the upper triangle is left as it is.
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_fronts(const int32_t* __restrict__ tasks, FrontArgs f,
+                                                     T* __restrict__ front) {
+  const int sn = tasks[2 * blockIdx.x], c0 = tasks[2 * blockIdx.x + 1];
+  const int64_t m = f.sn_m[sn];
+  T* F = front + f.sn_front_off[sn];
+  const int64_t c1 = c0 + 64 < m ? c0 + 64 : m;
+  for (int64_t c = c0; c < c1; ++c) {
+    T* col = F + c * m;
+    for (int64_t r = (c >= 63 ? c - 63 : 0) + threadIdx.x; r < m; r += 256) col[r] = (T)0;
+  }
+}
+
 // One wavefront per child column (four per block): adds the child's Schur complement column
 // (rows >= column) into the parent front through the child's relative map.  A wavefront rather than
 // a block per column keeps the lanes busy on the short columns of small fronts.  The column's task
@@ -700,6 +719,11 @@ void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* c
 }
 
 template <typename T>
+void launch_zero_fronts(int64_t ntasks, const int32_t* tasks, const FrontArgs& f, T* front, hipStream_t s) {
+  if (ntasks > 0) k_zero_fronts<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, f, front);
+}
+
+template <typename T>
 void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const int32_t* col_task,
                        const FrontArgs& f, T* front, hipStream_t s) {
   // nblocks: child columns of the round, one wavefront each
@@ -740,6 +764,8 @@ template void launch_csr_to_fronts<double>(int64_t, const int32_t*, const int32_
                                            const double*, double*, hipStream_t);
 template void launch_csr_to_fronts<float>(int64_t, const int32_t*, const int32_t*, const int64_t*, const double*,
                                           const double*, float*, hipStream_t);
+template void launch_zero_fronts<double>(int64_t, const int32_t*, const FrontArgs&, double*, hipStream_t);
+template void launch_zero_fronts<float>(int64_t, const int32_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_extend_add<double>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, double*,
                                         hipStream_t);
 template void launch_extend_add<float>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, float*,

@@ -391,33 +391,54 @@ __global__ void __launch_bounds__(256) k_fwd_rect_sum(const int32_t* __restrict_
   a.tp[a.sn_vec_off[J] + s + r] = a.tv[a.sn_vec_off[J] + s + r] - acc;
 }
 
-// z_k = (D^-1 y)_k - sum_r L21[r, k] x[row_r] into tv[k]; one wavefront per pivot column
+// z_k = (D^-1 y)_k - sum_r L21[r, k] x[row_r] into tv[k]; one wavefront per four pivot columns,
+// which share the gathered x[row_r].  Per 256 rows a lane issues its 16 factor loads (clamped to
+// the front, masked by x = 0) alongside the row-index and x loads, so the factor stream does not
+// wait on the gather.  Each column's sum runs over the rows in the same per-lane order as a
+// one-column-per-wavefront loop, then across lanes by the same butterfly.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bwd_rect(const int32_t* __restrict__ level_sn, SolveArgs a,
                                                   const T* __restrict__ front, const double* __restrict__ x) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int J = level_sn[blockIdx.x];
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J], u = m - s;
-  const int64_t k = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (k >= s) return;
+  const int64_t k0 = (int64_t)blockIdx.y * 16 + wave * 4;
+  if (k0 >= s) return;
+  const int nk = (int)(s - k0 < 4 ? s - k0 : 4);
   const double* tp = a.tp + a.sn_vec_off[J];
   double* tv = a.tv + a.sn_vec_off[J];
-  const T* F = front + f.sn_front_off[J] + s + k * m;
   const int32_t* rows = f.sn_rows + f.sn_rows_ptr[J];
-  double acc = 0.0;
-  int64_t r = lane;
-  for (; r + 192 < u; r += 256) {  // four independent loads in flight per lane
-    const double a0 = (double)F[r], a1 = (double)F[r + 64], a2 = (double)F[r + 128], a3 = (double)F[r + 192];
-    const double v0 = x[rows[r]], v1 = x[rows[r + 64]], v2 = x[rows[r + 128]], v3 = x[rows[r + 192]];
-    acc += a0 * v0;
-    acc += a1 * v1;
-    acc += a2 * v2;
-    acc += a3 * v3;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (u > 0) {
+    // rows s.. of columns k0..k0+nk-1
+    const rsrc_t rs = buffer_rsrc(front + f.sn_front_off[J] + s + k0 * m,
+                                  (int32_t)(((int64_t)(nk - 1) * m + u) * (int64_t)sizeof(T)));
+    const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
+#pragma unroll 1
+    for (int64_t r0 = 0; r0 < u; r0 += 256) {
+      double xv[4];
+      T fv[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + lane + 64 * q;
+        const int64_t rc = r < u ? r : 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fv[c][q] = buffer_load<T>(rs, (uint32_t)(rc * (int64_t)sizeof(T)), (c < nk ? c : 0) * cstr);
+        const double xl = x[rows[rc]];
+        xv[q] = r < u ? xl : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += (double)fv[c][q] * xv[q];
+    }
   }
-  for (; r < u; r += 64) acc += (double)F[r] * x[rows[r]];
-  acc = wave_sum(acc);
-  if (lane == 0) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = wave_sum(acc[c]);
+  if (lane < nk) {
+    const int64_t k = k0 + lane;
+    const double sum = lane == 0 ? acc[0] : lane == 1 ? acc[1] : lane == 2 ? acc[2] : acc[3];
     const int t = f.pivtype[g0 + k];
     double w;
     if (a.wd) {
@@ -431,7 +452,7 @@ __global__ void __launch_bounds__(256) k_bwd_rect(const int32_t* __restrict__ le
       const double A = f.dpiv[g0 + k - 1], B = f.epiv[g0 + k - 1], C = f.dpiv[g0 + k];
       w = (A * tp[k] - B * tp[k - 1]) / (A * C - B * B);
     }
-    tv[k] = w - acc;
+    tv[k] = w - sum;
   }
 }
 
@@ -517,7 +538,7 @@ void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const
                       const SolveArgs& a, const T* front, double* x, int* counter, int* flags, int epoch, int* err,
                       hipStream_t s) {
   if (nsn <= 0) return;
-  dim3 g((unsigned)nsn, (unsigned)((max_s + 3) / 4));
+  dim3 g((unsigned)nsn, (unsigned)((max_s + 15) / 16));
   k_bwd_rect<T><<<g, 256, 0, s>>>(level_sn, a, front, x);
   if (ntasks > 0)
     k_bwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, x, counter, flags, epoch, err);

@@ -93,6 +93,10 @@ struct FrontArgs {
 template <typename T>
 void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* colind, const int64_t* pos,
                           const double* vals, const double* scale, T* front, hipStream_t s);
+// zeroes rows >= column - 63 of every front (the lower triangle and a band above the diagonal);
+// ntasks (sn, first column) pairs
+template <typename T>
+void launch_zero_fronts(int64_t ntasks, const int32_t* tasks, const FrontArgs& f, T* front, hipStream_t s);
 template <typename T>
 void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const int32_t* col_task,
                        const FrontArgs& f, T* front, hipStream_t s);

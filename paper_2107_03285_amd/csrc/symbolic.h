@@ -89,6 +89,7 @@ struct System {
   std::vector<int32_t> var_sn;           // supernode of each var
   std::vector<int64_t> csr_front_pos;    // per lower CSR entry: element offset in its front
   int64_t front_total = 0, vec_total = 0;
+  std::vector<int32_t> fill_tasks;       // (sn, first column) pairs: 64-column groups of the fronts
   // panels: per supernode a list of local column starts (last = s)
   std::vector<int32_t> panel_ptr;        // [nsn+1]
   std::vector<int32_t> panel_col;        // local starts, with a terminating s per sn
