@@ -72,13 +72,25 @@ __global__ void k_csr_to_fronts(int64_t nnz, const int32_t* __restrict__ slot_ro
 template <typename T>
 __global__ void __launch_bounds__(256) k_zero_fronts(const int32_t* __restrict__ tasks, FrontArgs f,
                                                      T* __restrict__ front) {
+  // one wavefront per column: scalar stores up to 16-byte alignment, then 16-byte stores, then the
+  // scalar tail
+  constexpr int64_t V = 16 / sizeof(T);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sn = tasks[2 * blockIdx.x], c0 = tasks[2 * blockIdx.x + 1];
   const int64_t m = f.sn_m[sn];
   T* F = front + f.sn_front_off[sn];
   const int64_t c1 = c0 + 64 < m ? c0 + 64 : m;
-  for (int64_t c = c0; c < c1; ++c) {
+  for (int64_t c = c0 + wave; c < c1; c += 4) {
     T* col = F + c * m;
-    for (int64_t r = (c >= 63 ? c - 63 : 0) + threadIdx.x; r < m; r += 256) col[r] = (T)0;
+    const int64_t r0 = c >= 63 ? c - 63 : 0;
+    int64_t head = (int64_t)(((16 - ((uintptr_t)(col + r0) & 15)) & 15) / sizeof(T));
+    if (head > m - r0) head = m - r0;
+    if (lane < head) col[r0 + lane] = (T)0;
+    const int64_t rb = r0 + head, nv = (m - rb) / V;
+    uint4* vb = reinterpret_cast<uint4*>(col + rb);
+    for (int64_t v = lane; v < nv; v += 64) vb[v] = make_uint4(0u, 0u, 0u, 0u);
+    const int64_t rt = rb + nv * V;
+    if (rt + lane < m) col[rt + lane] = (T)0;
   }
 }
 
