@@ -63,8 +63,6 @@ struct DevSys {
   int64_t* sn_part_off = nullptr;
   double* part = nullptr;      // split-k partial sums of the forward solve
   int* solve_ctr = nullptr;    // [2 * nsn] per-front ticket counters of the forward / backward pipelined solves
-  int* solve_flags = nullptr;  // [n_panels] ready flags (epoch numbers)
-  int epoch = 0;
   int64_t* const_slots = nullptr;
   int64_t n_const = 0;
   double* vals = nullptr;
@@ -175,7 +173,7 @@ struct sgn_ctx_s {
     float *dec, *emb, *dh[2], *de[2], *dz, *dx, *dagg, *ddec, *demb, *part;
   } g{};
   bool gnn_fwd_done = false;
-  bool capturing = false;             // enqueueing into a graph: no host syncs, flags reset per sweep
+  bool capturing = false;             // enqueueing into a graph: no host syncs
   hipStream_t gstream = nullptr;      // stream of the captured step graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -300,7 +298,6 @@ size_t layout(sgn_ctx c, char* base) {
     D.solve_ctr = L.take<int>(2 * (size_t)S.nsn);
     D.sn_part_off = L.take<int64_t>(S.sn_part_off.size());
     D.part = L.take<double>(S.part_total);
-    D.solve_flags = L.take<int>(S.n_panels);
     D.n_const = (si == 0 && A.mesh.param_kind == 2) ? nx : 0;
     D.const_slots = L.take<int64_t>(D.n_const);
     D.vals = L.take<double>(S.colind.size());
@@ -667,13 +664,11 @@ sgn_status fwd_sweep_t(sgn_ctx c, int si, const double* b_new) {
   const SolveArgs a = solve_args(c, si);
   const T* front = reinterpret_cast<const T*>(D.front);
   launch_fill_i32(2 * (int64_t)S.nsn, 0, D.solve_ctr, st);
-  if (c->capturing) launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
   int* err = c->d_cnt + 12;
-  const int e_fwd = ++D.epoch;
   for (int L = 0; L < S.nlevels; ++L) {
     const LevelPlan& P = S.levels[L];
     launch_fwd_level<T>(P.sn_end - P.sn_begin, P.max_u, P.max_s, D.level_sn + P.sn_begin, D.solve_fwd_tasks + 2 * P.fwd_begin,
-                        P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr, D.solve_flags, e_fwd, err, st);
+                        P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr, err, st);
   }
   HIPCHK(hipGetLastError());
   return SGN_OK;
@@ -689,15 +684,11 @@ sgn_status bwd_sweep_t(sgn_ctx c, int si, double* x_new, const double* wd) {
   a.wd = wd;
   const T* front = reinterpret_cast<const T*>(D.front);
   launch_fill_i32(2 * (int64_t)S.nsn, 0, D.solve_ctr, st);  // tickets start at 0
-  // a replayed graph reuses its epochs: flags from the previous replay must not count as ready
-  if (c->capturing) launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
   int* err = c->d_cnt + 12;
-  const int e_bwd = ++D.epoch;
   for (int L = S.nlevels - 1; L >= 0; --L) {
     const LevelPlan& P = S.levels[L];
     launch_bwd_level<T>(P.sn_end - P.sn_begin, P.max_s, D.level_sn + P.sn_begin, D.solve_bwd_tasks + 2 * P.bwd_begin,
-                        P.bwd_end - P.bwd_begin, a, front, x_new, D.solve_ctr + S.nsn, D.solve_flags, e_bwd, err,
-                        st);
+                        P.bwd_end - P.bwd_begin, a, front, x_new, D.solve_ctr + S.nsn, err, st);
   }
   HIPCHK(hipGetLastError());
   return SGN_OK;
@@ -1799,8 +1790,6 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
       HIPCHK(up(D.grp_node, S.grp_node, st));
       HIPCHK(up(D.grp_vec, S.grp_vec, st));
     }
-    launch_fill_i32(std::max<int64_t>(1, S.n_panels), -1, D.solve_flags, st);
-    D.epoch = 0;
     if (D.n_const) {
       std::vector<int64_t> cs(D.n_const);
       for (int64_t i = 0; i < D.n_const; ++i) {

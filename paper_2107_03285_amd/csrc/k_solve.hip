@@ -24,7 +24,10 @@
 // Pipelined blocks take ordered tickets from their front's atomic counter, so
 // a block only ever waits for blocks of its front that started before it;
 // every wait is bounded and reports a timeout through an error flag instead of
-// hanging.  Vectors
+// hanging.  A panel's results are their own ready signal: before the pipelined
+// kernel of a level runs, its values hold a pending marker (a signalling-NaN bit
+// pattern that no arithmetic result has), and a consumer polls each value until
+// the marker is gone.  Vectors
 // are FP64 whatever the factor precision, and every sum has a fixed order,
 // so solves are bitwise reproducible.
 #include <hip/hip_runtime.h>
@@ -46,10 +49,12 @@ __device__ inline int ticket(int* counter) {
 }
 
 // Panel results pass between blocks of one launch through device-coherent accesses only: the
-// producer writes them with device-scope atomic stores (written through the per-die caches), waits
-// for their completion and then sets the panel's flag; the consumer polls the flag and reads them
-// with device-scope atomic loads.  No whole-cache write-back or invalidation is needed, so blocks
-// that wait do not evict the factor data other blocks are streaming.
+// producer writes each value with a device-scope atomic store (written through the per-die caches),
+// the consumer polls it with device-scope atomic loads until it is no longer the pending marker.
+// Each 8-byte value is written and read whole, so no ordering between values is needed, and no
+// whole-cache write-back or invalidation either.
+constexpr long long kPending = 0x7ff4d3adbeef5a5all;  // signalling NaN: never an arithmetic result
+
 __device__ inline double ld_dev(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -57,25 +62,17 @@ __device__ inline void st_dev(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// true once flag == epoch; false (and err set) when the bounded wait runs out or an
-// earlier wait of the same solve already timed out (so a failure ends every wait fast)
-__device__ inline bool wait_ready(const int* flag, int epoch, int* err) {
+// the value at p once it is no longer the pending marker; 0 (and err set) when the bounded wait runs
+// out or an earlier wait of the same solve already timed out (so a failure ends every wait fast)
+__device__ inline double wait_value(const double* p, int* err) {
   for (long it = 0; it < kSpinLimit; ++it) {
-    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) return true;
-    if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    const double v = ld_dev(p);
+    if (__double_as_longlong(v) != kPending) return v;
+    if ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0.0;
     __builtin_amdgcn_s_sleep(2);
   }
   atomicExch(err, 1);
-  return false;
-}
-
-// Called by the whole wavefront after its st_dev stores of the panel: waits until they have
-// completed, then the leader lane sets the flag.
-__device__ inline void publish(int* flag, int epoch, bool leader) {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  if (leader) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return 0.0;
 }
 
 // value of v in lane src (src the same for the whole wavefront): two lane reads into scalar registers
@@ -145,7 +142,9 @@ __global__ void __launch_bounds__(256) k_fwd_gather(const int32_t* __restrict__ 
   const FrontArgs& f = a.f;
   const int64_t g0 = f.sn_begin[J], s = f.sn_begin[J + 1] - g0, m = f.sn_m[J];
   double* tv = a.tv + a.sn_vec_off[J];
+  double* tp = a.tp + a.sn_vec_off[J];
   for (int64_t k = tid; k < m; k += 256) tv[k] = k < s ? b[g0 + k] : 0.0;
+  for (int64_t k = tid; k < s; k += 256) tp[k] = __longlong_as_double(kPending);  // y not yet solved
   __syncthreads();
   for (int32_t q = a.child_ptr[J]; q < a.child_ptr[J + 1]; ++q) {
     const int C = a.child_list[q];
@@ -203,9 +202,12 @@ __device__ void fwd_front_in_block(int J, const SolveArgs& a, const T* __restric
       if (lane < w) u = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
       const double z = __shfl(u, src, 64);
       double y = z;
-      for (int j = 0; j < w; ++j) {
+      // all 64 columns, unpredicated, eight LDS reads in flight at a time: Ld is zero outside its
+      // strict triangle and past the panel's width, so the extra terms add nothing
+#pragma unroll 8
+      for (int j = 0; j < 64; ++j) {
         const double zj = lane_bcast(z, j);
-        if (j < lane) y += Ld[j][lane] * zj;
+        y += Ld[j][lane] * zj;  // zero unless j < lane < w
       }
       if (lane < w) {
         ys[c0 + lane] = y;
@@ -257,9 +259,12 @@ __device__ void bwd_front_in_block(int J, const SolveArgs& a, const T* __restric
       double z = 0.0;
       if (lane < w) z = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
       double v = z;
-      for (int j = 0; j < w; ++j) {
+      // all 64 columns, unpredicated, eight LDS reads in flight at a time: Ld is zero outside its
+      // strict triangle and past the panel's width, so the extra terms add nothing
+#pragma unroll 8
+      for (int j = 0; j < 64; ++j) {
         const double zj = lane_bcast(z, j);
-        if (j > lane) v += Ld[lane][j] * zj;
+        v += Ld[lane][j] * zj;  // zero unless lane < j < w
       }
       if (lane < w) {
         xs[dst] = v;
@@ -272,8 +277,7 @@ __device__ void bwd_front_in_block(int J, const SolveArgs& a, const T* __restric
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ tasks, int64_t ntasks, SolveArgs a,
-                                                    const T* __restrict__ front, int* counter, int* flags,
-                                                    int epoch, int* err) {
+                                                    const T* __restrict__ front, int* counter, int* err) {
   __shared__ double part[4][64];
   __shared__ double Ld[64][65];
   __shared__ double ys[kSolveSeqPanels * 64];
@@ -313,10 +317,7 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
     T fv[64];  // factor precision in registers, widened at use
 #pragma unroll
     for (int k = 0; k < 64; ++k) fv[k] = buffer_load<T>(rs, voff, (k < nq ? k : 0) * cstr);
-    if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
-    __builtin_amdgcn_wave_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const double tk = lane < nq ? ld_dev(tp + q0 + lane) : 0.0;
+    const double tk = lane < nq ? wait_value(tp + q0 + lane, err) : 0.0;
 #pragma unroll
     for (int k = 0; k < 64; ++k) acc += (double)fv[k] * lane_bcast(tk, k);
   }
@@ -329,12 +330,14 @@ __global__ void __launch_bounds__(256) k_fwd_panels(const int32_t* __restrict__ 
     if (lane < w) u = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
     const double z = __shfl(u, src, 64);
     double y = z;
-    for (int j = 0; j < w; ++j) {
+    // all 64 columns, unpredicated, eight LDS reads in flight at a time: Ld is zero outside its
+    // strict triangle and past the panel's width, so the extra terms add nothing
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
       const double zj = lane_bcast(z, j);
-      if (j < lane) y += Ld[j][lane] * zj;
+      y += Ld[j][lane] * zj;  // zero unless j < lane < w
     }
     if (lane < w) st_dev(tp + c0 + lane, y);
-    publish(flags + pbase + pi, epoch, lane == 0);
   }
 }
 
@@ -398,7 +401,7 @@ __global__ void __launch_bounds__(256) k_fwd_rect_sum(const int32_t* __restrict_
 // one-column-per-wavefront loop, then across lanes by the same butterfly.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bwd_rect(const int32_t* __restrict__ level_sn, SolveArgs a,
-                                                  const T* __restrict__ front, const double* __restrict__ x) {
+                                                  const T* __restrict__ front, double* __restrict__ x) {
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int J = level_sn[blockIdx.x];
   const FrontArgs& f = a.f;
@@ -453,13 +456,14 @@ __global__ void __launch_bounds__(256) k_bwd_rect(const int32_t* __restrict__ le
       w = (A * tp[k] - B * tp[k - 1]) / (A * C - B * B);
     }
     tv[k] = w - sum;
+    x[g0 + k] = __longlong_as_double(kPending);  // solved by the panel kernel of this level
   }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ tasks, int64_t ntasks, SolveArgs a,
                                                     const T* __restrict__ front, double* __restrict__ x,
-                                                    int* counter, int* flags, int epoch, int* err) {
+                                                    int* counter, int* err) {
   __shared__ double part[4][64];
   __shared__ double Ld[64][65];
   __shared__ double xs[kSolveSeqPanels * 64];
@@ -492,10 +496,7 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
     T fv[64];  // factor precision in registers, widened at use
 #pragma unroll
     for (int kk = 0; kk < 64; ++kk) fv[kk] = buffer_load<T>(rs, voff, (kk < nq ? kk : 0) * (int)sizeof(T));
-    if (lane == 0) wait_ready(flags + pbase + q, epoch, err);
-    __builtin_amdgcn_wave_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const double vl = lane < nq ? ld_dev(x + g0 + q0 + lane) : 0.0;
+    const double vl = lane < nq ? wait_value(x + g0 + q0 + lane, err) : 0.0;
 #pragma unroll
     for (int kk = 0; kk < 64; ++kk) acc += (double)fv[kk] * lane_bcast(vl, kk);
   }
@@ -505,12 +506,14 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
     double z = 0.0;
     if (lane < w) z = tvl - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
     double v = z;  // v = L11^-T z
-    for (int j = 0; j < w; ++j) {
+    // all 64 columns, unpredicated, eight LDS reads in flight at a time: Ld is zero outside its
+    // strict triangle and past the panel's width, so the extra terms add nothing
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
       const double zj = lane_bcast(z, j);
-      if (j > lane) v += Ld[lane][j] * zj;
+      v += Ld[lane][j] * zj;  // zero unless lane < j < w
     }
     if (lane < w) st_dev(x + g0 + dst, v);
-    publish(flags + pbase + pi, epoch, lane == 0);
   }
 }
 
@@ -518,11 +521,11 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
 
 template <typename T>
 void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* level_sn, const int32_t* tasks,
-                      int64_t ntasks, const SolveArgs& a, const T* front, const double* b, int* counter, int* flags,
-                      int epoch, int* err, hipStream_t s) {
+                      int64_t ntasks, const SolveArgs& a, const T* front, const double* b, int* counter, int* err,
+                      hipStream_t s) {
   if (nsn <= 0) return;
   k_fwd_gather<<<(unsigned)nsn, 256, 0, s>>>(level_sn, a, b);
-  if (ntasks > 0) k_fwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, counter, flags, epoch, err);
+  if (ntasks > 0) k_fwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, counter, err);
   if (max_u > 0) {
     if (max_s > 0) {
       dim3 g((unsigned)nsn, (unsigned)((max_u + 255) / 256), (unsigned)((max_s + 255) / 256));
@@ -535,23 +538,21 @@ void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* 
 
 template <typename T>
 void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
-                      const SolveArgs& a, const T* front, double* x, int* counter, int* flags, int epoch, int* err,
-                      hipStream_t s) {
+                      const SolveArgs& a, const T* front, double* x, int* counter, int* err, hipStream_t s) {
   if (nsn <= 0) return;
   dim3 g((unsigned)nsn, (unsigned)((max_s + 15) / 16));
   k_bwd_rect<T><<<g, 256, 0, s>>>(level_sn, a, front, x);
   if (ntasks > 0)
-    k_bwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, x, counter, flags, epoch, err);
+    k_bwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, x, counter, err);
 }
 
 template void launch_fwd_level<double>(int64_t, int64_t, int64_t, const int32_t*, const int32_t*, int64_t,
-                                       const SolveArgs&, const double*, const double*, int*, int*, int, int*,
-                                       hipStream_t);
+                                       const SolveArgs&, const double*, const double*, int*, int*, hipStream_t);
 template void launch_fwd_level<float>(int64_t, int64_t, int64_t, const int32_t*, const int32_t*, int64_t,
-                                      const SolveArgs&, const float*, const double*, int*, int*, int, int*, hipStream_t);
+                                      const SolveArgs&, const float*, const double*, int*, int*, hipStream_t);
 template void launch_bwd_level<double>(int64_t, int64_t, const int32_t*, const int32_t*, int64_t, const SolveArgs&,
-                                       const double*, double*, int*, int*, int, int*, hipStream_t);
+                                       const double*, double*, int*, int*, hipStream_t);
 template void launch_bwd_level<float>(int64_t, int64_t, const int32_t*, const int32_t*, int64_t, const SolveArgs&,
-                                      const float*, double*, int*, int*, int, int*, hipStream_t);
+                                      const float*, double*, int*, int*, hipStream_t);
 
 }  // namespace sgn

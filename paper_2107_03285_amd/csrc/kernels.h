@@ -128,16 +128,13 @@ struct SolveArgs {
 };
 // One tree level of the forward / backward solve.  tasks: (front, panel) pairs, one per panel of
 // each front of the level (the block serves the front, the panel comes from the front's ticket);
-// counter: zeroed per-front ticket counters [nsn]; flags: per-panel ready flags compared against
-// epoch; err: set when a bounded wait runs out.
+// counter: zeroed per-front ticket counters [nsn]; err: set when a bounded wait runs out.
 template <typename T>
 void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
-                      const SolveArgs& a, const T* front, const double* b, int* counter, int* flags, int epoch,
-                      int* err, hipStream_t s);
+                      const SolveArgs& a, const T* front, const double* b, int* counter, int* err, hipStream_t s);
 template <typename T>
 void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
-                      const SolveArgs& a, const T* front, double* x, int* counter, int* flags, int epoch, int* err,
-                      hipStream_t s);
+                      const SolveArgs& a, const T* front, double* x, int* counter, int* err, hipStream_t s);
 
 // ---------------------------------------------------------------- node-block preconditioner
 struct PcArgs {
