@@ -110,7 +110,31 @@ def copy_calibration():
     torch.cuda.empty_cache()
 
 
-def batch_leg(steps: int, warmup: int, dev: str = "cuda:0"):
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2107_03285_amd", "tuning")
+
+
+def tuned_options(sgn, workload: str, **kw):
+    """FP32 options for a workload with the blocking of its autotuner record, if one exists; returns
+    (options, where the blocking came from)."""
+    o = sgn.default_options(**kw)
+    path = os.path.join(TUNING_DIR, f"{workload}.json")
+    if os.path.exists(path):
+        return sgn.apply_tuning(o, sgn.load_tuning(path)), os.path.relpath(path, os.path.dirname(TUNING_DIR))
+    return o, "library defaults"
+
+
+def run_autotune(sgn, prob, x, p, dev):
+    """Tunes the FP32 schedule blocking of prob at (x, p) and stores the record beside the package."""
+    os.makedirs(TUNING_DIR, exist_ok=True)
+    base = sgn.default_options(precision=sgn.SGN_FP32_IR, rhs_kind=sgn.SGN_RHS_KKT)
+    t0 = time.perf_counter()
+    rec = sgn.autotune(prob, x, p, base, reps=2, path=os.path.join(TUNING_DIR, f"{prob.name}.json"))
+    log(f"[bench] autotune {prob.name}: {sgn.tuning_of(sgn.apply_tuning(base, rec))} in "
+        f"{time.perf_counter() - t0:.0f} s; candidates ms {['%.1f' % v for v in rec['candidate_ms']]}")
+    return rec
+
+
+def batch_leg(steps: int, warmup: int, dev: str = "cuda:0", autotune: bool = False):
     """256 independent 2D membranes (8..48 nodes per side, seeds 10000..10255) as one disjoint union:
     the captured-graph step (level-batched FP32 factorisation, 3 refinement sweeps) against solving
     the same problems one at a time with their own FP64 contexts (assemble, factor, solve)."""
@@ -132,7 +156,9 @@ def batch_leg(steps: int, warmup: int, dev: str = "cuda:0"):
     u.target_val = xs.cpu().numpy()[u.target_dof]
     del ref
     torch.cuda.empty_cache()
-    o = sgn.default_options(precision=sgn.SGN_FP32_IR, rhs_kind=sgn.SGN_RHS_KKT)
+    if autotune:
+        run_autotune(sgn, u, x0, p0, dev)
+    o, blocking_src = tuned_options(sgn, u.name, precision=sgn.SGN_FP32_IR, rhs_kind=sgn.SGN_RHS_KKT)
     ctx = sgn.Context(u, o).allocate(dev)
     rhs = torch.zeros(N, dtype=torch.float64, device=dev)
     sol = torch.zeros(N, dtype=torch.float64, device=dev)
@@ -181,6 +207,7 @@ def batch_leg(steps: int, warmup: int, dev: str = "cuda:0"):
             "problem_steps_per_s_batched": len(probs) / t_graph, "one_at_a_time_fp64_ms": 1e3 * t_single,
             "problem_steps_per_s_one_at_a_time": len(probs) / t_single, "speedup": t_single / t_graph,
             "max_rel_residual": rel, "max_dp_rel_diff_vs_single_fp64": err,
+            "blocking": dict(sgn.tuning_of(o), source=blocking_src),
             "graph": "assemble + KKT rhs + FP32 LDL^T + solve + 3 FP64 refinement sweeps, replayed"}
 
 
@@ -196,6 +223,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events on the update kernel")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-problem leg")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the blocking autotuner on the workload and the batched union first and store its "
+                         "records (paper_2107_03285_amd/tuning/); later runs use them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB copy first (for scaling hardware byte counters)")
     args = ap.parse_args()
@@ -215,10 +245,17 @@ def main():
     log(f"[bench] workload {prob.name}: n_x={prob.n_x} n_p={prob.n_p} N={2 * prob.n_x + prob.n_p}")
     paths = [s.strip() for s in args.paths.split(",") if s.strip()]
 
+    blocking = {}
+
     def make_ctx(precision, rhs_kind=None):
         t0 = time.perf_counter()
-        o = sgn.default_options(precision=precision, profile=0 if args.no_profile else 1,
-                                rhs_kind=sgn.SGN_RHS_KKT if rhs_kind is None else rhs_kind)
+        kw = dict(precision=precision, profile=0 if args.no_profile else 1,
+                  rhs_kind=sgn.SGN_RHS_KKT if rhs_kind is None else rhs_kind)
+        if precision == sgn.SGN_FP32_IR:  # the tuning records are taken for the FP32 path
+            o, src = tuned_options(sgn, prob.name, **kw)
+        else:
+            o, src = sgn.default_options(**kw), "library defaults"
+        blocking[precision] = dict(sgn.tuning_of(o), source=src)
         ctx = sgn.Context(prob, o).allocate(dev)
         log(f"[bench] context precision={precision} ready in {time.perf_counter() - t0:.1f} s "
             f"(workspace {ctx.workspace_size() / 1e9:.1f} GB)")
@@ -240,6 +277,8 @@ def main():
     ref_ctx.set_targets(prob.target_val, ell)
     ref_ctx.equilibrium(p, x)  # re-establishes the Kx factor for the adjoint right-hand side
     N = 2 * prob.n_x + prob.n_p
+    if args.autotune:
+        run_autotune(sgn, prob, x, p, dev)
 
     def run_step(ctx, rhs, sol):
         ctx.assemble(x, p, rhs)
@@ -358,7 +397,7 @@ def main():
     batch = None
     if not args.no_batch:
         log("[bench] batched leg: 256 2D problems, captured-graph step vs one at a time")
-        batch = batch_leg(max(3, args.steps // 2), 1, dev)
+        batch = batch_leg(max(3, args.steps // 2), 1, dev, autotune=args.autotune)
         log(f"[bench] batched: {batch}")
     cpu = None
     if not args.no_cpu_baseline:
@@ -377,6 +416,7 @@ def main():
                    "path": head, "rhs": "KKT form [-df/dx; -df/dp; 0] (Appendix A, Theorem 2: same dp as [0; -g; 0])",
                    "solve_rtol": 1e-10},
         "paths": results,
+        "blocking": {("fp32" if k == sgn.SGN_FP32_IR else "fp64"): v for k, v in blocking.items()},
         "fp32_vs_fp64_step": err,
         "speedup_vs_fp64": (results[head]["steps_per_s"] / results["fp64"]["steps_per_s"]
                             if "fp64" in results else None),

@@ -118,6 +118,14 @@ typedef struct {
   int profile;                  /* 1: time every trailing-update launch with HIP events */
   int max_gmres;                /* restart cycles of the FGMRES(30) escalation of the saddle-point
                                    solves' refinement, 0: none */
+  /* Blocking of the factorisation and solve schedules (no effect on the mathematics; chosen per
+   * problem family by sgn_autotune, 0 = library default).  Fronts fall in buckets by their order
+   * m: m < 1024, 1024 <= m < 4096, m >= 4096. */
+  int outer_panels[3];          /* per bucket: trailing update beyond a block of this many 64-column
+                                   panels is delayed to the block's end (1..16, default 4) */
+  int seq_panels;               /* fronts with at most this many panels are solved by one
+                                   workgroup instead of a pipeline of workgroups (-1: none, 0:
+                                   default 8, else 1..8) */
 } sgn_options;
 
 typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;
@@ -349,6 +357,21 @@ sgn_status sgn_selftest_mfma(int prec, const double* d_a, const double* d_b, dou
 const char* sgn_last_error(sgn_ctx ctx);
 /* Release host state (the workspace stays owned by the caller). */
 void sgn_destroy(sgn_ctx ctx);
+
+/* Autotuner of the schedule's blocking, the batched form's requirement that the blocking per
+ * front-size bucket be chosen by measurement (Sec. 5 reports the method's cost as time per step,
+ * which is what is minimised).  For prob and the options *base, at the state (d_x [n_x], d_p [n_p],
+ * device), each candidate setting runs in a context of its own (created, its workspace allocated
+ * with hipMalloc on the current device, everything freed before the next) and is timed as the best
+ * of `reps` (1..100) rounds of assembly + factorisation + solve of a right-hand side of ones, after
+ * one warm-up round, in host wall milliseconds on `stream`.  Coordinate descent from *base: each
+ * bucket's outer_panels in {1, 2, 4, 8, 16}, then seq_panels in {-1, 2, 4, 8}; a candidate replaces the
+ * incumbent only if it is at least 1% faster.  *best receives *base with the chosen setting;
+ * h_ms (optional, host, room for 16) the milliseconds of every candidate in the order tried, the
+ * first being *base itself; *n_cand (optional) their count (at most 16).  Errors of a candidate's
+ * context (e.g. SGN_E_NOMEM when the device cannot hold it) end the search and are returned. */
+sgn_status sgn_autotune(const sgn_problem* prob, const sgn_options* base, const double* d_x, const double* d_p,
+                        int reps, void* stream, sgn_options* best, double* h_ms, int* n_cand);
 
 #ifdef __cplusplus
 }

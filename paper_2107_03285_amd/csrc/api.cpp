@@ -1693,6 +1693,14 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
     m.comp_ptr = {0, pr->n_nodes};
   }
   if (!(pr->E0 > 0) || !(pr->nu > -1.0 && pr->nu < 0.5)) return fail(c, SGN_E_ARG, "invalid material");
+  for (int b = 0; b < kTuneBuckets; ++b) {
+    const int v = c->opt.outer_panels[b];
+    if (v < 0 || v > 16) return fail(c, SGN_E_ARG, "outer_panels must be 1..16 (0: default)");
+    c->A.tune.outer_panels[b] = v == 0 ? kOuterPanels : v;
+  }
+  if (c->opt.seq_panels < -1 || c->opt.seq_panels > kSolveSeqPanels)
+    return fail(c, SGN_E_ARG, "seq_panels must be -1..8 (0: default)");
+  c->A.tune.seq_panels = c->opt.seq_panels == 0 ? kSolveSeqPanels : (c->opt.seq_panels < 0 ? 0 : c->opt.seq_panels);
   std::string err = analyse(c->A);
   if (!err.empty()) return fail(c, SGN_E_ARG, "symbolic analysis: " + err);
   err = build_gnn_graph(m, c->G);
@@ -2224,6 +2232,96 @@ sgn_status sgn_get_stats(sgn_ctx c, sgn_stats* out) {
 const char* sgn_last_error(sgn_ctx c) {
   if (!c) return "null context";
   return c->err.c_str();
+}
+
+namespace {
+
+// One candidate of the autotuner: a context of its own at (d_x, d_p); wall milliseconds per round of
+// assembly + factorisation + solve (right-hand side of ones), best of `reps` rounds after a warm-up.
+sgn_status time_candidate(const sgn_problem* prob, const sgn_options& o, const double* d_x, const double* d_p,
+                          int reps, void* stream, double* ms) {
+  sgn_ctx c = nullptr;
+  sgn_status st = sgn_create(prob, &o, stream, &c);
+  void* ws = nullptr;
+  double *rhs = nullptr, *sol = nullptr;
+  auto done = [&](sgn_status r) {
+    if (ws) (void)hipFree(ws);
+    if (rhs) (void)hipFree(rhs);
+    if (sol) (void)hipFree(sol);
+    sgn_destroy(c);
+    return r;
+  };
+  if (st != SGN_OK) return done(st);
+  size_t bytes = 0;
+  if ((st = sgn_workspace_size(c, &bytes)) != SGN_OK) return done(st);
+  const int64_t N = c->A.sgn.N;
+  if (hipMalloc(&ws, bytes) != hipSuccess || hipMalloc((void**)&rhs, N * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&sol, N * sizeof(double)) != hipSuccess)
+    return done(SGN_E_NOMEM);
+  if ((st = sgn_set_workspace(c, ws, bytes)) != SGN_OK) return done(st);
+  launch_fill(N, 1.0, rhs, c->stream);
+  double best = 1e300;
+  for (int r = 0; r <= reps; ++r) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return done(SGN_E_HIP);
+    const double t0 = now_ms();
+    if ((st = sgn_assemble(c, d_x, d_p, nullptr, nullptr, nullptr)) != SGN_OK) return done(st);
+    if ((st = sgn_factor(c, nullptr)) != SGN_OK) return done(st);
+    if ((st = sgn_solve(c, rhs, sol, nullptr)) != SGN_OK) return done(st);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return done(SGN_E_HIP);
+    const double t = now_ms() - t0;
+    if (r > 0 && t < best) best = t;  // round 0 warms up
+  }
+  *ms = best;
+  return done(SGN_OK);
+}
+
+}  // namespace
+
+sgn_status sgn_autotune(const sgn_problem* prob, const sgn_options* base, const double* d_x, const double* d_p,
+                        int reps, void* stream, sgn_options* best, double* h_ms, int* n_cand) {
+  if (!prob || !base || !d_x || !d_p || !best || reps < 1 || reps > 100) return SGN_E_ARG;
+  sgn_options cur = *base;
+  int nc = 0;
+  double cur_ms = 0.0;
+  sgn_status st = time_candidate(prob, cur, d_x, d_p, reps, stream, &cur_ms);
+  if (st != SGN_OK) return st;
+  if (h_ms) h_ms[nc] = cur_ms;
+  ++nc;
+  auto consider = [&](const sgn_options& cand) -> sgn_status {
+    double ms = 0.0;
+    const sgn_status s = time_candidate(prob, cand, d_x, d_p, reps, stream, &ms);
+    if (s != SGN_OK) return s;
+    if (h_ms) h_ms[nc] = ms;
+    ++nc;
+    if (ms < 0.99 * cur_ms) {  // a candidate must beat the incumbent by 1%
+      cur = cand;
+      cur_ms = ms;
+    }
+    return SGN_OK;
+  };
+  static const int kSpans[] = {1, 2, 4, 8, 16};
+  static const int kSeq[] = {-1, 2, 4, 8};
+  for (int b = 0; b < kTuneBuckets; ++b) {
+    const int inc = cur.outer_panels[b] == 0 ? kOuterPanels : cur.outer_panels[b];
+    for (int v : kSpans) {
+      if (v == inc) continue;
+      sgn_options cand = cur;
+      cand.outer_panels[b] = v;
+      if ((st = consider(cand)) != SGN_OK) return st;
+    }
+  }
+  {
+    const int inc = cur.seq_panels == 0 ? kSolveSeqPanels : cur.seq_panels;
+    for (int v : kSeq) {
+      if (v == inc) continue;
+      sgn_options cand = cur;
+      cand.seq_panels = v;
+      if ((st = consider(cand)) != SGN_OK) return st;
+    }
+  }
+  *best = cur;
+  if (n_cand) *n_cand = nc;
+  return SGN_OK;
 }
 
 void sgn_destroy(sgn_ctx c) { delete c; }

@@ -190,7 +190,8 @@ int64_t update_tiles(int64_t m, int64_t cb, int64_t ce) {
 std::string finish_system(System& S, const std::vector<TreeNode>& tree,
                           const std::vector<int64_t>& node_var_begin,   // per order position: first var
                           const std::vector<int64_t>& node_pub_begin,   // per order position: first public var
-                          int pub_per_node, const std::vector<std::vector<int64_t>>& node_adj_rank) {
+                          int pub_per_node, const std::vector<std::vector<int64_t>>& node_adj_rank,
+                          const Tuning& tune) {
   const int64_t N = S.N;
   S.etree = etree_liu(N, S.rowptr, S.colind);
   S.slot_row.resize(S.colind.size());
@@ -410,7 +411,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
       const int t = S.level_sn[q];
       const int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
-      if (np >= 1 && np <= kSolveSeqPanels) {  // short panel chain: one block walks it
+      if (np >= 1 && np <= tune.seq_panels) {  // short panel chain: one block walks it
         S.solve_fwd_tasks.push_back(t);
         S.solve_fwd_tasks.push_back(-1);
         S.solve_bwd_tasks.push_back(t);
@@ -468,8 +469,9 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         int t = S.level_sn[q];
         int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
         if (k >= np) continue;
-        int ob = (k / kOuterPanels) * kOuterPanels;
-        int oe = std::min(np, ob + kOuterPanels);
+        const int span = tune.outer_panels[tune_bucket(S.sn_m[t])];
+        int ob = (k / span) * span;
+        int oe = std::min(np, ob + span);
         int64_t c0 = S.panel_col[S.panel_ptr[t] + k], c1 = S.panel_col[S.panel_ptr[t] + k + 1];
         int64_t oend = S.panel_col[S.panel_ptr[t] + oe];
         if (c1 < oend) {
@@ -489,8 +491,9 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         int t = S.level_sn[q];
         int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
         if (k >= np) continue;
-        int ob = (k / kOuterPanels) * kOuterPanels;
-        int oe = std::min(np, ob + kOuterPanels);
+        const int span = tune.outer_panels[tune_bucket(S.sn_m[t])];
+        int ob = (k / span) * span;
+        int oe = std::min(np, ob + span);
         if (k != oe - 1) continue;
         int64_t kb = S.panel_col[S.panel_ptr[t] + ob], c1 = S.panel_col[S.panel_ptr[t] + k + 1];
         int64_t m = S.sn_m[t];
@@ -681,7 +684,7 @@ std::string analyse(Analysis& A) {
       for (int64_t q = 0; q < nfree; ++q) pub[q] = vbeg[q];
       pub_n = 3 * d;
     }
-    std::string err = finish_system(S, nd.tree, vbeg, pub, pub_n, adj);
+    std::string err = finish_system(S, nd.tree, vbeg, pub, pub_n, adj, A.tune);
     if (!err.empty()) return "SGN: " + err;
     S.grp_ptr.resize(nfree + 1);
     S.grp_node.resize(nfree);
@@ -782,7 +785,7 @@ std::string analyse(Analysis& A) {
     S.elem_stride = A.stride;
     std::vector<int64_t> pub(nfree);
     for (int64_t q = 0; q < nfree; ++q) pub[q] = vbeg[q];
-    std::string err = finish_system(S, nd.tree, vbeg, pub, d, adj);
+    std::string err = finish_system(S, nd.tree, vbeg, pub, d, adj, A.tune);
     if (!err.empty()) return "Kx: " + err;
   }
   return "";

@@ -18,6 +18,22 @@ constexpr int kSolveSeqPanels = 8;  // fronts with at most this many panels are 
 
 enum SystemKind { SYS_SGN = 0, SYS_KX = 1 };
 
+// Blocking choices of the schedule that leave the mathematics unchanged (tuned per problem family):
+// fronts fall in buckets by their order m (below kTuneBucketEdge[0], below kTuneBucketEdge[1], the
+// rest); each bucket delays the trailing update beyond a block of outer_panels panels; fronts with
+// at most seq_panels panels are solved by one block.
+constexpr int kTuneBuckets = 3;
+constexpr int64_t kTuneBucketEdge[kTuneBuckets - 1] = {1024, 4096};
+struct Tuning {
+  int outer_panels[kTuneBuckets] = {kOuterPanels, kOuterPanels, kOuterPanels};
+  int seq_panels = kSolveSeqPanels;
+};
+inline int tune_bucket(int64_t m) {
+  int b = 0;
+  while (b < kTuneBuckets - 1 && m >= kTuneBucketEdge[b]) ++b;
+  return b;
+}
+
 struct Mesh {
   int dim = 0, n_nodes = 0, n_elems = 0;
   std::vector<double> rest;       // [n_nodes*dim]
@@ -120,6 +136,7 @@ struct System {
 
 struct Analysis {
   Mesh mesh;
+  Tuning tune;
   std::vector<int64_t> node_order;  // free nodes in ND order
   System sgn, kx;
   // element buffer layout: component-major, value j of element e at j * n_elems + e

@@ -31,7 +31,7 @@ EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_w
            "sgn_get_symbolic", "sgn_get_values", "sgn_get_stats", "sgn_selftest_mfma", "sgn_last_error",
            "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
            "sgn_solve_minres", "sgn_gnn_num_weights", "sgn_gnn_init", "sgn_gnn_forward", "sgn_gnn_backward",
-           "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss", "sgn_graph_step"]
+           "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss", "sgn_graph_step", "sgn_autotune"]
 
 
 class sgn_problem(C.Structure):
@@ -50,7 +50,8 @@ class sgn_options(C.Structure):
                 ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("solve_rtol", C.c_double),
                 ("eps_x", C.c_double), ("eps_lambda", C.c_double), ("max_newton", C.c_int),
                 ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int),
-                ("profile", C.c_int), ("max_gmres", C.c_int)]
+                ("profile", C.c_int), ("max_gmres", C.c_int), ("outer_panels", C.c_int * 3),
+                ("seq_panels", C.c_int)]
 
 
 class sgn_stats(C.Structure):
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_pc_train_loss": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp, dp]),
         "sgn_adam": (C.c_int, [C.c_int64, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
                                vp]),
+        "sgn_autotune": (C.c_int, [C.POINTER(sgn_problem), C.POINTER(sgn_options), vp, vp, C.c_int, vp,
+                                   C.POINTER(sgn_options), dp, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -164,6 +167,79 @@ def _dev_ptr(t):
     return C.c_void_p(int(t.data_ptr())) if t is not None else None
 
 
+def _problem_struct(prob):
+    """The sgn_problem view of a Problem, with the arrays it points into (kept alive by the caller)."""
+    d = prob.dim
+    keep = dict(
+        rest=np.ascontiguousarray(prob.rest_pos, dtype=np.float64),
+        elems=np.ascontiguousarray(prob.elems, dtype=np.int32),
+        grid=np.ascontiguousarray(prob.node_grid(), dtype=np.int32),
+        fixed=np.ascontiguousarray(prob.fixed, dtype=np.uint8),
+        fext=np.ascontiguousarray(prob.f_ext, dtype=np.float64),
+        tdof=np.ascontiguousarray(prob.target_dof, dtype=np.int32),
+        tval=np.ascontiguousarray(prob.target_val if prob.target_val is not None
+                                  else np.zeros(len(prob.target_dof)), dtype=np.float64),
+        pref=np.ascontiguousarray(prob.p_ref if prob.p_ref is not None else np.zeros(prob.n_p),
+                                  dtype=np.float64),
+        comp=np.ascontiguousarray(getattr(prob, "components", None) if getattr(prob, "components", None)
+                                  is not None else [0, prob.n_nodes], dtype=np.int32),
+    )
+    k = keep
+    P = sgn_problem(dim=d, n_nodes=prob.n_nodes, n_elems=prob.n_elems,
+                    rest_pos=_ptr(k["rest"], C.c_double), elems=_ptr(k["elems"], C.c_int32),
+                    node_grid=_ptr(k["grid"], C.c_int32), fixed=_ptr(k["fixed"], C.c_uint8),
+                    f_ext=_ptr(k["fext"], C.c_double), E0=prob.E0, nu=prob.nu,
+                    param_kind=prob.param_kind, n_targets=len(k["tdof"]),
+                    target_dof=_ptr(k["tdof"], C.c_int32), target_val=_ptr(k["tval"], C.c_double),
+                    target_w=prob.target_w,
+                    length_scale=prob.length_scale if prob.length_scale else 1.0,
+                    reg_mu=prob.reg_mu, p_ref=_ptr(k["pref"], C.c_double),
+                    n_components=len(k["comp"]) - 1, component_ptr=_ptr(k["comp"], C.c_int32))
+    return P, keep
+
+
+def tuning_of(o: sgn_options) -> dict:
+    """The schedule-blocking fields of an options struct."""
+    return {"outer_panels": [int(v) for v in o.outer_panels], "seq_panels": int(o.seq_panels)}
+
+
+def apply_tuning(o: sgn_options, tuning: dict) -> sgn_options:
+    """Sets the schedule-blocking fields of o from a tuning record (as written by autotune)."""
+    for b, v in enumerate(tuning["outer_panels"]):
+        o.outer_panels[b] = int(v)
+    o.seq_panels = int(tuning["seq_panels"])
+    return o
+
+
+def autotune(prob, x, p, options: sgn_options = None, reps: int = 3, stream=None, path: str = None) -> dict:
+    """Runs sgn_autotune for prob at the device state (x, p); returns the tuning record (and writes it
+    as JSON to path if given): the chosen blocking, the candidates' milliseconds per round."""
+    import json
+    lib = load_library()
+    P, keep = _problem_struct(prob)
+    base = options if options is not None else default_options()
+    best = sgn_options()
+    ms = (C.c_double * 16)()
+    n = C.c_int(0)
+    sp = C.c_void_p(int(stream.cuda_stream)) if stream is not None else None
+    st = lib.sgn_autotune(C.byref(P), C.byref(base), _dev_ptr(x), _dev_ptr(p), int(reps), sp, C.byref(best), ms,
+                          C.byref(n))
+    if st != SGN_OK:
+        raise SgnError(st, "autotune: a candidate context failed")
+    rec = dict(tuning_of(best), base=tuning_of(base), candidate_ms=[float(v) for v in ms[:n.value]],
+               reps=int(reps), problem=getattr(prob, "name", ""))
+    if path:
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+    return rec
+
+
+def load_tuning(path: str) -> dict:
+    import json
+    with open(path) as f:
+        return json.load(f)
+
+
 class Context:
     """One libsgn context: host symbolic analysis at construction, a caller-owned
     device workspace (a torch uint8 tensor) once ``allocate()`` is called."""
@@ -173,32 +249,7 @@ class Context:
         self.lib = lib
         self.prob = prob
         self.options = options if options is not None else default_options()
-        d = prob.dim
-        self._keep = dict(
-            rest=np.ascontiguousarray(prob.rest_pos, dtype=np.float64),
-            elems=np.ascontiguousarray(prob.elems, dtype=np.int32),
-            grid=np.ascontiguousarray(prob.node_grid(), dtype=np.int32),
-            fixed=np.ascontiguousarray(prob.fixed, dtype=np.uint8),
-            fext=np.ascontiguousarray(prob.f_ext, dtype=np.float64),
-            tdof=np.ascontiguousarray(prob.target_dof, dtype=np.int32),
-            tval=np.ascontiguousarray(prob.target_val if prob.target_val is not None
-                                      else np.zeros(len(prob.target_dof)), dtype=np.float64),
-            pref=np.ascontiguousarray(prob.p_ref if prob.p_ref is not None else np.zeros(prob.n_p),
-                                      dtype=np.float64),
-            comp=np.ascontiguousarray(getattr(prob, "components", None) if getattr(prob, "components", None)
-                                      is not None else [0, prob.n_nodes], dtype=np.int32),
-        )
-        k = self._keep
-        P = sgn_problem(dim=d, n_nodes=prob.n_nodes, n_elems=prob.n_elems,
-                        rest_pos=_ptr(k["rest"], C.c_double), elems=_ptr(k["elems"], C.c_int32),
-                        node_grid=_ptr(k["grid"], C.c_int32), fixed=_ptr(k["fixed"], C.c_uint8),
-                        f_ext=_ptr(k["fext"], C.c_double), E0=prob.E0, nu=prob.nu,
-                        param_kind=prob.param_kind, n_targets=len(k["tdof"]),
-                        target_dof=_ptr(k["tdof"], C.c_int32), target_val=_ptr(k["tval"], C.c_double),
-                        target_w=prob.target_w,
-                        length_scale=prob.length_scale if prob.length_scale else 1.0,
-                        reg_mu=prob.reg_mu, p_ref=_ptr(k["pref"], C.c_double),
-                        n_components=len(k["comp"]) - 1, component_ptr=_ptr(k["comp"], C.c_int32))
+        P, self._keep = _problem_struct(prob)
         self._stream = stream
         h = C.c_void_p()
         st = lib.sgn_create(C.byref(P), C.byref(self.options), self._stream_ptr(), C.byref(h))

@@ -49,6 +49,35 @@ def test_create_rejects_invalid_problems():
         sgn.Context(bad)
 
 
+def test_create_rejects_invalid_schedule_blocking():
+    _lib()
+    prob = si.config_tiny()
+    for kw in ({"outer_panels": (17, 0, 0)}, {"outer_panels": (0, -1, 0)}, {"seq_panels": 9},
+               {"seq_panels": -2}):
+        o = sgn.default_options()
+        if "outer_panels" in kw:
+            for b, v in enumerate(kw["outer_panels"]):
+                o.outer_panels[b] = v
+        else:
+            o.seq_panels = kw["seq_panels"]
+        with pytest.raises(sgn.SgnError) as e:
+            sgn.Context(prob, o)
+        assert e.value.status == sgn.SGN_E_ARG
+
+
+def test_schedule_blocking_leaves_the_symbolic_structure_unchanged():
+    """The tuned blocking only regroups launches: ordering, pattern and elimination tree are those of
+    the default schedule (and the oracle's)."""
+    _lib()
+    prob = si.config_cantilever_small()
+    ref = sgn.Context(prob).symbolic(sgn.SGN_SYS_SGN)
+    for tun in ({"outer_panels": [1, 2, 8], "seq_panels": -1}, {"outer_panels": [8, 1, 2], "seq_panels": 2}):
+        ctx = sgn.Context(prob, sgn.apply_tuning(sgn.default_options(), tun))
+        for a, b in zip(ctx.symbolic(sgn.SGN_SYS_SGN), ref):
+            assert np.array_equal(a, b)
+        assert sgn.tuning_of(ctx.options) == tun
+
+
 def test_device_calls_before_workspace_are_state_errors():
     _lib()
     ctx = sgn.Context(si.config_tiny())
