@@ -136,13 +136,18 @@ __global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, int64_t ncol
   }
 }
 
-// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, 256 threads.
+// wavefronts of the panel factorisation: each takes every kDiagWaves-th column of a step's update
+constexpr int kDiagWaves = 8;
+
+// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, 64 * kDiagWaves threads.
 // Bunch-Kaufman 1x1/2x2 pivoting restricted to the rows of one node group.  Every
 // wavefront reads the pivot column into registers and takes the same pivot decision
 // (argmax by a shuffle butterfly over |a| bits with the row index in the low bits, so
 // near-ties go to the lower row); the multipliers of the update come from that register
-// copy by lane broadcasts, so the step needs one barrier (two more for an interchange).
-// The symmetric updates use lane = row, wavefront = every fourth column.
+// copy by lane broadcasts.  A step has two barriers (two more for an interchange): one after every
+// wavefront has read the pivot columns, before wavefront 0 overwrites them with the multipliers,
+// and one at its end.
+// The symmetric updates use lane = row, wavefront = every kDiagWaves-th column.
 // Alongside L11 the block accumulates X = L11^-1 (unit lower) from the
 // elementary column inverses, X <- L_k^-1 X, stored transposed in the upper
 // part of the finished rows (X[i][j] at A[j][i]); symmetric interchanges swap
@@ -181,10 +186,11 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
+__global__ void __launch_bounds__(64 * kDiagWaves) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
                                                     T* __restrict__ front) {
   __shared__ double A[64][65];
   __shared__ int pos[64];
+  constexpr int S = kDiagWaves;  // column stride of a wavefront's share of an update
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform_i(tid >> 6);
   const int sn = (int)tasks[blockIdx.x * 3];
   const int c0 = (int)tasks[blockIdx.x * 3 + 1], c1 = (int)tasks[blockIdx.x * 3 + 2];
@@ -194,18 +200,19 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
   T* F = front + f.sn_front_off[sn];
   const double tol = f.piv_tol;
   {
-    // the panel's lower triangle: all 16 loads of a thread issued unconditionally (clamped to the
+    // the panel's lower triangle: all loads of a thread issued unconditionally (clamped to the
     // panel, masked when staged) before the first LDS store
     const int lc = lane < w ? lane : 0;
-    T lv[16];
+    constexpr int NL = 64 / kDiagWaves;
+    T lv[NL];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int j = wave + 4 * t, jc = j < w ? j : 0;
+    for (int t = 0; t < NL; ++t) {
+      const int j = wave + kDiagWaves * t, jc = j < w ? j : 0;
       lv[t] = F[(c0 + lc) + (int64_t)(c0 + jc) * m];
     }
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int j = wave + 4 * t;
+    for (int t = 0; t < NL; ++t) {
+      const int j = wave + kDiagWaves * t;
       if (j < w && lane >= j && lane < w) {
         const double v = (double)lv[t];
         A[lane][j] = v;
@@ -276,6 +283,10 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
       __syncthreads();
       v = A[lane][k];
     }
+    // every wavefront holds the pivot columns it needs (k, and k + 1 for a 2 x 2 pivot) before any
+    // wavefront overwrites them with the step's multipliers
+    const double w2 = kind == 2 ? A[lane][k + 1] : 0.0;
+    __syncthreads();
     if (kind == 1) {
       double d = lane_bcast(v, k);
       if (pert) {
@@ -290,23 +301,23 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
         const double li = v * id;
         // Schur complement and X <- L_k^-1 X; the multipliers A[j][k] are lane j's copy of column k
         int j = k + 1 + wave;
-        for (; j + 12 < w; j += 16) {
-          const double a0 = A[lane][j], a1 = A[lane][j + 4], a2 = A[lane][j + 8], a3 = A[lane][j + 12];
+        for (; j + 3 * S < w; j += 4 * S) {
+          const double a0 = A[lane][j], a1 = A[lane][j + S], a2 = A[lane][j + 2 * S], a3 = A[lane][j + 3 * S];
           A[lane][j] = a0 - li * lane_bcast(v, j);
-          A[lane][j + 4] = a1 - li * lane_bcast(v, j + 4);
-          A[lane][j + 8] = a2 - li * lane_bcast(v, j + 8);
-          A[lane][j + 12] = a3 - li * lane_bcast(v, j + 12);
+          A[lane][j + S] = a1 - li * lane_bcast(v, j + S);
+          A[lane][j + 2 * S] = a2 - li * lane_bcast(v, j + 2 * S);
+          A[lane][j + 3 * S] = a3 - li * lane_bcast(v, j + 3 * S);
         }
-        for (; j < w; j += 4) A[lane][j] -= li * lane_bcast(v, j);
+        for (; j < w; j += S) A[lane][j] -= li * lane_bcast(v, j);
         j = wave;
-        for (; j + 12 < k; j += 16) {
-          const double a0 = A[j][lane], a1 = A[j + 4][lane], a2 = A[j + 8][lane], a3 = A[j + 12][lane];
+        for (; j + 3 * S < k; j += 4 * S) {
+          const double a0 = A[j][lane], a1 = A[j + S][lane], a2 = A[j + 2 * S][lane], a3 = A[j + 3 * S][lane];
           A[j][lane] = a0 - li * lane_bcast(v, j);
-          A[j + 4][lane] = a1 - li * lane_bcast(v, j + 4);
-          A[j + 8][lane] = a2 - li * lane_bcast(v, j + 8);
-          A[j + 12][lane] = a3 - li * lane_bcast(v, j + 12);
+          A[j + S][lane] = a1 - li * lane_bcast(v, j + S);
+          A[j + 2 * S][lane] = a2 - li * lane_bcast(v, j + 2 * S);
+          A[j + 3 * S][lane] = a3 - li * lane_bcast(v, j + 3 * S);
         }
-        for (; j < k; j += 4) A[j][lane] -= li * lane_bcast(v, j);
+        for (; j < k; j += S) A[j][lane] -= li * lane_bcast(v, j);
         if (wave == 0) {  // column k and row k are read by nobody in this step
           A[lane][k] = li;
           A[k][lane] = -li;
@@ -319,32 +330,31 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
       }
       k += 1;
     } else {
-      const double w2 = A[lane][k + 1];
       const double a = lane_bcast(v, k), b = lane_bcast(v, k + 1), c = lane_bcast(w2, k + 1);
       const double det = a * c - b * b;
       const double i00 = c / det, i01 = -b / det, i11 = a / det;
       if (lane > k + 1 && lane < w) {
         const double l0 = v * i00 + w2 * i01, l1 = v * i01 + w2 * i11;
         int j = k + 2 + wave;
-        for (; j + 12 < w; j += 16) {
+        for (; j + 3 * S < w; j += 4 * S) {
           double a4[4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) a4[t] = A[lane][j + 4 * t];
+          for (int t = 0; t < 4; ++t) a4[t] = A[lane][j + S * t];
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            A[lane][j + 4 * t] = a4[t] - (l0 * lane_bcast(v, j + 4 * t) + l1 * lane_bcast(w2, j + 4 * t));
+            A[lane][j + S * t] = a4[t] - (l0 * lane_bcast(v, j + S * t) + l1 * lane_bcast(w2, j + S * t));
         }
-        for (; j < w; j += 4) A[lane][j] -= l0 * lane_bcast(v, j) + l1 * lane_bcast(w2, j);
+        for (; j < w; j += S) A[lane][j] -= l0 * lane_bcast(v, j) + l1 * lane_bcast(w2, j);
         j = wave;
-        for (; j + 12 < k; j += 16) {
+        for (; j + 3 * S < k; j += 4 * S) {
           double a4[4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) a4[t] = A[j + 4 * t][lane];
+          for (int t = 0; t < 4; ++t) a4[t] = A[j + S * t][lane];
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            A[j + 4 * t][lane] = a4[t] - (l0 * lane_bcast(v, j + 4 * t) + l1 * lane_bcast(w2, j + 4 * t));
+            A[j + S * t][lane] = a4[t] - (l0 * lane_bcast(v, j + S * t) + l1 * lane_bcast(w2, j + S * t));
         }
-        for (; j < k; j += 4) A[j][lane] -= l0 * lane_bcast(v, j) + l1 * lane_bcast(w2, j);
+        for (; j < k; j += S) A[j][lane] -= l0 * lane_bcast(v, j) + l1 * lane_bcast(w2, j);
         if (wave == 0) {
           A[lane][k] = l0;
           A[lane][k + 1] = l1;
@@ -371,7 +381,7 @@ __global__ void __launch_bounds__(256) k_panel_diag(const int64_t* __restrict__ 
   }
   // A holds L below the diagonal and X[j][i] at (i, j) above it: the transposed
   // placement the rows-below solve reads
-  for (int j = wave; j < w; j += 4)
+  for (int j = wave; j < w; j += kDiagWaves)
     if (lane < w) F[(c0 + lane) + (int64_t)(c0 + j) * m] = (T)(lane == j ? 1.0 : A[lane][j]);
   if (tid < w) {
     f.dpiv[gbase + tid] = dv;
@@ -745,7 +755,7 @@ void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, co
 
 template <typename T>
 void launch_panel_diag(int64_t ntasks, const int64_t* tasks, const FrontArgs& f, T* front, hipStream_t s) {
-  if (ntasks > 0) k_panel_diag<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, f, front);
+  if (ntasks > 0) k_panel_diag<T><<<(unsigned)ntasks, 64 * kDiagWaves, 0, s>>>(tasks, f, front);
 }
 
 template <typename T>
