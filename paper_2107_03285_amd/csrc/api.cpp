@@ -1017,9 +1017,11 @@ sgn_status potential(sgn_ctx c, const double* x, const double* p, double* pi, do
     return SGN_OK;
   }
   const Analysis& A = c->A;
-  const double* energy = c->d_ebuf + (int64_t)A.off_energy * A.mesh.n_elems;  // component-major buffer
-  dev_dot(c, A.mesh.n_elems, energy, nullptr, 4, 1, 0);
-  dev_dot(c, A.mesh.n_elems, energy, nullptr, 5, 1, 1);
+  // element energies: value off_energy of every element, dim apart in the grouped buffer
+  const int g = A.mesh.dim;
+  const double* energy = c->d_ebuf + ebuf_index(A.off_energy, 0, A.mesh.n_elems, g);
+  dev_dot(c, A.mesh.n_elems, energy, nullptr, 4, g, 0);
+  dev_dot(c, A.mesh.n_elems, energy, nullptr, 5, g, 1);
   dev_dot(c, A.mesh.n_x, c->d_fext, x, 6);
   int ns = 3;
   if (A.mesh.param_kind == 2) {

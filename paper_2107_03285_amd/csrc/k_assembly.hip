@@ -93,13 +93,14 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
       F[i][j] = acc;
     }
   const double J = det<D>(F);
-  // component-major element buffer: value j of element e at ebuf[j * ne + e], so each store of a
-  // wavefront writes consecutive addresses
-  double* out = a.ebuf + e;
-  const int64_t cs = a.ne;
+  // element buffer in coordinate groups: value j of element e at ((j / D) ne + e) D + j % D, so a
+  // wavefront's stores of one group cover one contiguous span, and the D values the assembly gathers
+  // for neighbouring CSR slots share a cache line
+  const int64_t ne = a.ne;
+  auto out = [&](int64_t j) -> double& { return a.ebuf[((j / D) * ne + e) * D + j % D]; };
   if (!(J > 0.0)) {
     atomicAdd(a.inverted, 1);
-    out[(int64_t)(a.off_energy) * cs] = __builtin_inf();
+    out(a.off_energy) = __builtin_inf();
     return;
   }
   double Fi[D][D];
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
   double trC = 0.0;
   for (int i = 0; i < D; ++i)
     for (int j = 0; j < D; ++j) trC += F[i][j] * F[i][j];
-  out[(int64_t)(a.off_energy) * cs] = V0 * (0.5 * mu * (trC - D) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+  out(a.off_energy) = V0 * (0.5 * mu * (trC - D) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
   if (a.mode == 0) return;
   // F^-T[i][j] = Fi[j][i]
   double P[D][D];
@@ -123,10 +124,10 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
         double acc = 0.0;
         for (int j = 0; j < D; ++j) acc += P[c][j] * Dmi[k][j];
         acc *= V0;
-        out[(int64_t)(a.off_grad + (k + 1) * D + c) * cs] = acc;
+        out(a.off_grad + (k + 1) * D + c) = acc;
         g0[c] -= acc;
       }
-    for (int c = 0; c < D; ++c) out[(int64_t)(a.off_grad + c) * cs] = g0[c];
+    for (int c = 0; c < D; ++c) out(a.off_grad + c) = g0[c];
   }
   if (a.mode == 1) return;
   const double cA = mu - lam * lnJ;
@@ -165,10 +166,10 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
           double acc = 0.0;
           for (int j = 0; j < D; ++j) acc += dP[c][j] * Dmi[k][j];
           acc *= V0;
-          out[(int64_t)(((k + 1) * D + c) * ND + col) * cs] = acc;
+          out(((k + 1) * D + c) * ND + col) = acc;
           h0[c] -= acc;
         }
-      for (int c = 0; c < D; ++c) out[(int64_t)(c * ND + col) * cs] = h0[c];
+      for (int c = 0; c < D; ++c) out(c * ND + col) = h0[c];
     }
   }
   if (a.param_kind == 1) {
@@ -221,10 +222,10 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
             double acc = 0.0;
             for (int j = 0; j < D; ++j)
               acc += dV0 * P[c][j] * Dmi[k][j] + V0 * dP[c][j] * Dmi[k][j] - V0 * P[c][j] * Dmi[k][cb] * uD[j];
-            out[(int64_t)(a.off_kp + ((k + 1) * D + c) * ND + col) * cs] = acc;
+            out(a.off_kp + ((k + 1) * D + c) * ND + col) = acc;
             h0[c] -= acc;
           }
-        for (int c = 0; c < D; ++c) out[(int64_t)(a.off_kp + c * ND + col) * cs] = h0[c];
+        for (int c = 0; c < D; ++c) out(a.off_kp + c * ND + col) = h0[c];
       }
     }
   }

@@ -151,7 +151,23 @@ __global__ void __launch_bounds__(256) k_fwd_gather(const int32_t* __restrict__ 
     const int64_t sC = f.sn_begin[C + 1] - f.sn_begin[C], uC = f.sn_m[C] - sC;
     const double* cv = a.tp + a.sn_vec_off[C] + sC;
     const int32_t* rel = f.relmap + f.relmap_off[C];
-    for (int64_t r = tid; r < uC; r += 256) tv[rel[r]] += cv[r];
+    // eight rows per thread in flight, every load before the first store: the map is injective, so a
+    // child's rows land on distinct entries
+    for (int64_t r0 = 0; r0 < uC; r0 += 8 * 256) {
+      int32_t d[8];
+      double c[8], t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t r = r0 + tid + 256 * q, rc = r < uC ? r : 0;
+        d[q] = rel[rc];
+        c[q] = cv[rc];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = tv[d[q]];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (r0 + tid + 256 * q < uC) tv[d[q]] = t[q] + c[q];
+    }
     __syncthreads();
   }
 }

@@ -530,7 +530,7 @@ std::string analyse(Analysis& A) {
   A.off_grad = A.nd * A.nd;
   A.off_kp = A.off_grad + A.nd;
   A.off_energy = A.off_kp + (m.param_kind == 1 ? A.nd * A.nd : 0);
-  A.stride = A.off_energy + 1;
+  A.stride = (A.off_energy + 1 + d - 1) / d * d;  // padded to whole coordinate groups
 
   NdResult nd = nested_dissection(m);
   A.node_order = nd.order;
@@ -645,18 +645,18 @@ std::string analyse(Analysis& A) {
               int64_t B_ = m.fdof[vb] + cb;
               int64_t sl = find_slot(S, S.iperm[lam0 + A_], S.iperm[B_]);
               if (sl < 0) return "missing Kx slot";
-              contrib.emplace_back(sl, (int32_t)((int64_t)(A.off_hess + la * A.nd + lb) * m.n_elems + e));
+              contrib.emplace_back(sl, (int32_t)ebuf_index(A.off_hess + la * A.nd + lb, e, m.n_elems, d));
               if (m.param_kind == 1) {
                 int64_t s2 = find_slot(S, S.iperm[lam0 + A_], S.iperm[nx + B_]);
                 if (s2 < 0) return "missing Kp slot";
-                contrib.emplace_back(s2, (int32_t)((int64_t)(A.off_kp + la * A.nd + lb) * m.n_elems + e));
+                contrib.emplace_back(s2, (int32_t)ebuf_index(A.off_kp + la * A.nd + lb, e, m.n_elems, d));
               }
             }
           }
           if (m.param_kind == 0) {
             int64_t sl = find_slot(S, S.iperm[lam0 + A_], S.iperm[nx + e]);
             if (sl < 0) return "missing Kp slot";
-            contrib.emplace_back(sl, (int32_t)((int64_t)(A.off_grad + la) * m.n_elems + e));
+            contrib.emplace_back(sl, (int32_t)ebuf_index(A.off_grad + la, e, m.n_elems, d));
           }
         }
       }
@@ -749,7 +749,7 @@ std::string analyse(Analysis& A) {
               if (r < c) continue;  // each lower entry takes one of the two symmetric products
               int64_t sl = find_slot(S, r, c);
               if (sl < 0) return "missing Kx slot";
-              contrib.emplace_back(sl, (int32_t)((int64_t)(A.off_hess + (a * d + ca) * A.nd + b * d + cb) * m.n_elems + e));
+              contrib.emplace_back(sl, (int32_t)ebuf_index(A.off_hess + (a * d + ca) * A.nd + b * d + cb, e, m.n_elems, d));
             }
         }
       }
@@ -778,7 +778,7 @@ std::string analyse(Analysis& A) {
           int va = m.elems[(size_t)e * nv + a];
           if (!m.fixed[va])
             for (int c = 0; c < d; ++c)
-              S.vec_src[fill[m.fdof[va] + c]++] = (int32_t)((int64_t)(A.off_grad + a * d + c) * m.n_elems + e);
+              S.vec_src[fill[m.fdof[va] + c]++] = (int32_t)ebuf_index(A.off_grad + a * d + c, e, m.n_elems, d);
         }
     }
     S.diag_kind.assign(N, 3);

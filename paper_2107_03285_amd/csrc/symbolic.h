@@ -134,12 +134,21 @@ struct System {
   int max_front = 0;
 };
 
+// Position of value j of element e in the element buffer: values grouped by g (the spatial
+// dimension), groups major, elements next, the g values of a group innermost.  The element kernel's
+// stores of one group stay coalesced across elements, and the assembly gather, whose neighbouring
+// CSR slots take the x, y (, z) values of one element entry, reads them from one cache line.
+inline int64_t ebuf_index(int64_t j, int64_t e, int64_t n_elems, int g) {
+  return ((j / g) * n_elems + e) * g + j % g;
+}
+
 struct Analysis {
   Mesh mesh;
   Tuning tune;
   std::vector<int64_t> node_order;  // free nodes in ND order
   System sgn, kx;
-  // element buffer layout: component-major, value j of element e at j * n_elems + e
+  // element buffer layout: values in groups of dim (the coordinates of one node), group-major:
+  // value j of element e at ebuf_index(j, e, n_elems, dim); stride is padded to a multiple of dim
   int nd = 0;              // dofs per element (d+1)*d
   int off_hess = 0, off_grad = 0, off_kp = 0, off_energy = 0, stride = 0;
 };
