@@ -175,6 +175,8 @@ struct sgn_ctx_s {
   bool gnn_fwd_done = false;
   bool capturing = false;             // enqueueing into a graph: no host syncs
   hipStream_t gstream = nullptr;      // stream of the captured step graph
+  hipStream_t side = nullptr;         // the factorisation's second stream (updates beyond the next block)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   const void* graph_key[4] = {};      // (x, p, rhs, sol) the graph was captured for
@@ -204,6 +206,9 @@ struct sgn_ctx_s {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (gstream) (void)hipStreamDestroy(gstream);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (ev_a) (void)hipEventDestroy(ev_a);
     if (ev_b) (void)hipEventDestroy(ev_b);
@@ -235,6 +240,16 @@ sgn_status fail(sgn_ctx c, sgn_status s, const std::string& msg) {
 template <typename T>
 size_t bytes_of(const std::vector<T>& v) {
   return v.size() * sizeof(T);
+}
+
+// The factorisation's second stream (default priority, ordered against the context's stream by
+// events only) and its fork / join events.
+hipError_t ensure_side(sgn_ctx c) {
+  hipError_t e = hipSuccess;
+  if (!c->side) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess && !c->ev_fork) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess && !c->ev_join) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  return e;
 }
 
 hipError_t ensure_events(sgn_ctx c, size_t n) {
@@ -510,6 +525,7 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   DevSys& D = c->sys[si];
   hipStream_t st = c->stream;
   T* front = reinterpret_cast<T*>(D.front);
+  HIPCHK(ensure_side(c));
   launch_row_scaling(S.N, D.frowptr, D.fslot, D.vals, D.scale, st);
   FrontArgs f;
   f.sn_begin = D.sn_begin;
@@ -536,18 +552,20 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   if (prof) {
     size_t need = 0;
     for (const LevelPlan& P : S.levels)
-      for (const PanelStep& ps : P.steps) need += 2 * ((ps.upd_tiles > 0) + (ps.outer_tiles > 0));
+      for (const PanelStep& ps : P.steps)
+        need += 2 * ((ps.upd_tiles > 0) + (ps.outer_tiles > 0) + (ps.far_tiles > 0));
     HIPCHK(ensure_events(c, need));
   }
-  auto timed_update = [&](int64_t ntask, int64_t ntiles, const int64_t* tasks, double flops) -> hipError_t {
+  auto timed_update = [&](int64_t ntask, int64_t ntiles, const int64_t* tasks, double flops,
+                          hipStream_t ls) -> hipError_t {
     if (ntask <= 0 || ntiles <= 0) return hipSuccess;
-    if (prof) {
-      hipError_t e = hipEventRecord(c->ev_pool[nev], st);
+    if (prof) {  // events on the stream the launch goes to
+      hipError_t e = hipEventRecord(c->ev_pool[nev], ls);
       if (e != hipSuccess) return e;
     }
-    launch_update<T>(ntask, ntiles, tasks, f, front, st);
+    launch_update<T>(ntask, ntiles, tasks, f, front, ls);
     if (prof) {
-      hipError_t e = hipEventRecord(c->ev_pool[nev + 1], st);
+      hipError_t e = hipEventRecord(c->ev_pool[nev + 1], ls);
       if (e != hipSuccess) return e;
       nev += 2;
       upd_flops += flops;
@@ -561,14 +579,32 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
       launch_extend_add<T>(nt, P.ea_work[r], D.ea_tasks + P.ea_begin[r] * 3, D.ea_col_task + P.ea_col_begin[r], f,
                            front, st);
     }
+    // Look-ahead: the delayed update of a block's columns beyond the next block runs on the second
+    // stream, beside the next block's panels (which touch only the next block's columns and its W
+    // rows).  The main stream waits for it before the next delayed update of the next block's
+    // columns (both write the columns after it) and before the next level.
+    bool side_busy = false;
     for (const PanelStep& ps : P.steps) {
       const int64_t nt = ps.task_end - ps.task_begin;
       launch_panel_diag<T>(nt, D.panel_tasks + ps.task_begin * 3, f, front, st);
       launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
-      HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops));
+      HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops, st));
+      if (ps.outer_tiles > 0 && side_busy) {
+        HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
+        side_busy = false;
+      }
       HIPCHK(timed_update(ps.outer_end - ps.outer_begin, ps.outer_tiles, D.upd_tasks + ps.outer_begin * 6,
-                          ps.outer_flops));
+                          ps.outer_flops, st));
+      if (ps.far_tiles > 0) {  // after everything the main stream has so far; after earlier far updates
+        HIPCHK(hipEventRecord(c->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        HIPCHK(timed_update(ps.far_end - ps.far_begin, ps.far_tiles, D.upd_tasks + ps.far_begin * 6,
+                            ps.far_flops, c->side));
+        HIPCHK(hipEventRecord(c->ev_join, c->side));
+        side_busy = true;
+      }
     }
+    if (side_busy) HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
   }
   HIPCHK(hipGetLastError());
   if (prof) {
@@ -2127,7 +2163,8 @@ sgn_status sgn_graph_step(sgn_ctx c, const double* d_x, const double* d_p, doubl
     if (c->opt.profile) {  // create the update events before capture; their records become graph nodes
       size_t need = 0;
       for (const LevelPlan& P : c->A.sgn.levels)
-        for (const PanelStep& ps : P.steps) need += 2 * ((ps.upd_tiles > 0) + (ps.outer_tiles > 0));
+        for (const PanelStep& ps : P.steps)
+        need += 2 * ((ps.upd_tiles > 0) + (ps.outer_tiles > 0) + (ps.far_tiles > 0));
       hipError_t e0 = ensure_events(c, need);
       if (e0 != hipSuccess) {
         c->capturing = false;

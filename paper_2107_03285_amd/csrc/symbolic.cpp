@@ -497,15 +497,39 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         if (k != oe - 1) continue;
         int64_t kb = S.panel_col[S.panel_ptr[t] + ob], c1 = S.panel_col[S.panel_ptr[t] + k + 1];
         int64_t m = S.sn_m[t];
-        if (c1 < m) {
-          S.upd_tasks.insert(S.upd_tasks.end(), {t, kb, c1, c1, m, tiles});
-          tiles += update_tiles(m, c1, m);
-          fl += update_flops(m, c1, m, c1 - kb);
+        const int64_t nb = S.panel_col[S.panel_ptr[t] + std::min(np, oe + span)];  // end of the next block
+        if (c1 < nb) {  // rows c1.. of the next block's columns
+          S.upd_tasks.insert(S.upd_tasks.end(), {t, kb, c1, c1, nb, tiles});
+          tiles += update_tiles(m, c1, nb);
+          fl += update_flops(m, c1, nb, c1 - kb);
         }
       }
       ps.outer_end = (int64_t)S.upd_tasks.size() / 6;
       ps.outer_tiles = tiles;
       ps.outer_flops = fl;
+      ps.far_begin = ps.outer_end;
+      tiles = 0;
+      fl = 0.0;
+      for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
+        int t = S.level_sn[q];
+        int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
+        if (k >= np) continue;
+        const int span = tune.outer_panels[tune_bucket(S.sn_m[t])];
+        int ob = (k / span) * span;
+        int oe = std::min(np, ob + span);
+        if (k != oe - 1) continue;
+        int64_t kb = S.panel_col[S.panel_ptr[t] + ob], c1 = S.panel_col[S.panel_ptr[t] + k + 1];
+        int64_t m = S.sn_m[t];
+        const int64_t nb = S.panel_col[S.panel_ptr[t] + std::min(np, oe + span)];
+        if (nb < m) {  // rows nb.. of the columns beyond the next block
+          S.upd_tasks.insert(S.upd_tasks.end(), {t, kb, c1, nb, m, tiles});
+          tiles += update_tiles(m, nb, m);
+          fl += update_flops(m, nb, m, c1 - kb);
+        }
+      }
+      ps.far_end = (int64_t)S.upd_tasks.size() / 6;
+      ps.far_tiles = tiles;
+      ps.far_flops = fl;
       P.steps.push_back(ps);
     }
   }

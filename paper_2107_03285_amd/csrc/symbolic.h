@@ -53,10 +53,13 @@ struct Mesh {
 struct PanelStep {
   int64_t task_begin, task_end;    // range in the panel task table
   int64_t upd_begin, upd_end;      // range in the update task table (inner, k = one panel)
-  int64_t outer_begin, outer_end;  // range in the update task table (outer, k = block)
-  int64_t upd_tiles, outer_tiles;  // tiles of each update launch
+  int64_t outer_begin, outer_end;  // range in the update task table (outer, k = block): the next
+                                   // block's columns, which its panels need next
+  int64_t far_begin, far_end;      // range in the update task table (outer, k = block): the columns
+                                   // beyond the next block, free to run beside its panels
+  int64_t upd_tiles, outer_tiles, far_tiles;  // tiles of each update launch
   int64_t trsm_rows;               // max rows below the panel over the step's tasks
-  double upd_flops, outer_flops;   // algorithmic flops of the two update launches
+  double upd_flops, outer_flops, far_flops;   // algorithmic flops of the update launches
 };
 
 struct LevelPlan {
