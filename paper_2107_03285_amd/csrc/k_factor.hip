@@ -163,26 +163,26 @@ __device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v
 // Maximum over the wavefront: data-parallel-primitive moves within rows of 16 lanes (swap adjacent
 // lanes, adjacent pairs, mirrored half rows, mirrored rows), then the four row maxima by lane reads.
 template <int CTRL>
-__device__ inline unsigned long long dpp_u64(unsigned long long x) {
-  const unsigned int lo = (unsigned int)__builtin_amdgcn_update_dpp(0, (int)(unsigned int)x, CTRL, 0xF, 0xF, false);
-  const unsigned int hi =
-      (unsigned int)__builtin_amdgcn_update_dpp(0, (int)(unsigned int)(x >> 32), CTRL, 0xF, 0xF, false);
-  return ((unsigned long long)hi << 32) | lo;
+__device__ inline unsigned int dpp_u32(unsigned int x) {
+  return (unsigned int)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
 }
-__device__ inline unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+__device__ inline unsigned int wave_max_u32(unsigned int x) {
+  x = max(x, dpp_u32<0xB1>(x));   // quad_perm [1, 0, 3, 2]
+  x = max(x, dpp_u32<0x4E>(x));   // quad_perm [2, 3, 0, 1]
+  x = max(x, dpp_u32<0x141>(x));  // row_half_mirror
+  x = max(x, dpp_u32<0x140>(x));  // row_mirror
+  unsigned int r = (unsigned int)__builtin_amdgcn_readlane((int)x, 0);
+  r = max(r, (unsigned int)__builtin_amdgcn_readlane((int)x, 16));
+  r = max(r, (unsigned int)__builtin_amdgcn_readlane((int)x, 32));
+  return max(r, (unsigned int)__builtin_amdgcn_readlane((int)x, 48));
+}
+// 64-bit maximum as two 32-bit ones: the largest high word, then the largest low word among the
+// lanes that hold it (the same key as a 64-bit comparison)
 __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
-  x = umax64(x, dpp_u64<0xB1>(x));   // quad_perm [1, 0, 3, 2]
-  x = umax64(x, dpp_u64<0x4E>(x));   // quad_perm [2, 3, 0, 1]
-  x = umax64(x, dpp_u64<0x141>(x));  // row_half_mirror
-  x = umax64(x, dpp_u64<0x140>(x));  // row_mirror
-  unsigned long long r = 0;
-#pragma unroll
-  for (int row = 0; row < 4; ++row) {
-    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(x >> 32), 16 * row);
-    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)x, 16 * row);
-    r = umax64(r, ((unsigned long long)hi << 32) | lo);
-  }
-  return r;
+  const unsigned int hi = (unsigned int)(x >> 32);
+  const unsigned int mh = wave_max_u32(hi);
+  const unsigned int ml = wave_max_u32(hi == mh ? (unsigned int)x : 0u);
+  return ((unsigned long long)mh << 32) | ml;
 }
 
 template <typename T>
