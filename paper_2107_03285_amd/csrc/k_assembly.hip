@@ -392,30 +392,64 @@ __global__ void k_fill_bytes(int64_t n16, uint4* out) {
     out[k] = z;
 }
 
-// one wave (64 lanes) per row: lanes stride the row, then a fixed butterfly
+// 16 lanes per row (four rows per wavefront): lane l sums the row's entries l, l + 16, l + 32, ... in
+// ascending order, four loads in flight per pass (indices clamped to the row's first entry, products
+// masked), then a fixed butterfly over the 16 lanes
+constexpr int kRowLanes = 16;
+
 __global__ void __launch_bounds__(256) k_spmv(int64_t N, const int64_t* __restrict__ frp,
                                               const int32_t* __restrict__ fcol, const int32_t* __restrict__ fslot,
                                               const double* __restrict__ vals, const double* __restrict__ x,
                                               const double* __restrict__ b, double* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= N) return;
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / kRowLanes) + (threadIdx.x / kRowLanes);
+  if (row >= N) return;  // whole 16-lane groups leave together
+  const int64_t t0 = frp[row], t1 = frp[row + 1];
   double acc = 0.0;
-  for (int64_t t = frp[row] + lane; t < frp[row + 1]; t += 64) acc += vals[fslot[t]] * x[fcol[t]];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[row] = b ? b[row] - acc : acc;
+  for (int64_t t = t0 + sub; t < t1; t += 4 * kRowLanes) {
+    int32_t sl[4], cl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t tt = t + q * kRowLanes, tc = tt < t1 ? tt : t0;
+      sl[q] = fslot[tc];
+      cl[q] = fcol[tc];
+    }
+    double pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pv[q] = vals[sl[q]] * x[cl[q]];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (t + q * kRowLanes < t1) acc += pv[q];
+  }
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kRowLanes);
+  if (sub == 0) y[row] = b ? b[row] - acc : acc;
 }
 
+// max |K_ij| over row i, 16 lanes per row as in the SpMV (max is order-independent)
 __global__ void __launch_bounds__(256) k_row_scaling(int64_t N, const int64_t* __restrict__ frp,
                                                      const int32_t* __restrict__ fslot,
                                                      const double* __restrict__ vals, double* __restrict__ scale) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / kRowLanes) + (threadIdx.x / kRowLanes);
   if (row >= N) return;
+  const int64_t t0 = frp[row], t1 = frp[row + 1];
   double m = 0.0;
-  for (int64_t t = frp[row] + lane; t < frp[row + 1]; t += 64) m = fmax(m, fabs(vals[fslot[t]]));
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-  if (lane == 0) scale[row] = m > 0.0 ? 1.0 / sqrt(m) : 1.0;
+  for (int64_t t = t0 + sub; t < t1; t += 4 * kRowLanes) {
+    int32_t sl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t tt = t + q * kRowLanes;
+      sl[q] = fslot[tt < t1 ? tt : t0];
+    }
+    double av[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) av[q] = fabs(vals[sl[q]]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (t + q * kRowLanes < t1) m = fmax(m, av[q]);
+  }
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, kRowLanes));
+  if (sub == 0) scale[row] = m > 0.0 ? 1.0 / sqrt(m) : 1.0;
 }
 
 __global__ void k_objective_fx(int64_t nt, const int32_t* tdof, const double* tval, const double* x, double c,
@@ -518,17 +552,17 @@ void launch_fill_bytes(int64_t nbytes, void* out, hipStream_t s) {
 
 void launch_spmv(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot, const double* vals,
                  const double* x, double* y, hipStream_t s) {
-  if (N > 0) k_spmv<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, nullptr, y);
+  if (N > 0) k_spmv<<<(unsigned)((N + 15) / 16), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, nullptr, y);
 }
 
 void launch_residual(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
                      const double* vals, const double* x, const double* b, double* out, hipStream_t s) {
-  if (N > 0) k_spmv<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, b, out);
+  if (N > 0) k_spmv<<<(unsigned)((N + 15) / 16), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, b, out);
 }
 
 void launch_row_scaling(int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals, double* scale,
                         hipStream_t s) {
-  if (N > 0) k_row_scaling<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(N, frowptr, fslot, vals, scale);
+  if (N > 0) k_row_scaling<<<(unsigned)((N + 15) / 16), 256, 0, s>>>(N, frowptr, fslot, vals, scale);
 }
 
 void launch_objective_fx(int64_t nt, const int32_t* tdof, const double* tval, const double* x, double w_over_ell2,
