@@ -231,13 +231,28 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
   }
 }
 
+// sum of ebuf[src[q]] over q in [q0, q1), ascending; four sources in flight at a time (indices clamped to
+// the first source, values past the end masked: adding +0.0 to a sum that starts at +0.0 changes nothing)
+__device__ inline double sum_sources(int64_t q0, int64_t q1, const int32_t* __restrict__ src,
+                                     const double* __restrict__ ebuf) {
+  double acc = 0.0;
+  for (int64_t q = q0; q < q1; q += 4) {
+    int32_t sq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sq[u] = src[q + u < q1 ? q + u : q0];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = ebuf[sq[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += q + u < q1 ? v[u] : 0.0;
+  }
+  return acc;
+}
+
 __global__ void k_gather_slots(int64_t nnz, const int64_t* __restrict__ ptr, const int32_t* __restrict__ src,
                                const double* __restrict__ ebuf, double* __restrict__ vals) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int64_t q = ptr[t]; q < ptr[t + 1]; ++q) acc += ebuf[src[q]];
-    vals[t] = acc;
-  }
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * blockDim.x)
+    vals[t] = sum_sources(ptr[t], ptr[t + 1], src, ebuf);
 }
 
 __global__ void k_diag_add(int64_t N, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ kind,
@@ -262,8 +277,7 @@ __global__ void k_gather_vec(int64_t n, const int64_t* __restrict__ ptr, const i
                              const double* __restrict__ ebuf, const double* __restrict__ fext,
                              const double* __restrict__ pforce, double* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) acc += ebuf[src[q]];
+    double acc = sum_sources(ptr[i], ptr[i + 1], src, ebuf);
     acc -= fext[i];
     if (pforce) acc -= pforce[i];
     out[i] = acc;
