@@ -96,28 +96,23 @@ __global__ void __launch_bounds__(256) k_zero_fronts(const int32_t* __restrict__
 
 // One wavefront per child column (four per block): adds the child's Schur complement column
 // (rows >= column) into the parent front through the child's relative map.  A wavefront rather than
-// a block per column keeps the lanes busy on the short columns of small fronts.  The column's task
-// comes from a per-column table; rows go eight per lane at a time, every load (clamped to the
-// column's first row past its end) issued before the first store.  The relative map is injective,
-// so the parent entries a wavefront reads and writes are distinct.
+// a block per column keeps the lanes busy on the short columns of small fronts.  The column's
+// offsets come from one precomputed record (no chain of table lookups before the data); rows go
+// eight per lane at a time, every load (clamped to the column's first row past its end) issued
+// before the first store.  The relative map is injective, so the parent entries a wavefront reads
+// and writes are distinct.
 template <typename T>
-__global__ void __launch_bounds__(256) k_extend_add(int64_t ntasks, int64_t ncols, const int64_t* __restrict__ tasks,
-                                                    const int32_t* __restrict__ col_task, FrontArgs f,
+__global__ void __launch_bounds__(256) k_extend_add(int64_t ncols, const int64_t* __restrict__ cols, FrontArgs f,
                                                     T* __restrict__ front) {
   constexpr int R = 8;
   const int lane = threadIdx.x & 63;
   const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= ncols) return;
-  const int lo = col_task[b];
-  if (lo < 0 || lo >= ntasks) return;  // the table never holds such an entry
-  const int C = (int)tasks[lo * 3], P = (int)tasks[lo * 3 + 1];
-  const int64_t c = b - tasks[lo * 3 + 2];
-  const int64_t sC = f.sn_begin[C + 1] - f.sn_begin[C], mC = f.sn_m[C], uC = mC - sC;
-  if (c >= uC) return;
-  const int64_t mP = f.sn_m[P];
-  const T* src = front + f.sn_front_off[C] + sC + (sC + c) * mC;
-  T* dst = front + f.sn_front_off[P] + (int64_t)f.relmap[f.relmap_off[C] + c] * mP;
-  const int32_t* rel = f.relmap + f.relmap_off[C];
+  const int64_t* rec = cols + 4 * b;
+  const int64_t cu = rec[3], c = cu >> 32, uC = cu & 0xffffffffll;
+  const T* src = front + rec[0];
+  T* dst = front + rec[1];
+  const int32_t* rel = f.relmap + rec[2];
   for (int64_t r0 = c; r0 < uC; r0 += 64 * R) {
     T v[R], o[R];
     int32_t d[R];
@@ -746,11 +741,9 @@ void launch_zero_fronts(int64_t ntasks, const int32_t* tasks, const FrontArgs& f
 }
 
 template <typename T>
-void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const int32_t* col_task,
-                       const FrontArgs& f, T* front, hipStream_t s) {
-  // nblocks: child columns of the round, one wavefront each
-  if (ntasks > 0 && nblocks > 0)
-    k_extend_add<T><<<(unsigned)((nblocks + 3) / 4), 256, 0, s>>>(ntasks, nblocks, tasks, col_task, f, front);
+void launch_extend_add(int64_t ncols, const int64_t* cols, const FrontArgs& f, T* front, hipStream_t s) {
+  // ncols: child columns of the round, one wavefront each
+  if (ncols > 0) k_extend_add<T><<<(unsigned)((ncols + 3) / 4), 256, 0, s>>>(ncols, cols, f, front);
 }
 
 template <typename T>
@@ -788,10 +781,8 @@ template void launch_csr_to_fronts<float>(int64_t, const int32_t*, const int32_t
                                           const double*, float*, hipStream_t);
 template void launch_zero_fronts<double>(int64_t, const int32_t*, const FrontArgs&, double*, hipStream_t);
 template void launch_zero_fronts<float>(int64_t, const int32_t*, const FrontArgs&, float*, hipStream_t);
-template void launch_extend_add<double>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, double*,
-                                        hipStream_t);
-template void launch_extend_add<float>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, float*,
-                                       hipStream_t);
+template void launch_extend_add<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
+template void launch_extend_add<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_panel_diag<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
 template void launch_panel_diag<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_panel_trsm<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);

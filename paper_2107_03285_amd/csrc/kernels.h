@@ -98,8 +98,7 @@ void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* c
 template <typename T>
 void launch_zero_fronts(int64_t ntasks, const int32_t* tasks, const FrontArgs& f, T* front, hipStream_t s);
 template <typename T>
-void launch_extend_add(int64_t ntasks, int64_t nblocks, const int64_t* tasks, const int32_t* col_task,
-                       const FrontArgs& f, T* front, hipStream_t s);
+void launch_extend_add(int64_t ncols, const int64_t* cols, const FrontArgs& f, T* front, hipStream_t s);
 template <typename T>
 void launch_panel_diag(int64_t ntasks, const int64_t* tasks, const FrontArgs& f, T* front, hipStream_t s);
 template <typename T>

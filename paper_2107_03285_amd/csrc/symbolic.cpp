@@ -386,8 +386,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.levels.assign(S.nlevels, LevelPlan());
   S.panel_tasks.clear();
   S.upd_tasks.clear();
-  S.ea_tasks.clear();
-  S.ea_col_task.clear();
+  S.ea_cols.clear();
   S.solve_fwd_tasks.clear();
   S.solve_bwd_tasks.clear();
   S.n_panels = (int64_t)S.panel_col.size();
@@ -428,23 +427,23 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     P.fwd_end = (int64_t)S.solve_fwd_tasks.size() / 2;
     P.bwd_end = (int64_t)S.solve_bwd_tasks.size() / 2;
     for (int r = 0; r < P.max_children; ++r) {
-      P.ea_begin.push_back((int64_t)S.ea_tasks.size() / 3);
-      P.ea_col_begin.push_back((int64_t)S.ea_col_task.size());
+      P.ea_col_begin.push_back((int64_t)S.ea_cols.size() / 4);
       int64_t work = 0;
-      int32_t task = 0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
         int t = S.level_sn[q];
         if (S.child_ptr[t + 1] - S.child_ptr[t] > r) {
           int c = S.child_list[S.child_ptr[t] + r];
-          int64_t uc = S.sn_rows_ptr[c + 1] - S.sn_rows_ptr[c];
-          S.ea_tasks.push_back(c);
-          S.ea_tasks.push_back(t);
-          S.ea_tasks.push_back(work);
-          S.ea_col_task.insert(S.ea_col_task.end(), (size_t)uc, task++);
-          work += uc;  // one wavefront per child column
+          const int64_t uc = S.sn_rows_ptr[c + 1] - S.sn_rows_ptr[c];
+          const int64_t sc = S.sn_begin[c + 1] - S.sn_begin[c], mc = S.sn_m[c], mp = S.sn_m[t];
+          for (int64_t j = 0; j < uc; ++j) {  // one wavefront per child column
+            S.ea_cols.push_back(S.sn_front_off[c] + sc + (sc + j) * mc);
+            S.ea_cols.push_back(S.sn_front_off[t] + (int64_t)S.relmap[S.relmap_off[c] + j] * mp);
+            S.ea_cols.push_back(S.relmap_off[c]);
+            S.ea_cols.push_back((j << 32) | uc);
+          }
+          work += uc;
         }
       }
-      P.ea_end.push_back((int64_t)S.ea_tasks.size() / 3);
       P.ea_work.push_back(work);
     }
     for (int k = 0; k < maxp; ++k) {

@@ -65,8 +65,8 @@ struct PanelStep {
 struct LevelPlan {
   int64_t sn_begin, sn_end;            // range in level_sn (supernodes of this level)
   int max_children;                    // extend-add rounds
-  std::vector<int64_t> ea_begin, ea_end, ea_work;  // per round: range in ea task table, total entries
-  std::vector<int64_t> ea_col_begin;               // per round: offset of its columns in ea_col_task
+  std::vector<int64_t> ea_work;                    // per round: child columns
+  std::vector<int64_t> ea_col_begin;               // per round: its first column record in ea_cols
   std::vector<PanelStep> steps;
   int64_t max_m = 0, max_s = 0, max_u = 0;
   int64_t fwd_begin = 0, fwd_end = 0;  // range (pairs) in solve_fwd_tasks: panels ascending per front
@@ -119,8 +119,10 @@ struct System {
   // task tables (flattened int64 quintuples, see kernels)
   std::vector<int64_t> panel_tasks;      // (sn, c0, c1) per task: 3 entries
   std::vector<int64_t> upd_tasks;        // (sn, k0, k1, cb, ce, tile_prefix): 6 entries
-  std::vector<int64_t> ea_tasks;         // (child, parent, work_prefix): 3 entries
-  std::vector<int32_t> ea_col_task;      // per child column of a round: its task, relative to the round
+  // per child column c of a round, 4 entries: front offset of the child's entry (sC, sC + c) (the
+  // column's rows c.. follow), front offset of the parent column it adds into, offset of the child's
+  // relative map, (c << 32) | uC
+  std::vector<int64_t> ea_cols;
   std::vector<int32_t> solve_fwd_tasks;  // (sn, panel index) pairs, per level; (sn, -1): whole front in one block
   std::vector<int32_t> solve_bwd_tasks;
   int64_t n_panels = 0;                  // total panels (ready flags of the pipelined solves)
