@@ -188,7 +188,10 @@ sgn_status sgn_equilibrium(sgn_ctx ctx, const double* d_p, double* d_x, sgn_eq_i
 sgn_status sgn_assemble(sgn_ctx ctx, const double* d_x, const double* d_p,
                         double* d_rhs, double* d_grad, double* h_obj);
 /* Supernodal LDL^T of the assembled K_SGN (Bunch-Kaufman pivots restricted
- * to each mesh node's variable group).  Checks the inertia (n_x+n_p, n_x, 0). */
+ * to each mesh node's variable group).  Checks the inertia (n_x+n_p, n_x, 0).
+ * Part of the trailing updates runs on a second stream that the context creates
+ * (default priority) and owns; it is forked from and joined back into the
+ * context's stream with events, so the caller sees only its own stream's order. */
 sgn_status sgn_factor(sgn_ctx ctx, sgn_factor_info* info);
 /* Solve K_SGN sol = rhs with the current factor plus FP64 iterative
  * refinement to solve_rtol (both device arrays, [N], block order).  When a
