@@ -370,8 +370,9 @@ void sgn_destroy(sgn_ctx ctx);
  * one warm-up round, in host wall milliseconds on `stream`.  Coordinate descent from *base: each
  * bucket's outer_panels in {1, 2, 4, 8, 16}, then seq_panels in {-1, 2, 4, 8}; a candidate replaces the
  * incumbent only if it is at least 1% faster.  *best receives *base with the chosen setting;
- * h_ms (optional, host, room for 16) the milliseconds of every candidate in the order tried, the
- * first being *base itself; *n_cand (optional) their count (at most 16).  Errors of a candidate's
+ * h_ms (optional, host, room for 16) the milliseconds of the candidates in the order tried, the
+ * first being *base itself (the first 16 only); *n_cand (optional) the number tried: 16 when
+ * *base's settings are among the candidates, up to 20 otherwise.  Errors of a candidate's
  * context (e.g. SGN_E_NOMEM when the device cannot hold it) end the search and are returned. */
 sgn_status sgn_autotune(const sgn_problem* prob, const sgn_options* base, const double* d_x, const double* d_p,
                         int reps, void* stream, sgn_options* best, double* h_ms, int* n_cand);

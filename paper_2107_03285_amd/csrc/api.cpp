@@ -2318,13 +2318,14 @@ sgn_status sgn_autotune(const sgn_problem* prob, const sgn_options* base, const 
   double cur_ms = 0.0;
   sgn_status st = time_candidate(prob, cur, d_x, d_p, reps, stream, &cur_ms);
   if (st != SGN_OK) return st;
+  constexpr int kRecorded = 16;  // entries of h_ms the caller provides
   if (h_ms) h_ms[nc] = cur_ms;
   ++nc;
   auto consider = [&](const sgn_options& cand) -> sgn_status {
     double ms = 0.0;
     const sgn_status s = time_candidate(prob, cand, d_x, d_p, reps, stream, &ms);
     if (s != SGN_OK) return s;
-    if (h_ms) h_ms[nc] = ms;
+    if (h_ms && nc < kRecorded) h_ms[nc] = ms;
     ++nc;
     if (ms < 0.99 * cur_ms) {  // a candidate must beat the incumbent by 1%
       cur = cand;

@@ -226,7 +226,7 @@ def autotune(prob, x, p, options: sgn_options = None, reps: int = 3, stream=None
                           C.byref(n))
     if st != SGN_OK:
         raise SgnError(st, "autotune: a candidate context failed")
-    rec = dict(tuning_of(best), base=tuning_of(base), candidate_ms=[float(v) for v in ms[:n.value]],
+    rec = dict(tuning_of(best), base=tuning_of(base), candidate_ms=[float(v) for v in ms[:min(n.value, 16)]],
                reps=int(reps), problem=getattr(prob, "name", ""))
     if path:
         with open(path, "w") as f:
