@@ -537,8 +537,8 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   __shared__ __attribute__((aligned(16))) T sW[TM][SW];  // sW[c][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // Workgroups are handed to the 8 dies (each with its own L2) round-robin by index; renumber so that
-  // each die takes one contiguous run of tiles.  Consecutive tiles share their W column tile (and
-  // neighbouring runs their L row tiles), which then stays in that die's L2.
+  // each die takes one contiguous run of tiles.  In that run the tiles of one row of a column group
+  // (same L rows) run side by side, and the group's W columns serve all its rows from that die's L2.
   int64_t b;
   {
     const int64_t n = gridDim.x, x = blockIdx.x & 7;
@@ -556,20 +556,11 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   const int sn = (int)tk[0];
   const int64_t k0 = tk[1], k1 = tk[2], cb = tk[3], ce = tk[4];
   const int64_t m = f.sn_m[sn];
-  int64_t lt = b - tk[5];
+  const int64_t lt = b - tk[5];
   const int64_t R = (m - cb + TM - 1) / TM;
   const int64_t ct = (ce - cb + TM - 1) / TM;
-  // Tiles run column block by column block, rows j .. R-1 in column block j, so S(j) = j R - j (j-1) / 2
-  // tiles precede column block j; j is the root of S(j) = lt rounded down, corrected for rounding.
-  auto S = [R](int64_t jj) { return jj * R - jj * (jj - 1) / 2; };
-  const double b2 = 2.0 * (double)R + 1.0;
-  int64_t j = (int64_t)(0.5 * (b2 - sqrt(fmax(0.0, b2 * b2 - 8.0 * (double)lt))));
-  if (j < 0) j = 0;
-  if (j > ct) j = ct;
-  while (j > 0 && S(j) > lt) --j;
-  while (j < ct && S(j + 1) <= lt) ++j;
-  if (j >= ct) return;  // beyond the task's tiles (never for a consistent schedule)
-  const int64_t i = j + (lt - S(j));
+  int64_t i, j;
+  if (!update_tile(lt, R, ct, i, j)) return;  // beyond the task's tiles (never for a consistent schedule)
   const int64_t r0 = cb + TM * i, cc0 = cb + TM * j;
   T* F = front + f.sn_front_off[sn];
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;

@@ -9,6 +9,39 @@ namespace sgn {
 
 constexpr int kRedBlocks = 1024;  // fixed partition of deterministic reductions
 constexpr int kUpdTile = 64;      // edge of the trailing-update tile (the symbolic schedule counts these tiles)
+constexpr int kUpdGroup = 8;      // column tiles per group of the trailing update's tile order
+
+// Tile lt of a trailing update over R row tiles and ct <= R column tiles (tile (i, j) for j < ct,
+// j <= i < R; ct R - ct (ct - 1) / 2 tiles): column tiles go in groups of kUpdGroup, and a group's
+// tiles run row by row, so the tiles of one row (sharing their L rows) run side by side and the
+// group's W columns serve every row.  Full groups J' before group J hold
+// G (G + 1) / 2 + (R - G J' - G) G tiles each.  Returns false past the last tile.
+__host__ __device__ inline bool update_tile(int64_t lt, int64_t R, int64_t ct, int64_t& i, int64_t& j) {
+  constexpr int64_t G = kUpdGroup;
+  if (lt < 0) return false;
+  int64_t g0 = 0;  // first column tile of the group
+  for (;;) {
+    if (g0 >= ct) return false;
+    const int64_t w = ct - g0 < G ? ct - g0 : G;
+    const int64_t n = w * (w + 1) / 2 + (R - g0 - w) * w;
+    if (lt < n) {
+      const int64_t head = w * (w + 1) / 2;
+      int64_t d;
+      if (lt < head) {
+        d = 0;
+        while ((d + 1) * (d + 2) / 2 <= lt) ++d;
+        j = g0 + (lt - d * (d + 1) / 2);
+      } else {
+        d = w + (lt - head) / w;
+        j = g0 + (lt - head) % w;
+      }
+      i = g0 + d;
+      return i < R;
+    }
+    lt -= n;
+    g0 += G;
+  }
+}
 
 // ---------------------------------------------------------------- element + assembly
 struct ElemArgs {
