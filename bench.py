@@ -41,7 +41,7 @@ HBM_PEAK = 8000.0  # GB/s
 # WRITE_SIZE, scaled by what the counters read for a plain copy of known size).  The record holds a
 # hash of the kernel's source; a record taken from another version of the kernel is not used.
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_update_cantilever_100x25x25_traffic.json")
-UPDATE_SOURCES = [os.path.join(ROOT, "paper_2107_03285_amd", "csrc", "k_factor.hip")]
+UPDATE_SOURCES = [os.path.join(ROOT, "paper_2107_03285_amd", "csrc", f) for f in ("k_factor.hip", "kernels.h")]
 COPY_ELEMS = 1 << 28  # float32 elements of the calibration copy: 1 GiB read + 1 GiB written
 
 
