@@ -22,7 +22,11 @@ written so that complex weights propagate (complex-step gradients).
 Pins (tests/test_oracle_gnn.py): zero decoders give zero outputs; outputs are
 invariant under a rigid translation of the mesh and states; relabelling the
 nodes permutes the outputs; complex-step gradients agree with central
-differences.
+differences.  symmetric_operator: symmetric, T^2 = I at the reference matrix with
+zero corrections, spectrum equal to that of M^-1 K with M built densely from the
+reference factor.  train_loss: zero for uniform corrections at the reference
+matrix (T^2 = e^{-4c} I, absorbed by the best scale), unchanged when K is scaled,
+complex-step derivative equal to central differences.
 """
 from __future__ import annotations
 

@@ -3,7 +3,12 @@
 Zero decoders give zero corrections; a rigid translation of mesh and states
 leaves the outputs unchanged; relabelling the nodes permutes the outputs the same
 way; complex-step weight gradients agree with central differences; the weight
-count follows the layer list.
+count follows the layer list.  The training loss: at the reference matrix with
+zero corrections its symmetric operator squares to the identity; its spectrum is
+that of M^-1 K with M assembled densely from the reference factor; the best-scale
+substitution makes the loss vanish for uniform corrections and leaves it unchanged
+when the matrix is scaled; its complex-step derivative agrees with central
+differences.
 """
 import dataclasses
 
@@ -100,3 +105,138 @@ def test_weight_count():
     H = 64
     expect = (9 + 1) * H + (6 + 1) * H + 3 * ((3 * H + 1) * H + (2 * H + 1) * H) + (H + 1) * 21 + (H + 1) * 1
     assert G.num_weights(prob) == expect
+
+
+# ---- the training loss and its symmetric operator ------------------------------------------------
+# T = (R C)^-1 L^-1 Q K Q^T L^-T (R C)^-T is similar to M^-1 K (M the preconditioner of the same
+# reference factor and corrections), symmetric, and equal to R^-1 D R^-T (eigenvalues +-1) when K is
+# the reference matrix and the corrections vanish.  The loss substitutes the best scale gamma, so a
+# uniform correction (M -> e^{2c} M) leaves it at zero and scaling K leaves it unchanged.
+
+from oracle import dense as D  # noqa: E402
+from oracle import precond as PC  # noqa: E402
+
+
+@pytest.fixture(scope="module", params=["tiny", "loge3d", "rest3d"])
+def ref_case(request):
+    mk = {"tiny": si.config_tiny,
+          "loge3d": lambda: si.problem_3d(3, 2, 2, 1 / 3, seed=2),
+          "rest3d": lambda: si.problem_3d(3, 2, 2, 1 / 3, seed=1, param_kind=si.P_REST_POS)}[request.param]
+    prob = D.setup_targets(mk())
+    rng = np.random.default_rng(7)
+    p = prob.p_init() + 0.05 * rng.standard_normal(prob.n_p)
+    x, info = D.equilibrium(prob, p)
+    assert info.converged
+    K = PC.sgn_matrix(prob, x, p)
+    P = PC.Preconditioner(prob, K)
+    # a second state near the reference one (the matrices the loss sees in training)
+    p2 = p + 0.02 * rng.standard_normal(prob.n_p)
+    x2, info2 = D.equilibrium(prob, p2)
+    assert info2.converged
+    K2 = PC.sgn_matrix(prob, x2, p2)
+    return prob, x, p, K, P, x2, p2, K2
+
+
+def _tri(prob):
+    nb = 2 * prob.dim
+    return nb * (nb + 1) // 2
+
+
+def _uniform_weights(prob, c):
+    """Network weights whose corrections are exactly c on every diagonal position and 0 elsewhere."""
+    w = np.zeros(G.num_weights(prob))
+    L = G.unpack(prob, w)
+    nb = 2 * prob.dim
+    _, bn = L["dec_node"]
+    for i in range(nb):
+        bn[i * (i + 1) // 2 + i] = c
+    if prob.param_kind == si.P_LOGE:
+        L["dec_elem"][1][:] = c
+    else:
+        bn[_tri(prob):] = c
+    return w
+
+
+def test_symmetric_operator_at_reference_squares_to_identity(ref_case):
+    prob, x, p, K, P, *_ = ref_case
+    n = K.shape[0]
+    T = G.symmetric_operator(prob, P, K, np.zeros(prob.n_nodes * _tri(prob)), np.zeros(prob.n_p))
+    # T = R^-1 D R^-T: block diagonal with eigenvalues exactly +-1, so T^2 = I up to cond(L) rounding
+    assert np.abs(T - T.T).max() <= 1e-9
+    assert np.abs(T @ T - np.eye(n)).max() <= 1e-8
+    ev = np.linalg.eigvalsh(0.5 * (T + T.T))
+    assert np.sum(ev > 0) == prob.n_x + prob.n_p and np.sum(ev < 0) == prob.n_x
+
+
+def test_symmetric_operator_spectrum_is_that_of_preconditioned_matrix(ref_case):
+    prob, x, p, K, P, x2, p2, K2 = ref_case
+    rng = np.random.default_rng(11)
+    cn = 0.3 * rng.standard_normal(prob.n_nodes * _tri(prob))
+    cp = 0.3 * rng.standard_normal(prob.n_p)
+    T = G.symmetric_operator(prob, P, K2, cn, cp)
+    scale = np.abs(T).max()
+    assert np.abs(T - T.T).max() <= 1e-9 * scale
+    ev_t = np.sort(np.linalg.eigvalsh(0.5 * (T + T.T)))
+    # M assembled densely from the reference factor (L B L^T, B = R C C^T R^T), then M^-1 K directly
+    M = P.matrix(cn, cp)
+    ev_m = np.linalg.eigvals(np.linalg.solve(M, K2))
+    assert np.abs(ev_m.imag).max() <= 1e-6 * np.abs(ev_m).max()   # similar to a symmetric matrix
+    ev_m = np.sort(ev_m.real)
+    assert np.abs(ev_t - ev_m).max() <= 1e-6 * np.abs(ev_t).max(), np.abs(ev_t - ev_m).max()
+
+
+def test_train_loss_vanishes_at_reference_for_uniform_corrections(ref_case):
+    prob, x, p, K, P, *_ = ref_case
+    rng = np.random.default_rng(2)
+    probes = [rng.standard_normal(K.shape[0]) for _ in range(3)]
+    state = (x, p, x, p, 0.05)
+    for c in (0.0, 0.7):
+        w = _uniform_weights(prob, c)
+        cn, cp = G.forward(prob, w, *state)
+        nb = 2 * prob.dim
+        diag = np.array([i * (i + 1) // 2 + i for i in range(nb)])
+        cnr = cn.reshape(prob.n_nodes, -1)
+        assert np.all(cnr[:, diag] == c) and np.all(np.delete(cnr, diag, axis=1) == 0) and np.all(cp == c)
+        # C = e^c I, so T = e^{-2c} T0 and T^2 = e^{-4c} I: the best scale gamma = e^{4c} makes every
+        # probe's residual vanish (without gamma the loss would be (e^{-4c} - 1)^2)
+        T = G.symmetric_operator(prob, P, K, cn, cp)
+        assert np.abs(T @ T - np.exp(-4 * c) * np.eye(K.shape[0])).max() <= 1e-8
+        assert G.train_loss(prob, P, K, w, state, probes) <= 1e-14
+
+
+def test_train_loss_is_invariant_to_scaling_the_matrix(ref_case):
+    prob, x, p, K, P, x2, p2, K2 = ref_case
+    rng = np.random.default_rng(4)
+    probes = [rng.standard_normal(K.shape[0]) for _ in range(2)]
+    w = 0.05 * rng.standard_normal(G.num_weights(prob))
+    state = (x, p, x2, p2, 0.05)
+    l1 = G.train_loss(prob, P, K2, w, state, probes)
+    l2 = G.train_loss(prob, P, 3.0 * K2, w, state, probes)
+    assert 0.0 < l1 < 1.0
+    assert abs(l1 - l2) <= 1e-10 * l1
+    # one probe by hand: gamma = u.b / b.b with b = T^2 u minimises |gamma b - u|^2
+    u = probes[0]
+    cn, cp = G.forward(prob, w, *state)
+    T = G.symmetric_operator(prob, P, K2, cn, cp)
+    b = T @ (T @ u)
+    gam = (u @ b) / (b @ b)
+    best = np.sum((gam * b - u) ** 2) / (u @ u)
+    for g in (0.9 * gam, 1.1 * gam):
+        assert np.sum((g * b - u) ** 2) / (u @ u) > best
+    assert abs(G.train_loss(prob, P, K2, w, state, [u]) - best) <= 1e-12 * best
+
+
+def test_train_loss_complex_step_matches_central_differences(ref_case):
+    prob, x, p, K, P, x2, p2, K2 = ref_case
+    rng = np.random.default_rng(6)
+    probes = [rng.standard_normal(K.shape[0]) for _ in range(2)]
+    w = 0.05 * rng.standard_normal(G.num_weights(prob))
+    state = (x, p, x2, p2, 0.05)
+    u = rng.standard_normal(w.size)
+    h = 1e-30
+    cs = G.train_loss(prob, P, K2, w.astype(np.complex128) + 1j * h * u, state, probes).imag / h
+    hd = 1e-5
+    fd = (G.train_loss(prob, P, K2, w + hd * u, state, probes)
+          - G.train_loss(prob, P, K2, w - hd * u, state, probes)) / (2 * hd)
+    assert abs(cs - fd) <= 1e-5 * max(abs(fd), 1e-8), (cs, fd)
+    assert abs(fd) > 0
