@@ -20,8 +20,12 @@ Modules:
   fem       -- neo-Hookean linear-simplex element: energy and closed-form
                gradient; Hessians by complex-step differentiation.
   dense     -- global assembly, Newton equilibrium, dense S / GN step, dense
-               solve of the saddle-point system, objective and gradient.
+               solve of the saddle-point system, objective and gradient; the
+               variants of Sec. 4: block Gauss-Newton step (Appendix B) and
+               L-BFGS initialised with the Gauss-Newton Hessian.
   symbolic  -- K_SGN pattern, nested-dissection order, permuted CSR, etree.
+  krylov    -- the stabilised saddle-point matrix and BiCGSTAB of the paper's robust fall-back
+               solve (Sec. 5).
   precond   -- dense LDL^T with node-group-restricted Bunch-Kaufman pivoting and
                the node-block preconditioner built from it (the library's
                MINRES path; the paper leaves preconditioning to future work).

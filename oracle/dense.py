@@ -429,3 +429,103 @@ def sgn_iterations(prob: Problem, p: np.ndarray, x: np.ndarray, iters: int = 10,
         trace.append((f0, float(np.linalg.norm(st.grad)), a))
         p, x = pt, xt
     return trace, p, x
+
+
+# ----------------------------------------------------------------------------- variants (Sec. 4)
+
+def block_gn_step(prob: Problem, x: np.ndarray, p: np.ndarray) -> Step:
+    """Block Gauss-Newton step (Sec. 4 "Block Solve", Appendix B) for objectives without a direct
+    parameter term (B = 0, C = 0) and a square, invertible Kp = dc/dp.
+
+    Block substitution of eq. sparseSystemGN with the adjoint right-hand side [0; -g; 0]:
+      Kp^T dlam = -g                   -> dlam = -Kp^-T g  (= -lam_adj, as g = Kp^T lam_adj)
+      A dx + Kx^T dlam = 0             -> dx = -A^-1 df/dx^T
+      Kx dx + Kp dp = 0                -> dp = -Kp^-1 Kx dx = Kp^-1 Kx A^-1 df/dx^T
+    (the appendix's sign; the body of Sec. 4 prints the opposite one).  Dense LU solves with Kp.
+    """
+    Kx = stiffness(prob, x, p).toarray()
+    Kp = param_jacobian(prob, x, p).toarray()
+    fx, fp, A, B, C = objective_blocks(prob, x, p)
+    if Kp.shape[0] != Kp.shape[1]:
+        raise ValueError("block solve needs a square Kp")
+    if B.nnz or np.any(C.diagonal() != 0):
+        raise ValueError("block solve needs B = 0 and C = 0")
+    a = A.diagonal()
+    if np.any(a == 0):
+        raise ValueError("block solve needs an invertible A (every free DOF a target)")
+    dx = -fx / a
+    dp = np.linalg.solve(Kp, -(Kx @ dx))
+    lam_adj = -np.linalg.solve(Kx.T, fx)
+    g = fp + Kp.T @ lam_adj
+    dlam = -np.linalg.solve(Kp.T, g)
+    return Step(dx, dp, dlam, g, lam_adj)
+
+
+def dense_gn_hessian(prob: Problem, x: np.ndarray, p: np.ndarray):
+    """(H, g): the reduced Gauss-Newton Hessian H = S^T A S + B S + S^T B^T + C (eq. reducedGN) and the
+    gradient g = df/dp^T + S^T df/dx^T (eq. totalGradient), dense."""
+    Kx = stiffness(prob, x, p).toarray()
+    Kp = param_jacobian(prob, x, p).toarray()
+    fx, fp, A, B, C = objective_blocks(prob, x, p)
+    S = -sla.cho_solve(sla.cho_factor(Kx, lower=True), Kp)
+    g = fp + S.T @ fx
+    Bd = B.toarray()
+    H = S.T @ (A.diagonal()[:, None] * S) + Bd @ S + S.T @ Bd.T + C.toarray()
+    return 0.5 * (H + H.T), g
+
+
+def lbfgs_direction(g: np.ndarray, pairs, h0_solve) -> np.ndarray:
+    """-H_k g by the L-BFGS two-loop recursion (Nocedal & Wright, Algorithm 7.4) over the curvature
+    pairs [(s_i, y_i)] (oldest first) with the initial inverse Hessian applied by h0_solve (for the
+    SGN-initialised form: the inverse Gauss-Newton Hessian of the current iterate, Sec. 4
+    "Combination with L-BFGS")."""
+    q = g.copy()
+    alphas = []
+    for s, y in reversed(pairs):
+        a = (s @ q) / (y @ s)
+        alphas.append(a)
+        q = q - a * y
+    r = h0_solve(q)
+    for (s, y), a in zip(pairs, reversed(alphas)):
+        b = (y @ r) / (y @ s)
+        r = r + s * (a - b)
+    return -r
+
+
+def lbfgs_sgn_iterations(prob: Problem, p: np.ndarray, x: np.ndarray, iters: int = 10, m: int = 5,
+                         c1: float = 1e-4, max_halvings: int = 30, curvature_eps: float = 1e-12):
+    """L-BFGS whose initial inverse Hessian is the Gauss-Newton one of the current iterate (Sec. 4,
+    "Combination with L-BFGS": one saddle-point solve per search direction), with the outer loop's
+    Armijo backtracking (one equilibrium per trial).  A pair (s, y) = (p+ - p, g+ - g) enters the
+    memory of the newest m pairs only when s^T y > curvature_eps |s| |y| (a reading: the paper gives
+    no memory size or curvature rule).  Returns the trace [(f, |g|, alpha)] and the final (p, x)."""
+    pairs = []
+    prev = None
+    trace = []
+    for _ in range(iters):
+        H, g = dense_gn_hessian(prob, x, p)
+        if prev is not None:
+            s, y = p - prev[0], g - prev[1]
+            if m > 0 and s @ y > curvature_eps * np.linalg.norm(s) * np.linalg.norm(y):
+                pairs = (pairs + [(s, y)])[-m:]
+        fac = sla.cho_factor(H, lower=True)
+        d = lbfgs_direction(g, pairs, lambda q: sla.cho_solve(fac, q))
+        f0 = objective(prob, x, p)
+        slope = float(g @ d)
+        a = 1.0
+        for _ in range(max_halvings):
+            pt = p + a * d
+            xt, info = equilibrium(prob, pt, x)
+            if info.converged and objective(prob, xt, pt) <= f0 + c1 * a * slope:
+                break
+            a *= 0.5
+        else:
+            if abs(slope) > 1e-12 * abs(f0):
+                raise RuntimeError("line search failed")
+            trace.append((f0, float(np.linalg.norm(g)), 0.0))
+            prev = (p, g)
+            continue
+        trace.append((f0, float(np.linalg.norm(g)), a))
+        prev = (p, g)
+        p, x = pt, xt
+    return trace, p, x
