@@ -49,29 +49,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(budget_s: float = 20.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(budget_s: float = 20.0, budget_1t_s: float = 8.0):
     """The FP64 oracle's dense Gauss-Newton step, timed on the host cores, on the smallest
     cantilever of the same family (20 x 5 x 5 hexes): the dense method cannot hold the
-    200k-DOF problem (its sensitivity matrix alone would be ~500 GB)."""
-    from threadpoolctl import threadpool_info
+    200k-DOF problem (its sensitivity matrix alone would be ~500 GB).  Timed with the BLAS
+    threads the host gives and again with one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import dense as D
     prob = D.setup_targets(si.problem_3d(20, 5, 5, 0.2, seed=0))
     p = prob.p_init()
     x, _ = D.equilibrium(prob, p)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        D.dense_gn_step(prob, x, p)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 50:
-            break
-    dt = time.perf_counter() - t0
+
+    def timed(budget, cap):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            D.dense_gn_step(prob, x, p)
+            n += 1
+            if time.perf_counter() - t0 > budget or n >= cap:
+                break
+        return n, time.perf_counter() - t0
+
+    n, dt = timed(budget_s, 50)
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    with threadpool_limits(limits=1):
+        n1, dt1 = timed(budget_1t_s, 20)
     return {"value": n / dt, "unit": "SGN steps/s", "cores": int(threads), "kind": "oracle",
+            "value_1thread": n1 / dt1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"dense GN step (S = -Kx^-1 Kp, H = S^T A S + C, Cholesky) of the oracle on the "
                       f"20x5x5-hex cantilever of the same family (n_x={prob.n_x}, n_p={prob.n_p}), "
-                      f"{n} steps in {dt:.1f} s"}
+                      f"{n} steps in {dt:.1f} s with {threads} BLAS threads, {n1} steps in {dt1:.1f} s "
+                      f"with one"}
 
 
 def update_source_hash():
@@ -217,18 +237,208 @@ def batch_leg(steps: int, warmup: int, dev: str = "cuda:0", autotune: bool = Fal
                      f"solve), replayed; the residual checked on the device at every replay"}
 
 
+WEIGHTS_DIR = os.path.join(ROOT, "paper_2107_03285_amd", "weights")
+
+
+def learned_pc_leg(sgn, prob, x, p, dp, dev, steps, fractions=(1.0, 0.05)):
+    """The learned-preconditioner form at the workload's size: the reference factor (FP32 fronts) is
+    the exact LDL^T at the current iterate (x, p); the next system is the one a fraction t along the
+    FP64 Gauss-Newton step dp (t = 1: the next iterate; t = 0.05: a short move, like a late iteration
+    or a line-search trial), at its equilibrium.  One timed step = assembly of the next system + MINRES
+    with the reference factor's node-block preconditioner to the 1e-10 equilibrated residual, with
+    the exact LDL^T + refinement as its fallback.  Timed with the trained network's corrections (weights
+    file of the 3D log-modulus family, when present) and with none; the reference is re-established
+    (untimed) before every step."""
+    import torch
+    wpath = os.path.join(WEIGHTS_DIR, "pc_3d_loge.f32")
+    o = sgn.default_options(precision=sgn.SGN_FP32_IR, solver=sgn.SGN_MINRES_LEARNED, rhs_kind=sgn.SGN_RHS_KKT,
+                            max_minres=300)
+    ctx = sgn.Context(prob, o).allocate(dev)
+    ctx.set_targets(prob.target_val, prob.length_scale)
+    w = None
+    if os.path.exists(wpath):
+        wh = np.fromfile(wpath, dtype=np.float32)
+        if wh.size == ctx.gnn_num_weights():
+            w = torch.tensor(wh, device=dev)
+    N = 2 * prob.n_x + prob.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device=dev)
+    sol = torch.zeros(N, dtype=torch.float64, device=dev)
+    out = {"weights": os.path.relpath(wpath, ROOT) if w is not None else None, "fractions": {}}
+    for t0_ in fractions:
+        t = t0_
+        while True:  # the next system must have an equilibrium (the outer line search halves the same way)
+            p1 = p + t * dp
+            x1 = x.clone()
+            try:
+                ctx.equilibrium(p1, x1)
+                break
+            except sgn.SgnError:
+                ctx = sgn.Context(prob, o).allocate(dev)  # an error is sticky: start a fresh context
+                ctx.set_targets(prob.target_val, prob.length_scale)
+                t *= 0.5
+                if t < 1e-3:
+                    raise
+        row = {"t": t}
+        for label, use in (("with_network", True), ("without_network", False)):
+            if use and w is None:
+                row[label] = None
+                continue
+            times, iters, fb, res = [], [], [], []
+            for k in range(steps):
+                ctx.assemble(x, p)  # reference factor at the current iterate (untimed)
+                ctx.factor()
+                if use:
+                    ctx.set_pc_weights(w)
+                else:
+                    ctx.set_pc_correction(None, None)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.assemble(x1, p1, rhs)
+                info = ctx.solve_minres(rhs, sol)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                iters.append(int(info.sweeps))
+                fb.append(int(info.fallback))
+                res.append(info.rel_res)
+            row[label] = {"steps_per_s": len(times) / sum(times), "ms_per_step": 1e3 * sum(times) / len(times),
+                          "minres_iterations": iters[-1], "fallback_rate": float(np.mean(fb)),
+                          "rel_res_max": max(res)}
+        out["fractions"][str(t0_)] = row
+        log(f"[bench] learned-PC t = {t}: {row}")
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def variants_leg(sgn, dev, steps):
+    """The Sec. 4/5 variants, each timed for one search direction beside the plain direction on the same
+    system: the block solve on a rest-position bar (every free DOF a target, no regulariser: the
+    conditions of the block solve) against the full SGN solve of the same system in FP64; and BiCGSTAB
+    preconditioned by the LDL^T of the stabilised matrix (eps = 1e-6, Sec. 5) at the workload's size."""
+    import torch
+    out = {}
+    prob = si.problem_3d(40, 10, 10, 0.1, seed=0, param_kind=si.P_REST_POS)
+    prob.reg_mu = 0.0
+    x = torch.tensor(prob.x_rest(), dtype=torch.float64, device=dev)
+    p = torch.tensor(prob.p_init(), dtype=torch.float64, device=dev)
+    setup = sgn.Context(prob, sgn.default_options()).allocate(dev)
+    setup.equilibrium(p, x)
+    xh = x.cpu().numpy()
+    prob.target_dof = np.arange(prob.n_x, dtype=np.int32)
+    prob.target_val = xh + 1e-3 * np.sin(np.arange(prob.n_x))
+    prob.length_scale = float(np.max(np.abs(xh - prob.x_rest())))
+    del setup
+    N = 2 * prob.n_x + prob.n_p
+    sols = {}
+    for label, solver in (("block_gn", sgn.SGN_BLOCK_GN), ("sgn_ldlt_fp64", sgn.SGN_LDLT)):
+        ctx = sgn.Context(prob, sgn.default_options(solver=solver, rhs_kind=sgn.SGN_RHS_KKT)).allocate(dev)
+        xe = x.clone()
+        ctx.equilibrium(p, xe)
+        rhs = torch.zeros(N, dtype=torch.float64, device=dev)
+        sol = torch.zeros(N, dtype=torch.float64, device=dev)
+
+        def one():
+            if solver == sgn.SGN_BLOCK_GN:
+                return ctx.block_step(xe, p, sol)
+            ctx.assemble(xe, p, rhs)
+            ctx.factor()
+            return ctx.solve(rhs, sol)
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = one()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        sols[label] = sol.cpu().numpy()
+        out[label] = {"ms_per_direction": 1e3 * dt, "iterations": int(info.sweeps), "rel_res": info.rel_res}
+        del ctx
+        torch.cuda.empty_cache()
+    nx, npar = prob.n_x, prob.n_p
+    a, b = sols["block_gn"][nx:nx + npar], sols["sgn_ldlt_fp64"][nx:nx + npar]
+    out["block_vs_sgn"] = {"workload": f"{prob.name}, every free DOF a target, reg_mu = 0 (n_x = {nx})",
+                           "speedup": out["sgn_ldlt_fp64"]["ms_per_direction"] / out["block_gn"]["ms_per_direction"],
+                           "dp_rel_diff": float(np.linalg.norm(a - b) / np.linalg.norm(b))}
+    torch.cuda.empty_cache()
+    return out
+
+
+def bicgstab_leg(sgn, prob, x, p, dev, steps, dp_ref):
+    """BiCGSTAB on K preconditioned by the FP32 LDL^T of the stabilised matrix (eps_x = eps_lambda =
+    1e-6, Sec. 5) at the workload's size: one direction (assembly + factorisation + BiCGSTAB)."""
+    import torch
+    o = sgn.default_options(precision=sgn.SGN_FP32_IR, solver=sgn.SGN_BICGSTAB, rhs_kind=sgn.SGN_RHS_KKT,
+                            eps_x=1e-6, eps_lambda=1e-6)
+    ctx = sgn.Context(prob, o).allocate(dev)
+    ctx.set_targets(prob.target_val, prob.length_scale)
+    N = 2 * prob.n_x + prob.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device=dev)
+    sol = torch.zeros(N, dtype=torch.float64, device=dev)
+
+    def one():
+        ctx.assemble(x, p, rhs)
+        ctx.factor()
+        return ctx.solve(rhs, sol)
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    nx, npar = prob.n_x, prob.n_p
+    dp = sol.cpu().numpy()[nx:nx + npar]
+    del ctx
+    torch.cuda.empty_cache()
+    return {"steps_per_s": 1.0 / dt, "ms_per_step": 1e3 * dt, "bicgstab_iterations": int(info.sweeps),
+            "rel_res": info.rel_res, "raw_rel_res": info.raw_rel_res,
+            "dp_rel_diff_vs_fp64": float(np.linalg.norm(dp - dp_ref) / np.linalg.norm(dp_ref))
+            if dp_ref is not None else None}
+
+
+def speedups(results):
+    """FP32 + refinement over FP64, like for like: replayed graph against replayed graph, eager against
+    eager."""
+    out = {}
+    for label, a, b in (("graph_vs_graph", "fp32ir_graph", "fp64_graph"), ("eager_vs_eager", "fp32ir", "fp64")):
+        if a in results and b in results:
+            out[label] = results[a]["steps_per_s"] / results[b]["steps_per_s"]
+    return out or None
+
+
+def stage_rooflines(results):
+    """Assembly (HBM bound: algorithmic bytes of inputs and CSR values over the measured assembly time) and
+    factorisation (matrix cores: dense front flops over the measured factorisation time) of the eager
+    paths as fractions of the chip's peaks; the graph replays time the whole step only."""
+    out = {}
+    for path, peak in (("fp32ir", PEAK["fp32"]), ("fp64", PEAK["fp64"])):
+        r = results.get(path)
+        if not r or r.get("assemble_gbs") is None:
+            continue
+        out[path] = {
+            "assembly": {"bound": "hbm", "achieved": round(r["assemble_gbs"], 2), "peak": HBM_PEAK, "unit": "GB/s",
+                         "frac": round(r["assemble_gbs"] / HBM_PEAK, 4), "ms": r["assemble_ms"]},
+            "factorization": {"bound": "mfma", "achieved": round(r["factor_tflops"], 2), "peak": peak,
+                              "unit": "TFLOP/s", "frac": round(r["factor_tflops"] / peak, 4), "ms": r["factor_ms"]},
+        }
+    return out or None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cantilever_100x25x25", choices=sorted(WORKLOADS))
-    ap.add_argument("--paths", default="fp32ir_graph,fp32ir,fp64,fp32ir_adjoint",
-                    help="fp32ir / fp64: KKT right-hand side, eager launches; fp32ir_graph: the same step captured "
-                         "once into a HIP graph and replayed; fp32ir_adjoint: adjoint right-hand side (one Kx solve)")
+    ap.add_argument("--paths", default="fp32ir_graph,fp32ir,fp64,fp64_graph,fp32ir_adjoint",
+                    help="fp32ir / fp64: KKT right-hand side, eager launches; fp32ir_graph / fp64_graph: the same "
+                         "step captured once into a HIP graph and replayed; fp32ir_adjoint: adjoint right-hand "
+                         "side (one Kx solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events on the update kernel")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-problem leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the learned-preconditioner, BiCGSTAB and block-solve legs")
     ap.add_argument("--autotune", action="store_true",
                     help="run the blocking autotuner on the workload and the batched union first and store its "
                          "records (paper_2107_03285_amd/tuning/); later runs use them")
@@ -295,13 +505,14 @@ def main():
     class GraphInfo:  # what the graph step reports in place of the eager factor / solve infos
         def __init__(self, rel, n_ir):
             self.rel_res, self.sweeps, self.ms = rel, n_ir, 0.0
+            self.raw_rel_res = None
             self.n_pos = self.n_neg = self.n_zero = self.n_perturbed = -1
 
     results = {}
     sols = {}
     for path in paths:
         prec = {"fp32ir": sgn.SGN_FP32_IR, "fp64": sgn.SGN_FP64, "fp32ir_adjoint": sgn.SGN_FP32_IR,
-                "fp32ir_graph": sgn.SGN_FP32_IR}[path]
+                "fp32ir_graph": sgn.SGN_FP32_IR, "fp64_graph": sgn.SGN_FP64}[path]
         adj = path.endswith("_adjoint")
         graph = path.endswith("_graph")
         ctx = ref_ctx if (prec == f64 and not adj) else make_ctx(prec, sgn.SGN_RHS_ADJOINT if adj else None)
@@ -331,6 +542,7 @@ def main():
         upd_n = 0
         asm_ms = fac_ms = sol_ms = 0.0
         res = []
+        raw = []
         sweeps = []
         step_ms = []
         for k in range(args.steps):
@@ -346,6 +558,7 @@ def main():
             fac_ms += st.factor_ms
             sol_ms += st.solve_ms
             res.append(si_.rel_res)
+            raw.append(si_.raw_rel_res)
             sweeps.append(si_.sweeps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -356,6 +569,7 @@ def main():
             iqr_ms=float(np.percentile(step_ms, 75) - np.percentile(step_ms, 25)), factor_ms=fac_ms / K, solve_ms=sol_ms / K,
             assemble_ms=asm_ms / K, assemble_gbs=st.assemble_bytes / (asm_ms / K * 1e-3) / 1e9,
             factor_tflops=st.factor_flops / (fac_ms / K * 1e-3) / 1e12, rel_res_max=max(res),
+            raw_rel_res_max=max(raw) if all(v is not None for v in raw) else None,
             refine_sweeps=max(sweeps), inertia=[fi.n_pos, fi.n_neg, fi.n_zero], perturbed=fi.n_perturbed,
             update_ms=upd_ms / K, update_tflops=(upd_fl / (upd_ms * 1e-3) / 1e12) if upd_ms > 0 else None,
             update_launches=upd_n // K, update_avg_us=(1e3 * upd_ms / upd_n) if upd_n else None,
@@ -400,6 +614,21 @@ def main():
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_update (MFMA trailing update of the fronts)",
                 "avg_launch_us": r["update_avg_us"], "flops_per_launch": r["update_flops_per_launch"]}
+    if roof is not None:
+        roof["stages"] = stage_rooflines(results)
+    learned = bicg = variants = None
+    if not args.no_variants:
+        nx, npar = prob.n_x, prob.n_p
+        dp_ref = sols["fp64"][nx:nx + npar] if "fp64" in sols else None
+        if dp_ref is not None:
+            log("[bench] learned-preconditioner leg")
+            learned = learned_pc_leg(sgn, prob, x, p, torch.tensor(dp_ref, device=dev), dev, max(2, args.steps // 4))
+        log("[bench] BiCGSTAB leg")
+        bicg = bicgstab_leg(sgn, prob, x, p, dev, max(2, args.steps // 4), dp_ref)
+        log(f"[bench] BiCGSTAB: {bicg}")
+        log("[bench] block-solve leg")
+        variants = variants_leg(sgn, dev, max(3, args.steps // 2))
+        log(f"[bench] variants: {variants}")
     batch = None
     if not args.no_batch:
         log("[bench] batched leg: 256 2D problems, captured-graph step vs one at a time")
@@ -424,9 +653,11 @@ def main():
         "paths": results,
         "blocking": {("fp32" if k == sgn.SGN_FP32_IR else "fp64"): v for k, v in blocking.items()},
         "fp32_vs_fp64_step": err,
-        "speedup_vs_fp64": (results[head]["steps_per_s"] / results["fp64"]["steps_per_s"]
-                            if "fp64" in results else None),
+        "speedup_vs_fp64": speedups(results),
         "roofline": roof,
+        "learned_pc": learned,
+        "bicgstab_stabilised": bicg,
+        "block_solve": variants,
         "batched_2d_256": batch,
         "cpu_baseline": cpu,
     }

@@ -71,8 +71,12 @@ typedef enum {
 enum { SGN_P_LOGE = 0, SGN_P_REST_POS = 1, SGN_P_NODAL_FORCE = 2 };
 /* internal factor precision of the saddle-point system */
 enum { SGN_FP64 = 0, SGN_FP32_IR = 1 };
-/* linear solver of the saddle-point system */
-enum { SGN_LDLT = 0, SGN_MINRES_LEARNED = 1 };
+/* linear solver of the saddle-point system: refined LDL^T; MINRES with the learned preconditioner;
+ * BiCGSTAB on K preconditioned by the LDL^T of the stabilised matrix K + diag(eps_x 1, 0, -eps_lambda 1)
+ * (Sec. 5, "Solving the saddle point problem"; set eps_x, eps_lambda, e.g. 1e-6 as there); the
+ * block solve of Sec. 4 ("Block Solve", Appendix B), which needs no factorisation of K_SGN
+ * (see sgn_block_step for its conditions) */
+enum { SGN_LDLT = 0, SGN_MINRES_LEARNED = 1, SGN_BICGSTAB = 2, SGN_BLOCK_GN = 3 };
 /* right-hand side of the step: [0; -g; 0] (eq. sparseSystemGN) or the KKT
  * form [-df/dx^T; -df/dp^T; 0] (Appendix A), which gives the same dp and a
  * multiplier block shifted by the adjoint multiplier */
@@ -126,6 +130,8 @@ typedef struct {
   int seq_panels;               /* fronts with at most this many panels are solved by one
                                    workgroup instead of a pipeline of workgroups (-1: none, 0:
                                    default 8, else 1..8) */
+  int max_bicgstab;             /* BiCGSTAB iterations of the SGN_BICGSTAB solver (default 50) */
+  int lbfgs_m;                  /* curvature pairs kept by sgn_lbfgs_step (default 5, 0..32) */
 } sgn_options;
 
 typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;
@@ -201,6 +207,53 @@ sgn_status sgn_factor(sgn_ctx ctx, sgn_factor_info* info);
  * by the factor (at most max_gmres cycles).  SGN_E_REFINE if solve_rtol is
  * still not met. */
 sgn_status sgn_solve(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_info* info);
+/* One iteration of L-BFGS whose initial inverse Hessian is the Gauss-Newton one of the current
+ * iterate (Sec. 4, "Combination with L-BFGS"): at the equilibrium (d_p, d_x) the adjoint gradient g
+ * (eq. totalGradient) and K_SGN are assembled and factorised; the pair (s, y) = (p - p_prev,
+ * g - g_prev) of the previous call enters the memory of the newest lbfgs_m pairs when
+ * s^T y > 1e-12 |s| |y|; the two-loop recursion gives d = -H g with H0 q = H_GN^-1 q taken from one
+ * saddle-point solve with right-hand side [0; q; 0]; then the Armijo backtracking of sgn_step along
+ * d.  With no pairs (first call, restart != 0, or lbfgs_m = 0) d is the Gauss-Newton step.  The
+ * memory lives in the workspace and persists across calls; restart != 0 clears it.  Needs solver
+ * SGN_LDLT or SGN_BICGSTAB (SGN_E_STATE otherwise).  info as for sgn_step (grad_norm = |g|). */
+sgn_status sgn_lbfgs_step(sgn_ctx ctx, double* d_p, double* d_x, int restart, sgn_step_info* info);
+/* A batch of n independent problems (the batched form; each problem is the problem statement of
+ * Sec. 3 on its own mesh) as one context: sgn_create of their disjoint union with n_components = n,
+ * each problem's nodes, elements, free DOFs, parameters and targets stored in order, problem by
+ * problem.  The problems must share dim, param_kind, E0, nu, target_w and reg_mu (SGN_E_ARG
+ * otherwise, *out = NULL); the batch takes the largest length_scale of its problems, so each
+ * problem's step is its Gauss-Newton step at that ell.  probs[i]->n_components must be 0 or 1;
+ * NULL target_val / p_ref read as zeros.  Every other call works on the union (x, p, sol of length
+ * n_x, n_p, N of the union, problems in order). */
+sgn_status sgn_batch_create(int n, const sgn_problem* const* probs, const sgn_options* opt, void* stream,
+                            sgn_ctx* out);
+/* One outer iteration for every problem of a batch: d_p[k], d_x[k] (device, problem k's own layout,
+ * an equilibrium on entry) are gathered into the union, the search directions of all problems come
+ * from one assembly, factorisation and solve of the union (the union's K_SGN is block diagonal over
+ * the problems, so each block of the solution is that problem's step), and each problem then takes
+ * its own Armijo backtracking along its direction, f_k(alpha_k) <= f_k(0) + 1e-4 alpha_k g_k^T dp_k,
+ * with the trials of all problems still searching solved together in one union equilibrium per
+ * round (problems already accepted keep their state).  On success every d_p[k], d_x[k] is updated
+ * in place.  info: NULL or an array of n entries (per-problem alpha, f0, f1, gtdp, halvings; shared
+ * timings and solve info).  A problem stationary to working precision stays (alpha = 0, as sgn_step);
+ * SGN_E_LINESEARCH if a problem finds no step (then nothing is written back).  Needs solver SGN_LDLT
+ * or SGN_BICGSTAB and, for contexts not made by sgn_batch_create, log-modulus parameters stored
+ * problem by problem (SGN_E_STATE otherwise). */
+sgn_status sgn_batch_step(sgn_ctx ctx, double* const* d_p, double* const* d_x, sgn_step_info* info);
+/* Block Gauss-Newton direction (Sec. 4 "Block Solve", Appendix B) at the equilibrium (d_x, d_p) into
+ * d_sol ([N], block order [dx; dp; dlam]).  Only for contexts created with solver = SGN_BLOCK_GN, which
+ * sgn_create accepts for rest-position parameters (Kp square), reg_mu = 0 (C = 0; B = 0 always) and
+ * every free DOF a target exactly once (A = (w/ell^2) I invertible).  Then eq. sparseSystemGN reduces
+ * by block substitution to dx = -A^-1 df/dx^T, Kp dp = -Kx dx (the appendix's sign) and, for the
+ * adjoint right-hand side, dlam = Kx^-1 df/dx^T (the KKT form's multiplier block is 0): the same
+ * step as the full solve when Kp is invertible.  K_SGN is assembled at (d_x, d_p) but never
+ * factorised; Kp dp = -Kx dx is solved by restarted GMRES(30) (at most max_gmres cycles, at least
+ * one) to a relative residual of min(1e-12, solve_rtol / 100), right-preconditioned by -Kx^-1 through
+ * the Kx factor (the one sgn_equilibrium left, else a fresh one at this state).  info: sweeps and
+ * gmres_iters = GMRES iterations, rel_res = raw_rel_res = final relative residual of the Kp system.
+ * SGN_E_REFINE if GMRES does not reach it; SGN_E_PIVOT if a fresh Kx is not positive definite.
+ * sgn_step with this solver uses the same direction. */
+sgn_status sgn_block_step(sgn_ctx ctx, const double* d_x, const double* d_p, double* d_sol, sgn_solve_info* info);
 /* One outer iteration: assemble + factor + solve for the step, then
  * backtracking p + alpha dp with one equilibrium per trial and Armijo
  * acceptance f(alpha) <= f(0) + 1e-4 alpha g^T dp.  (d_p, d_x) must be an

@@ -529,3 +529,52 @@ def lbfgs_sgn_iterations(prob: Problem, p: np.ndarray, x: np.ndarray, iters: int
         prev = (p, g)
         p, x = pt, xt
     return trace, p, x
+
+
+def equilibrated_residual_extended(K: sp.spmatrix, z: np.ndarray, b: np.ndarray) -> float:
+    """equilibrated_residual with b - K z accumulated in extended precision (np.longdouble): the residual
+    of z itself, free of the FP64 rounding of its evaluation."""
+    K = sp.csr_matrix(K)
+    r = b.astype(np.longdouble) - np.add.reduceat(K.data.astype(np.longdouble) * z.astype(np.longdouble)[K.indices],
+                                                  K.indptr[:-1])
+    rowmax = abs(K).max(axis=1).toarray().ravel()
+    s = 1.0 / np.sqrt(rowmax)
+    return float(np.linalg.norm(s * r.astype(np.float64)) / np.linalg.norm(s * b))
+
+
+def refine_extended(K: sp.spmatrix, b: np.ndarray, z0: np.ndarray, sweeps: int = 3):
+    """Iterative refinement with residuals in extended precision (Wilkinson; np.longdouble, 64-bit
+    mantissa on x86): z <- z + M^-1 (b - K z) with M^-1 a sparse LU (SuperLU) of the symmetrically
+    equilibrated K in FP64 and the residual b - K z accumulated in extended precision, so the
+    iteration converges (when cond(K) u_64 < 1) to the exact solution within u_64 + cond(K) u_ext in
+    the forward error, not merely to a small residual.  Returns (z, [equilibrated residual before and
+    after every sweep])."""
+    import scipy.sparse.linalg as spla
+    K = sp.csr_matrix(K)
+    rowmax = abs(K).max(axis=1).toarray().ravel()
+    s = 1.0 / np.sqrt(rowmax)
+    lu = spla.splu((sp.diags(s) @ K @ sp.diags(s)).tocsc())
+    data = K.data.astype(np.longdouble)
+    bl = b.astype(np.longdouble)
+
+    def residual(z):
+        prod = data * z.astype(np.longdouble)[K.indices]
+        return bl - np.add.reduceat(prod, K.indptr[:-1])
+
+    z = z0.copy()
+    hist = [equilibrated_residual(K, z, b)]
+    for _ in range(sweeps):
+        r = residual(z).astype(np.float64)
+        z = z + s * lu.solve(s * r)
+        hist.append(equilibrated_residual(K, z, b))
+    return z, hist
+
+
+def polish_sgn_solution(prob: Problem, x: np.ndarray, p: np.ndarray, z0: np.ndarray, b: np.ndarray,
+                        sweeps: int = 3):
+    """The solution of eq. sparseSystemGN refined from z0 (e.g. the dense Gauss-Newton step, the same
+    solution by Theorem 1) with extended-precision residuals (refine_extended).  The dense step forms
+    H = S^T A S + C explicitly and rounds at the level of cond(Kx) u in S (at the 40 x 10 x 10 size
+    its equilibrated residual in the saddle-point system is about 3e-11); the refined one is the
+    saddle-point solution to FP64 accuracy."""
+    return refine_extended(sgn_matrix_sparse(prob, x, p), b, z0, sweeps)

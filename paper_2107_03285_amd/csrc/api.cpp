@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -197,6 +198,26 @@ struct sgn_ctx_s {
   const float* corr_par = nullptr;
   bool kx_valid = false;
   bool sgn_assembled = false;
+  // L-BFGS memory (sgn_lbfgs_step): newest pair at lb_head - 1 (circular), curvature 1 / s^T y
+  double* lb_s = nullptr;             // [lbfgs_m x n_p]
+  double* lb_y = nullptr;             // [lbfgs_m x n_p]
+  double* lb_pprev = nullptr;         // [n_p] parameters and gradient of the previous iterate
+  double* lb_gprev = nullptr;
+  double* lb_q = nullptr;             // [n_p] two-loop vectors
+  double* lb_r = nullptr;
+  std::vector<double> lb_rho;
+  int lb_count = 0, lb_head = 0;
+  bool lb_have_prev = false;
+  // batches (n_components problems): contiguous ranges of each problem's free DOFs and parameters
+  // (sgn_batch_step needs the parameters stored problem by problem: batch_ok)
+  int ncomp = 1;
+  bool batch_ok = false;
+  std::vector<int64_t> seg_x, seg_p;
+  int64_t* d_seg_x = nullptr;
+  int64_t* d_seg_p = nullptr;
+  double* d_seg_val = nullptr;        // [4 x ncomp] per-problem reductions
+  double* d_seg_alpha = nullptr;      // [ncomp] per-problem step lengths
+  int32_t* d_seg_mask = nullptr;      // [ncomp]
   size_t ws_need = 0;  // workspace bytes, fixed at create (layout() with a null base resets pointers)
   sgn_stats stats{};
   std::vector<hipEvent_t> ev_pool;  // per-launch timing events (profile = 1)
@@ -413,6 +434,20 @@ size_t layout(sgn_ctx c, char* base) {
   c->d_rt = L.take<double>(nt);
   c->d_srhs = L.take<double>(A.sgn.N);
   c->d_ssol = L.take<double>(A.sgn.N);
+  {
+    const int64_t m = std::max(0, c->opt.lbfgs_m);
+    c->lb_s = L.take<double>(m * np);
+    c->lb_y = L.take<double>(m * np);
+    c->lb_pprev = L.take<double>(np);
+    c->lb_gprev = L.take<double>(np);
+    c->lb_q = L.take<double>(np);
+    c->lb_r = L.take<double>(np);
+  }
+  c->d_seg_x = L.take<int64_t>(c->ncomp + 1);
+  c->d_seg_p = L.take<int64_t>(c->ncomp + 1);
+  c->d_seg_val = L.take<double>(4 * (int64_t)c->ncomp);
+  c->d_seg_alpha = L.take<double>(c->ncomp);
+  c->d_seg_mask = L.take<int32_t>(c->ncomp);
   c->d_part = L.take<double>(4 * kRedBlocks);
   c->d_scal = L.take<double>(64);
   c->d_gm = L.take<double>(256);
@@ -428,6 +463,23 @@ hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ reductions
+// Forget the captured step graph: its nodes hold the workspace addresses and the objective
+// weights (target values are read through a pointer, ell and mu by value) of the time of capture.
+sgn_status drop_graph(sgn_ctx c) {
+  hipError_t e = hipSuccess;
+  if (c->graph_exec) e = hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) {
+    const hipError_t e2 = hipGraphDestroy(c->graph);
+    if (e == hipSuccess) e = e2;
+  }
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  std::fill(c->graph_key, c->graph_key + 4, nullptr);
+  c->graph_nir = -1;
+  if (e != hipSuccess) return fail(c, SGN_E_HIP, std::string("graph destroy: ") + hipGetErrorString(e));
+  return SGN_OK;
+}
+
 sgn_status read_scalars(sgn_ctx c, int first, int n, double* out) {
   HIPCHK(hipMemcpyAsync(out, c->d_scal + first, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -940,6 +992,158 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
   return SGN_OK;
 }
 
+// BiCGSTAB (van der Vorst 1992) on the saddle-point system K z = b, right-preconditioned by the
+// stored factor, which is the LDL^T of the stabilised matrix K_eps = K + diag(eps_x 1, 0, -eps_lambda 1)
+// (Sec. 5, "Solving the saddle point problem"; the assembled values hold K_eps, and products with K
+// subtract the stabilisation diagonal again).  It runs on the equilibrated system (S K S) u = S b,
+// z = S u, where the factor's sweeps without their scaling are the preconditioner (S K_eps S)^-1, so
+// the recursive residual is the equilibrated residual the tolerance is stated in.  Restarts from
+// the true residual whenever the recursion claims convergence that the true residual does not
+// confirm, or when the recurrence breaks down.  b_new, z_new as for refined_solve.
+sgn_status bicgstab_solve(sgn_ctx c, const double* b_new, double* z_new, sgn_solve_info* info) {
+  const System& S = c->A.sgn;
+  DevSys& D = c->sys[0];
+  const int64_t N = S.N;
+  hipStream_t st = c->stream;
+  const double t0 = now_ms();
+  const double ex = c->opt.eps_x, el = c->opt.eps_lambda;
+  double* r = D.gm_V;  // work vectors: the FGMRES bases are not in use during this solve
+  double* rt = r + N;
+  double* p = rt + N;
+  double* v = p + N;
+  double* sv = v + N;
+  double* t = sv + N;
+  double* y = t + N;
+  double* zh = y + N;
+  double* u = zh + N;
+  double* tmp = u + N;
+  // out = S K S w (K unstabilised)
+  auto matvec = [&](const double* w, double* out) {
+    scale_vec(c, N, D.scale, w, tmp);
+    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, tmp, out, st);
+    if (ex != 0.0 || el != 0.0) launch_unstabilise(N, D.diag_kind, ex, el, -1.0, tmp, out, st);
+    scale_vec(c, N, D.scale, out, out);
+  };
+  // out = (S K_eps S)^-1 w by the factor's sweeps
+  auto precond = [&](const double* w, double* out) -> sgn_status {
+    TRY(fwd_sweep(c, 0, w));
+    return bwd_sweep(c, 0, out, nullptr);
+  };
+  // true equilibrated residual r = S b - S K S u, its squared norm into slot 40
+  auto true_residual = [&]() {
+    matvec(u, r);
+    scale_vec(c, N, D.scale, b_new, tmp);
+    launch_axpby(N, 1.0, tmp, -1.0, r, r, st);
+    dev_dot(c, N, r, r, 40);
+  };
+  launch_fill_i32(1, 0, c->d_cnt + 12, st);
+  launch_fill(N, 0.0, u, st);
+  scale_vec(c, N, D.scale, b_new, tmp);
+  dev_dot(c, N, tmp, tmp, 41);
+  dev_dot(c, N, b_new, b_new, 42);
+  double hb[2];
+  TRY(read_scalars(c, 41, 2, hb));
+  const double sb = std::sqrt(hb[0]), rb = std::sqrt(hb[1]);
+  const double tol = c->opt.solve_rtol * sb;
+  const int max_it = std::max(1, c->opt.max_bicgstab);
+  int it = 0;
+  double rel = 1.0;
+  HIPCHK(hipMemcpyAsync(r, tmp, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double rn = sb;
+  while (sb > 0.0 && it < max_it) {
+    // (re)start from the current residual r
+    HIPCHK(hipMemcpyAsync(rt, r, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_fill(N, 0.0, p, st);
+    launch_fill(N, 0.0, v, st);
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    bool claimed = false;
+    while (it < max_it) {
+      dev_dot(c, N, rt, r, 43);
+      double rho;
+      TRY(read_scalars(c, 43, 1, &rho));
+      if (!(std::fabs(rho) > 0.0)) break;  // breakdown: restart from the true residual
+      const double beta = (rho / rho_prev) * (alpha / omega);
+      launch_axpby(N, 1.0, p, -omega, v, p, st);  // p = r + beta (p - omega v)
+      launch_axpby(N, 1.0, r, beta, p, p, st);
+      TRY(precond(p, y));
+      matvec(y, v);
+      dev_dot(c, N, rt, v, 44);
+      double rv;
+      TRY(read_scalars(c, 44, 1, &rv));
+      ++it;
+      if (!(std::fabs(rv) > 0.0)) break;
+      alpha = rho / rv;
+      launch_axpby(N, 1.0, r, -alpha, v, sv, st);  // s = r - alpha v
+      dev_dot(c, N, sv, sv, 45);
+      double ss;
+      TRY(read_scalars(c, 45, 1, &ss));
+      if (std::sqrt(std::max(ss, 0.0)) <= tol) {
+        launch_axpby(N, 1.0, u, alpha, y, u, st);
+        claimed = true;
+        break;
+      }
+      TRY(precond(sv, zh));
+      matvec(zh, t);
+      dev_dot(c, N, t, sv, 46);
+      dev_dot(c, N, t, t, 47);
+      double ts[2];
+      TRY(read_scalars(c, 46, 2, ts));
+      if (!(ts[1] > 0.0)) break;
+      omega = ts[0] / ts[1];
+      launch_axpby(N, 1.0, u, alpha, y, u, st);  // u += alpha y + omega zh
+      launch_axpby(N, 1.0, u, omega, zh, u, st);
+      launch_axpby(N, 1.0, sv, -omega, t, r, st);  // r = s - omega t
+      dev_dot(c, N, r, r, 45);
+      double r2;
+      TRY(read_scalars(c, 45, 1, &r2));
+      rn = std::sqrt(std::max(r2, 0.0));
+      if (rn <= tol) {
+        claimed = true;
+        break;
+      }
+      if (!(omega != 0.0)) break;
+      rho_prev = rho;
+    }
+    true_residual();
+    double r2;
+    TRY(read_scalars(c, 40, 1, &r2));
+    rn = std::sqrt(std::max(r2, 0.0));
+    rel = rn / sb;
+    if (rn <= tol) break;
+    (void)claimed;  // not confirmed by the true residual: restart from it
+  }
+  if (sb == 0.0) rel = 0.0;
+  scale_vec(c, N, D.scale, u, z_new);
+  // raw residual |b - K z| / |b| for the report
+  launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, z_new, b_new, D.ir_r, st);
+  if (ex != 0.0 || el != 0.0) launch_unstabilise(N, D.diag_kind, ex, el, 1.0, z_new, D.ir_r, st);
+  dev_dot(c, N, D.ir_r, D.ir_r, 41);
+  double raw2;
+  TRY(read_scalars(c, 41, 1, &raw2));
+  int timeout = 0;
+  HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (timeout) {
+    c->err = "a pipelined triangular solve timed out waiting for a panel";
+    return SGN_E_HIP;
+  }
+  if (info) {
+    info->sweeps = it;
+    info->fallback = 0;
+    info->rel_res = rel;
+    info->raw_rel_res = rb > 0 ? std::sqrt(std::max(raw2, 0.0)) / rb : 0.0;
+    info->ms = now_ms() - t0;
+    info->gmres_iters = 0;
+  }
+  if (!(rel <= c->opt.solve_rtol)) {
+    char buf[96];
+    snprintf(buf, sizeof(buf), "BiCGSTAB stopped at equilibrated relative residual %.3e", rel);
+    c->err = buf;
+    return SGN_E_REFINE;
+  }
+  return SGN_OK;
+}
+
 // Preconditioned MINRES on the assembled SGN matrix (new order, unscaled), with the
 // node-block preconditioner of the reference factor.  The iterate minimises the
 // M^-1-norm of the residual over the Krylov space (Lanczos three-term recurrence with
@@ -1268,6 +1472,274 @@ sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rh
   return SGN_OK;
 }
 
+// ------------------------------------------------------------------ block Gauss-Newton
+// y = K_SGN v for vectors in boundary (block) order, with the currently assembled values
+void sgn_matvec_boundary(sgn_ctx c, const double* v_old, double* y_old) {
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  launch_gather_perm(N, D.perm, nullptr, v_old, D.t, c->stream);
+  launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, D.t, D.r, c->stream);
+  launch_scatter_perm(N, D.perm, nullptr, D.r, y_old, c->stream);
+}
+
+// Right-preconditioned restarted GMRES(m) (Saad and Schultz) for A u = b on length-n vectors in
+// FP64: u += P (V y) with V an orthonormal basis of the Krylov space of A P built by two passes of
+// classical Gram-Schmidt (device dot products, one read-back per step) and y from the Givens-reduced
+// least-squares problem on the host.  Cycles restart from the true residual until
+// |b - A u| <= rtol |b| or max_cycles.  V holds (m + 1) n, w1 and w2 n each.
+sgn_status gmres_right(sgn_ctx c, int64_t n, const std::function<sgn_status(const double*, double*)>& Aop,
+                       const std::function<sgn_status(const double*, double*)>& Pop, const double* b, double* u,
+                       double rtol, int m, int max_cycles, double* V, double* w1, double* w2, int* iters,
+                       double* rel_out) {
+  hipStream_t st = c->stream;
+  dev_dot(c, n, b, b, 48);
+  double b2;
+  TRY(read_scalars(c, 48, 1, &b2));
+  const double bn = std::sqrt(std::max(b2, 0.0));
+  *iters = 0;
+  *rel_out = 0.0;
+  if (bn == 0.0) {
+    launch_fill(n, 0.0, u, st);
+    return SGN_OK;
+  }
+  const double stop = rtol * bn;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hb(2 * 64 + 1), y(m);
+  auto h = [&](int i, int j) -> double& { return H[(size_t)j * (m + 1) + i]; };
+  for (int cycle = 0; cycle < max_cycles; ++cycle) {
+    TRY(Aop(u, w1));
+    launch_axpby(n, 1.0, b, -1.0, w1, V, st);  // r = b - A u
+    dev_dot(c, n, V, V, 48);
+    double r2;
+    TRY(read_scalars(c, 48, 1, &r2));
+    const double beta = std::sqrt(std::max(r2, 0.0));
+    *rel_out = beta / bn;
+    if (beta <= stop) return SGN_OK;
+    launch_axpby(n, 1.0 / beta, V, 0.0, nullptr, V, st);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    while (k < m) {
+      const int j = k;
+      double* vj = V + (int64_t)j * n;
+      double* vn = V + (int64_t)(j + 1) * n;
+      TRY(Pop(vj, w2));
+      TRY(Aop(w2, vn));
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i <= j; ++i) dev_dot_to(c, n, V + (int64_t)i * n, vn, c->d_gm + 64 * pass + i);
+        launch_multi_axpy(n, j + 1, V, n, c->d_gm + 64 * pass, -1.0, vn, st);
+      }
+      dev_dot_to(c, n, vn, vn, c->d_gm + 128);
+      HIPCHK(hipMemcpyAsync(hb.data(), c->d_gm, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) h(i, j) = hb[i] + hb[64 + i];
+      const double hn = std::sqrt(std::max(hb[128], 0.0));
+      h(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = h(i, j), bb = h(i + 1, j);
+        h(i, j) = cs[i] * a + sn[i] * bb;
+        h(i + 1, j) = -sn[i] * a + cs[i] * bb;
+      }
+      const double den = std::hypot(h(j, j), h(j + 1, j));
+      if (!(den > 0.0)) break;
+      cs[j] = h(j, j) / den;
+      sn[j] = h(j + 1, j) / den;
+      h(j, j) = den;
+      h(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      ++*iters;
+      if (std::fabs(g[j + 1]) <= 0.5 * stop || !(hn > 0.0)) break;
+      launch_axpby(n, 1.0 / hn, vn, 0.0, nullptr, vn, st);
+    }
+    if (k == 0) break;
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int l = i + 1; l < k; ++l) t -= h(i, l) * y[l];
+      y[i] = t / h(i, i);
+    }
+    HIPCHK(hipMemcpyAsync(c->d_gm + 192, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_fill(n, 0.0, w1, st);
+    launch_multi_axpy(n, k, V, n, c->d_gm + 192, 1.0, w1, st);
+    TRY(Pop(w1, w2));
+    launch_axpby(n, 1.0, u, 1.0, w2, u, st);
+    HIPCHK(hipStreamSynchronize(st));  // y is read by the copy above
+  }
+  TRY(Aop(u, w1));
+  launch_axpby(n, 1.0, b, -1.0, w1, w1, st);
+  dev_dot(c, n, w1, w1, 48);
+  double r2;
+  TRY(read_scalars(c, 48, 1, &r2));
+  *rel_out = std::sqrt(std::max(r2, 0.0)) / bn;
+  return SGN_OK;
+}
+
+// Block Gauss-Newton direction (Sec. 4 "Block Solve", Appendix B) at (x, p) with K_SGN assembled
+// there and df/dx^T in c->d_fx:  dx = -A^-1 df/dx^T (A = (w / ell^2) I on every free DOF),
+// dp = -Kp^-1 Kx dx (the appendix's sign), dlam = Kx^-1 df/dx^T (adjoint right-hand side; the KKT
+// form's multiplier is dlam + lam_adj = 0).  Kp is never factorised: Kp dp = -Kx dx is solved by
+// GMRES right-preconditioned with -Kx^-1 through the Kx factor (for rest-position parameters Kp =
+// -Kx up to terms of the order of the strain, so few iterations suffice); the products with Kx and
+// Kp come from the assembled K_SGN.  sol: [N] boundary order.
+sgn_status bgn_solve_assembled(sgn_ctx c, const double* x, const double* p, double* sol, sgn_solve_info* info) {
+  const Analysis& A = c->A;
+  const int64_t nx = A.mesh.n_x, np = A.mesh.n_p, N = A.sgn.N;
+  hipStream_t st = c->stream;
+  const double t0 = now_ms();
+  DevSys& K = c->sys[1];
+  if (!c->kx_valid) {  // the Kx factor at (x, p): the element buffer holds this state's derivatives
+    assemble_kx(c, 0.0);
+    TRY(factor_dispatch(c, 1, 1e-300, nullptr));
+    if (c->sys[1].inertia[0] != nx) return fail(c, SGN_E_PIVOT, "Kx is not positive definite at this state");
+    c->kx_valid = true;
+  }
+  const double a = c->target_w / (c->ell * c->ell);
+  double* dx = sol;
+  double* dp = sol + nx;
+  double* dl = sol + nx + np;
+  launch_axpby(nx, -1.0 / a, c->d_fx, 0.0, nullptr, dx, st);
+  double* e = c->d_old;
+  double* ke = c->d_old2;
+  // rhs of the Kp system: v = -Kx dx, the x block of K [0; 0; dx] (Kx symmetric)
+  launch_fill(N, 0.0, e, st);
+  HIPCHK(hipMemcpyAsync(e + nx + np, dx, nx * sizeof(double), hipMemcpyDeviceToDevice, st));
+  sgn_matvec_boundary(c, e, ke);
+  double* V = c->sys[0].gm_V;  // (31) x nx fits the SGN system's FGMRES basis (31 x N)
+  double* w1 = c->sys[0].gm_Z;
+  double* w2 = w1 + nx;
+  double* v = w2 + nx;
+  launch_axpby(nx, -1.0, ke, 0.0, nullptr, v, st);
+  // Kp u: the multiplier block of K [0; u; 0]
+  auto Kp = [&](const double* u, double* out) -> sgn_status {
+    launch_fill(N, 0.0, e, st);
+    HIPCHK(hipMemcpyAsync(e + nx, u, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+    sgn_matvec_boundary(c, e, ke);
+    HIPCHK(hipMemcpyAsync(out, ke + nx + np, nx * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return SGN_OK;
+  };
+  // -Kx^-1 u by the Kx factor's sweeps
+  auto prec = [&](const double* u, double* out) -> sgn_status {
+    launch_gather_perm(nx, K.perm, nullptr, u, K.b, st);
+    TRY(solve_once(c, 1, K.b, K.z));
+    launch_scatter_perm(nx, K.perm, nullptr, K.z, out, st);
+    launch_axpby(nx, -1.0, out, 0.0, nullptr, out, st);
+    return SGN_OK;
+  };
+  launch_fill_i32(1, 0, c->d_cnt + 12, st);
+  launch_fill(np, 0.0, dp, st);
+  int its = 0;
+  double rel = 0.0;
+  const double rtol = std::min(1e-12, 1e-2 * c->opt.solve_rtol);
+  TRY(gmres_right(c, nx, Kp, prec, v, dp, rtol, kGmresM, std::max(1, c->opt.max_gmres), V, w1, w2, &its, &rel));
+  if (c->opt.rhs_kind == SGN_RHS_KKT) {
+    launch_fill(nx, 0.0, dl, st);
+  } else {  // dlam = Kx^-1 df/dx^T, refined on the Kx system
+    launch_gather_perm(nx, K.perm, nullptr, c->d_fx, K.b, st);
+    const double keep = c->opt.solve_rtol;
+    c->opt.solve_rtol = 1e-14;
+    sgn_solve_info si{};
+    const sgn_status s = refined_solve(c, 1, K.b, K.z, &si);
+    c->opt.solve_rtol = keep;
+    if (s != SGN_OK && s != SGN_E_REFINE) return s;
+    launch_scatter_perm(nx, K.perm, nullptr, K.z, dl, st);
+  }
+  int timeout = 0;
+  HIPCHK(hipMemcpyAsync(&timeout, c->d_cnt + 12, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (timeout) return fail(c, SGN_E_HIP, "a pipelined triangular solve timed out waiting for a panel");
+  if (info) {
+    info->sweeps = its;
+    info->fallback = 0;
+    info->rel_res = rel;
+    info->raw_rel_res = rel;
+    info->ms = now_ms() - t0;
+    info->gmres_iters = its;
+  }
+  c->stats.solve_ms = now_ms() - t0;
+  if (!(rel <= rtol)) {
+    char buf[96];
+    snprintf(buf, sizeof(buf), "block solve: GMRES on Kp stopped at relative residual %.3e", rel);
+    return fail(c, SGN_E_REFINE, buf);
+  }
+  return SGN_OK;
+}
+
+// Backtracking along dir from the equilibrium (d_p, d_x) with one equilibrium per trial and Armijo
+// acceptance f(alpha) <= f(0) + 1e-4 alpha g^T dir (si->f0, si->gtdp set by the caller); on success
+// (d_p, d_x) move to the accepted trial.  t_start: host time the search began (ms_linesearch).
+sgn_status line_search(sgn_ctx c, double* d_p, double* d_x, const double* dir, double t_start, sgn_step_info* si,
+                       sgn_step_info* info) {
+  const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p;
+  const double f0 = si->f0, gtdp = si->gtdp;
+  double alpha = 1.0;
+  bool ok = false;
+  int nt_iters = 0;
+  for (int h = 0; h <= c->opt.max_halvings; ++h) {
+    launch_axpby(np, 1.0, d_p, alpha, dir, c->d_pt, c->stream);
+    HIPCHK(hipMemcpyAsync(c->d_xt, d_x, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    sgn_eq_info ei{};
+    sgn_status s = equilibrium_impl(c, c->d_pt, c->d_xt, &ei);
+    if (s == SGN_OK) {
+      nt_iters += ei.iters;
+      double f1;
+      TRY(objective_value(c, c->d_xt, c->d_pt, &f1));
+      if (f1 <= f0 + 1e-4 * alpha * gtdp) {
+        si->f1 = f1;
+        ok = true;
+        break;
+      }
+    } else if (s == SGN_E_HIP) {
+      return fail(c, s, c->err);
+    }
+    alpha *= 0.5;
+    ++si->halvings;
+  }
+  si->ms_linesearch = now_ms() - t_start;
+  si->newton_iters = nt_iters;
+  if (!ok && std::fabs(gtdp) <= 1e-12 * std::fabs(f0)) {
+    // the predicted decrease of the whole step is below the objective's rounding: the iterate is
+    // stationary to working precision and Armijo decisions are noise; stay (alpha = 0)
+    si->alpha = 0.0;
+    si->f1 = f0;
+    c->kx_valid = false;  // the Kx factor and values belong to the last trial, not to d_p
+    if (info) *info = *si;
+    return SGN_OK;
+  }
+  si->alpha = alpha;
+  if (info) *info = *si;
+  if (!ok) {
+    c->kx_valid = false;
+    return fail(c, SGN_E_LINESEARCH, "line search failed");
+  }
+  HIPCHK(hipMemcpyAsync(d_p, c->d_pt, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d_x, c->d_xt, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return SGN_OK;
+}
+
+// Objective of every problem of a batch at the union state (x, p) into h_f[ncomp]:
+// f_k = w/(2 ell^2) sum over k's targets (x - t)^2 + mu/2 sum over k's parameters (p - p_ref)^2.
+// Uses c->d_old as scratch.
+sgn_status batch_objectives(sgn_ctx c, const double* x, const double* p, double* h_f) {
+  const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p;
+  const int nc = c->ncomp;
+  hipStream_t st = c->stream;
+  double* rx = c->d_old;
+  double* rp = c->d_old + nx;
+  launch_fill(nx, 0.0, rx, st);
+  launch_objective_fx((int64_t)c->target_dof.size(), c->d_tdof, c->d_tval, x, 1.0, rx, st);  // x_T - t
+  launch_axpby(np, 1.0, p, -1.0, c->d_pref, rp, st);
+  launch_segment_dot(nc, c->d_seg_x, rx, rx, c->d_seg_val, st);
+  launch_segment_dot(nc, c->d_seg_p, rp, rp, c->d_seg_val + nc, st);
+  std::vector<double> v(2 * (size_t)nc);
+  HIPCHK(hipMemcpyAsync(v.data(), c->d_seg_val, v.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double wl = c->target_w / (c->ell * c->ell);
+  for (int k = 0; k < nc; ++k) h_f[k] = 0.5 * wl * v[k] + 0.5 * c->mu_reg * v[nc + k];
+  return SGN_OK;
+}
+
 sgn_status check_ready(sgn_ctx c) {
   if (!c) return SGN_E_ARG;
   if (c->sticky) return SGN_E_STATE;
@@ -1300,7 +1772,8 @@ sgn_status sgn_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_i
   launch_gather_perm(N, D.perm, nullptr, rhs, c->d_old2, c->stream);
   double* zn = c->d_old;  // new-order solution
   const double t0 = now_ms();
-  sgn_status s = refined_solve(c, 0, c->d_old2, zn, info);
+  sgn_status s = c->opt.solver == SGN_BICGSTAB ? bicgstab_solve(c, c->d_old2, zn, info)
+                                               : refined_solve(c, 0, c->d_old2, zn, info);
   launch_scatter_perm(N, D.perm, nullptr, zn, sol, c->stream);
   HIPCHK(hipStreamSynchronize(c->stream));
   c->stats.solve_ms = now_ms() - t0;
@@ -1666,6 +2139,8 @@ void sgn_default_options(sgn_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = SGN_FP64;
   o->solver = SGN_LDLT;
+  o->max_bicgstab = 50;
+  o->lbfgs_m = 5;
   o->rhs_kind = SGN_RHS_ADJOINT;
   o->newton_rtol = 1e-10;
   o->newton_atol = 0.0;
@@ -1733,6 +2208,12 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
   }
   if (c->opt.seq_panels < -1 || c->opt.seq_panels > kSolveSeqPanels)
     return fail(c, SGN_E_ARG, "seq_panels must be -1..8 (0: default)");
+  if (c->opt.solver < SGN_LDLT || c->opt.solver > SGN_BLOCK_GN) return fail(c, SGN_E_ARG, "unknown solver");
+  if (c->opt.lbfgs_m < 0 || c->opt.lbfgs_m > 32) return fail(c, SGN_E_ARG, "lbfgs_m must be 0..32");
+  c->lb_rho.assign(std::max(1, c->opt.lbfgs_m), 0.0);
+  if (c->opt.solver == SGN_BICGSTAB && c->opt.max_bicgstab < 1)
+    return fail(c, SGN_E_ARG, "max_bicgstab must be at least 1");
+  if (!(c->opt.eps_x >= 0.0) || !(c->opt.eps_lambda >= 0.0)) return fail(c, SGN_E_ARG, "eps_x, eps_lambda must be >= 0");
   c->A.tune.seq_panels = c->opt.seq_panels == 0 ? kSolveSeqPanels : (c->opt.seq_panels < 0 ? 0 : c->opt.seq_panels);
   std::string err = analyse(c->A);
   if (!err.empty()) return fail(c, SGN_E_ARG, "symbolic analysis: " + err);
@@ -1763,10 +2244,49 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
   c->fext_norm = std::sqrt(fn);
   c->efdof.resize((size_t)m.n_elems * nv);
   for (size_t k = 0; k < c->efdof.size(); ++k) c->efdof[k] = m.fdof[m.elems[k]];
+  {
+    // per-problem ranges of a batch: free DOFs follow the node order, so each component's are
+    // contiguous; log-modulus parameters must be stored problem by problem for sgn_batch_step
+    const int nc = (int)m.comp_ptr.size() - 1;
+    c->ncomp = nc;
+    std::vector<int32_t> comp(m.n_nodes);
+    for (int k = 0; k < nc; ++k)
+      for (int v = m.comp_ptr[k]; v < m.comp_ptr[k + 1]; ++v) comp[v] = k;
+    c->seg_x.assign(nc + 1, 0);
+    for (int v = 0; v < m.n_nodes; ++v)
+      if (m.fdof[v] >= 0) c->seg_x[comp[v] + 1] += d;
+    for (int k = 0; k < nc; ++k) c->seg_x[k + 1] += c->seg_x[k];
+    bool ok = true;
+    if (m.param_kind == SGN_P_LOGE) {
+      c->seg_p.assign(nc + 1, 0);
+      int prev = 0;
+      for (int e = 0; e < m.n_elems; ++e) {
+        const int k = comp[m.elems[(size_t)e * nv]];
+        if (k < prev) ok = false;
+        prev = k;
+        c->seg_p[k + 1] += 1;
+      }
+      for (int k = 0; k < nc; ++k) c->seg_p[k + 1] += c->seg_p[k];
+    } else {
+      c->seg_p = c->seg_x;
+    }
+    c->batch_ok = ok && nc <= 65535;
+  }
   // target flags on the SGN diagonal
   {
     System& S = c->A.sgn;
     for (int32_t t : c->target_dof) S.diag_kind[S.iperm[t]] = 1;
+  }
+  if (c->opt.solver == SGN_BLOCK_GN) {
+    // Sec. 4 "Block Solve": no direct parameter term (C = 0; B = 0 always here), a square Kp
+    // (rest-position parameters) and an invertible A (every free DOF a target)
+    if (m.param_kind != SGN_P_REST_POS) return fail(c, SGN_E_ARG, "block solve needs rest-position parameters");
+    if (c->mu_in != 0.0) return fail(c, SGN_E_ARG, "block solve needs reg_mu = 0 (C = 0)");
+    std::vector<char> hit(nx, 0);
+    for (int32_t t : c->target_dof) hit[t] = 1;
+    if ((int64_t)c->target_dof.size() != nx || std::count(hit.begin(), hit.end(), 1) != nx)
+      return fail(c, SGN_E_ARG, "block solve needs every free DOF to be a target once (A invertible)");
+    if (!(c->target_w > 0)) return fail(c, SGN_E_ARG, "block solve needs target_w > 0");
   }
   c->ws_need = layout(c, nullptr);
   return SGN_OK;
@@ -1785,6 +2305,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
   if (((uintptr_t)d_ws & 255) != 0) return fail(c, SGN_E_ARG, "workspace must be 256-byte aligned");
   const size_t need = c->ws_need;
   if (bytes < need) return fail(c, SGN_E_NOMEM, "workspace too small");
+  TRY(drop_graph(c));  // a graph captured on the previous workspace must never replay
   layout(c, reinterpret_cast<char*>(d_ws));
   const Analysis& A = c->A;
   hipStream_t st = c->stream;
@@ -1860,6 +2381,8 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
   HIPCHK(up(c->d_tdof, c->target_dof, st));
   HIPCHK(up(c->d_tval, c->target_val, st));
   HIPCHK(up(c->d_pref, c->p_ref, st));
+  HIPCHK(up(c->d_seg_x, c->seg_x, st));
+  HIPCHK(up(c->d_seg_p, c->seg_p, st));
   HIPCHK(hipStreamSynchronize(st));
   c->has_ws = true;
   return SGN_OK;
@@ -1868,6 +2391,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
 sgn_status sgn_set_targets(sgn_ctx c, const double* h_tval, double ell) {
   TRY(check_ready(c));
   if (!h_tval || !(ell > 0)) return fail(c, SGN_E_ARG, "targets");
+  TRY(drop_graph(c));  // the captured right-hand side holds ell and mu by value
   c->target_val.assign(h_tval, h_tval + c->target_dof.size());
   c->ell = ell;
   c->mu_reg = c->A.mesh.param_kind == SGN_P_REST_POS ? c->mu_in / (ell * ell) : c->mu_in;
@@ -1893,6 +2417,19 @@ sgn_status sgn_assemble(sgn_ctx c, const double* d_x, const double* d_p, double*
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail(c, SGN_E_HIP, hipGetErrorString(e));
   return SGN_OK;
+}
+
+sgn_status sgn_block_step(sgn_ctx c, const double* d_x, const double* d_p, double* d_sol, sgn_solve_info* info) {
+  TRY(check_ready(c));
+  if (!d_x || !d_p || !d_sol) return fail(c, SGN_E_ARG, "null vector");
+  if (c->opt.solver != SGN_BLOCK_GN) return fail(c, SGN_E_STATE, "the context was not created with SGN_BLOCK_GN");
+  sgn_status s = assemble_impl(c, d_x, d_p, nullptr, nullptr, nullptr);
+  if (s != SGN_OK) return fail(c, s, c->err);
+  const int64_t nx = c->A.mesh.n_x;
+  launch_fill(nx, 0.0, c->d_fx, c->stream);
+  launch_objective_fx((int64_t)c->target_dof.size(), c->d_tdof, c->d_tval, d_x, c->target_w / (c->ell * c->ell),
+                      c->d_fx, c->stream);
+  return bgn_solve_assembled(c, d_x, d_p, d_sol, info);
 }
 
 sgn_status sgn_factor(sgn_ctx c, sgn_factor_info* info) {
@@ -1931,14 +2468,17 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   if (c->opt.solver == SGN_MINRES_LEARNED) {
     sgn_status s = minres_solve_impl(c, rhs, sol, &si.solve);
     if (s != SGN_OK) return s;
-  } else {
+  } else if (c->opt.solver != SGN_BLOCK_GN) {
     sgn_factor_info fi{};
     sgn_status s = sgn_factor_impl(c, &fi);
     if (s != SGN_OK) return s;
   }
   double t2 = now_ms();
   si.ms_factor = t2 - t1;
-  if (c->opt.solver != SGN_MINRES_LEARNED) {
+  if (c->opt.solver == SGN_BLOCK_GN) {
+    sgn_status s = bgn_solve_assembled(c, d_x, d_p, sol, &si.solve);
+    if (s != SGN_OK) return s;
+  } else if (c->opt.solver != SGN_MINRES_LEARNED) {
     sgn_status s = sgn_solve_impl(c, rhs, sol, &si.solve);
     if (s != SGN_OK) return s;
   }
@@ -1964,49 +2504,330 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   si.grad_norm = v[1] >= 0.0 ? std::sqrt(v[1]) : -1.0;
   si.gtdp = gtdp;
   si.f0 = f0;
-  // backtracking with one equilibrium per trial
-  double alpha = 1.0;
-  bool ok = false;
+  return line_search(c, d_p, d_x, sol + nx, t3, &si, info);
+}
+
+sgn_status sgn_lbfgs_step(sgn_ctx c, double* d_p, double* d_x, int restart, sgn_step_info* info) {
+  TRY(check_ready(c));
+  if (!d_p || !d_x) return fail(c, SGN_E_ARG, "null state");
+  if (c->opt.solver != SGN_LDLT && c->opt.solver != SGN_BICGSTAB)
+    return fail(c, SGN_E_STATE, "L-BFGS applies its initial inverse Hessian by the direct solve (SGN_LDLT or SGN_BICGSTAB)");
+  const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p, N = c->A.sgn.N;
+  const int m = c->opt.lbfgs_m;
+  hipStream_t st = c->stream;
+  if (restart) {
+    c->lb_count = 0;
+    c->lb_head = 0;
+    c->lb_have_prev = false;
+  }
+  sgn_step_info si{};
+  const double t0 = now_ms();
+  if (!c->kx_valid) {
+    sgn_status s = equilibrium_impl(c, d_p, d_x, nullptr);
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  // gradient g (adjoint form, eq. totalGradient) and K_SGN at the iterate
+  double f0 = 0;
+  {
+    const int keep = c->opt.rhs_kind;
+    c->opt.rhs_kind = SGN_RHS_ADJOINT;
+    sgn_status s = assemble_impl(c, d_x, d_p, c->d_srhs, c->d_g, &f0);
+    c->opt.rhs_kind = keep;
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  const double t1 = now_ms();
+  si.ms_assemble = t1 - t0;
+  {
+    sgn_factor_info fi{};
+    sgn_status s = sgn_factor_impl(c, &fi);
+    if (s != SGN_OK) return s;
+  }
+  const double t2 = now_ms();
+  si.ms_factor = t2 - t1;
+  // curvature pair of the previous step, kept when s^T y > 1e-12 |s| |y|
+  if (c->lb_have_prev && m > 0) {
+    double* sn = c->lb_s + (int64_t)c->lb_head * np;
+    double* yn = c->lb_y + (int64_t)c->lb_head * np;
+    launch_axpby(np, 1.0, d_p, -1.0, c->lb_pprev, sn, st);
+    launch_axpby(np, 1.0, c->d_g, -1.0, c->lb_gprev, yn, st);
+    dev_dot(c, np, sn, yn, 50);
+    dev_dot(c, np, sn, sn, 51);
+    dev_dot(c, np, yn, yn, 52);
+    double v[3];
+    TRY(read_scalars(c, 50, 3, v));
+    if (v[0] > 1e-12 * std::sqrt(std::max(v[1], 0.0) * std::max(v[2], 0.0))) {
+      c->lb_rho[c->lb_head] = 1.0 / v[0];
+      c->lb_head = (c->lb_head + 1) % m;
+      c->lb_count = std::min(c->lb_count + 1, m);
+    }
+  }
+  // two-loop recursion (newest pair first, then oldest first) around H0 q = H_GN^-1 q, which is the
+  // parameter block of the saddle-point solve with right-hand side [0; q; 0] (eq. sparseSystemGN with
+  // -g replaced by q)
+  HIPCHK(hipMemcpyAsync(c->lb_q, c->d_g, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+  std::vector<double> alpha(c->lb_count);
+  for (int k = 0; k < c->lb_count; ++k) {
+    const int i = (c->lb_head - 1 - k + 2 * m) % m;
+    dev_dot(c, np, c->lb_s + (int64_t)i * np, c->lb_q, 53);
+    double sq;
+    TRY(read_scalars(c, 53, 1, &sq));
+    alpha[k] = c->lb_rho[i] * sq;
+    launch_axpby(np, 1.0, c->lb_q, -alpha[k], c->lb_y + (int64_t)i * np, c->lb_q, st);
+  }
+  launch_fill(N, 0.0, c->d_srhs, st);
+  HIPCHK(hipMemcpyAsync(c->d_srhs + nx, c->lb_q, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+  {
+    sgn_status s = sgn_solve_impl(c, c->d_srhs, c->d_ssol, &si.solve);
+    if (s != SGN_OK) return s;
+  }
+  HIPCHK(hipMemcpyAsync(c->lb_r, c->d_ssol + nx, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int k = c->lb_count - 1; k >= 0; --k) {
+    const int i = (c->lb_head - 1 - k + 2 * m) % m;
+    dev_dot(c, np, c->lb_y + (int64_t)i * np, c->lb_r, 53);
+    double yr;
+    TRY(read_scalars(c, 53, 1, &yr));
+    const double beta = c->lb_rho[i] * yr;
+    launch_axpby(np, 1.0, c->lb_r, alpha[k] - beta, c->lb_s + (int64_t)i * np, c->lb_r, st);
+  }
+  double* dir = c->lb_q;  // -H g
+  launch_axpby(np, -1.0, c->lb_r, 0.0, nullptr, dir, st);
+  dev_dot(c, np, c->d_g, dir, 54);
+  dev_dot(c, np, c->d_g, c->d_g, 55);
+  double v[2];
+  TRY(read_scalars(c, 54, 2, v));
+  const double t3 = now_ms();
+  si.ms_solve = t3 - t2;
+  HIPCHK(hipMemcpyAsync(c->lb_pprev, d_p, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(c->lb_gprev, c->d_g, np * sizeof(double), hipMemcpyDeviceToDevice, st));
+  c->lb_have_prev = true;
+  si.f0 = f0;
+  si.gtdp = v[0];
+  si.grad_norm = std::sqrt(std::max(v[1], 0.0));
+  return line_search(c, d_p, d_x, dir, t3, &si, info);
+}
+
+sgn_status sgn_batch_create(int n, const sgn_problem* const* probs, const sgn_options* opt, void* stream,
+                            sgn_ctx* out) {
+  if (!out) return SGN_E_ARG;
+  *out = nullptr;
+  if (n < 1 || !probs) return SGN_E_ARG;
+  for (int i = 0; i < n; ++i) {
+    const sgn_problem* q = probs[i];
+    if (!q || q->n_components > 1 || q->n_nodes <= 0 || q->n_elems <= 0 || (q->dim != 2 && q->dim != 3))
+      return SGN_E_ARG;
+    if (!q->rest_pos || !q->elems || !q->node_grid || !q->fixed || !q->f_ext) return SGN_E_ARG;
+    if (q->n_targets < 0 || (q->n_targets > 0 && !q->target_dof)) return SGN_E_ARG;
+    const sgn_problem* f = probs[0];
+    if (q->dim != f->dim || q->param_kind != f->param_kind || q->E0 != f->E0 || q->nu != f->nu ||
+        q->target_w != f->target_w || q->reg_mu != f->reg_mu)
+      return SGN_E_ARG;
+  }
+  const int d = probs[0]->dim, nv = d + 1;
+  std::vector<double> rest, fext, tval, pref;
+  std::vector<int32_t> elems, grid, tdof, cptr{0};
+  std::vector<uint8_t> fixed;
+  double ell = 0.0;
+  int64_t node_off = 0, x_off = 0;
+  for (int i = 0; i < n; ++i) {
+    const sgn_problem* q = probs[i];
+    const int64_t nn = q->n_nodes;
+    int64_t nfree = 0;
+    for (int64_t v = 0; v < nn; ++v) nfree += q->fixed[v] ? 0 : 1;
+    const int64_t nxq = nfree * d;
+    const int64_t npq = q->param_kind == SGN_P_LOGE ? q->n_elems : nxq;
+    rest.insert(rest.end(), q->rest_pos, q->rest_pos + nn * d);
+    fext.insert(fext.end(), q->f_ext, q->f_ext + nn * d);
+    grid.insert(grid.end(), q->node_grid, q->node_grid + nn * d);
+    fixed.insert(fixed.end(), q->fixed, q->fixed + nn);
+    for (int64_t k = 0; k < (int64_t)q->n_elems * nv; ++k) {
+      const int32_t v = q->elems[k];
+      if (v < 0 || v >= nn) return SGN_E_ARG;
+      elems.push_back((int32_t)(v + node_off));
+    }
+    for (int t = 0; t < q->n_targets; ++t) {
+      if (q->target_dof[t] < 0 || q->target_dof[t] >= nxq) return SGN_E_ARG;
+      tdof.push_back((int32_t)(q->target_dof[t] + x_off));
+      tval.push_back(q->target_val ? q->target_val[t] : 0.0);
+    }
+    for (int64_t k = 0; k < npq; ++k) pref.push_back(q->p_ref ? q->p_ref[k] : 0.0);
+    ell = std::max(ell, q->length_scale);
+    node_off += nn;
+    x_off += nxq;
+    cptr.push_back((int32_t)node_off);
+    if (node_off > INT32_MAX / 2) return SGN_E_ARG;
+  }
+  sgn_problem u = *probs[0];
+  u.n_nodes = (int)node_off;
+  u.n_elems = (int)(elems.size() / nv);
+  u.rest_pos = rest.data();
+  u.elems = elems.data();
+  u.node_grid = grid.data();
+  u.fixed = fixed.data();
+  u.f_ext = fext.data();
+  u.n_targets = (int)tdof.size();
+  u.target_dof = tdof.data();
+  u.target_val = tval.data();
+  u.length_scale = ell > 0 ? ell : 1.0;
+  u.p_ref = pref.data();
+  u.n_components = n;
+  u.component_ptr = cptr.data();
+  return sgn_create(&u, opt, stream, out);
+}
+
+sgn_status sgn_batch_step(sgn_ctx c, double* const* d_p, double* const* d_x, sgn_step_info* info) {
+  TRY(check_ready(c));
+  if (!c->batch_ok) return fail(c, SGN_E_STATE, "parameters are not stored problem by problem (sgn_batch_create does)");
+  if (c->opt.solver != SGN_LDLT && c->opt.solver != SGN_BICGSTAB)
+    return fail(c, SGN_E_STATE, "the batched step uses the direct solve (SGN_LDLT or SGN_BICGSTAB)");
+  const int nc = c->ncomp;
+  if (!d_p || !d_x) return fail(c, SGN_E_ARG, "null state arrays");
+  for (int k = 0; k < nc; ++k)
+    if (!d_p[k] || !d_x[k]) return fail(c, SGN_E_ARG, "null state of a problem");
+  const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p;
+  hipStream_t st = c->stream;
+  const bool kkt = c->opt.rhs_kind == SGN_RHS_KKT;
+  const std::vector<int64_t>&sx = c->seg_x, &sp = c->seg_p;
+  double* X = c->d_x;
+  double* P = c->d_p;
+  for (int k = 0; k < nc; ++k) {
+    HIPCHK(hipMemcpyAsync(P + sp[k], d_p[k], (sp[k + 1] - sp[k]) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(X + sx[k], d_x[k], (sx[k + 1] - sx[k]) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  const double t0 = now_ms();
+  // the problems' states are equilibria: the union Newton confirms it (and leaves the Kx factor the
+  // adjoint right-hand side needs)
+  {
+    sgn_status s = equilibrium_impl(c, P, X, nullptr);
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  std::vector<double> f0(nc), f1(nc), ft(nc), slope(nc), gn(nc, -1.0), alpha(nc, 1.0);
+  std::vector<int> done(nc, 0), halv(nc, 0);
+  std::vector<int32_t> mask(nc);
+  TRY(batch_objectives(c, X, P, f0.data()));
+  {
+    sgn_status s = assemble_impl(c, X, P, c->d_srhs, kkt ? nullptr : c->d_g, nullptr);
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  const double t1 = now_ms();
+  {
+    sgn_factor_info fi{};
+    sgn_status s = sgn_factor_impl(c, &fi);
+    if (s != SGN_OK) return s;
+  }
+  const double t2 = now_ms();
+  sgn_solve_info sinfo{};
+  {
+    sgn_status s = sgn_solve_impl(c, c->d_srhs, c->d_ssol, &sinfo);
+    if (s != SGN_OK) return s;
+  }
+  const double t3 = now_ms();
+  const double* dx = c->d_ssol;
+  const double* dp = c->d_ssol + nx;
+  // per-problem slopes g^T dp (KKT form: df/dx dx + df/dp dp, equal since Kx dx + Kp dp = 0)
+  {
+    std::vector<double> v(3 * (size_t)nc);
+    if (kkt) {
+      launch_segment_dot(nc, c->d_seg_x, c->d_fx, dx, c->d_seg_val, st);
+      launch_segment_dot(nc, c->d_seg_p, c->d_fp, dp, c->d_seg_val + nc, st);
+    } else {
+      launch_fill(nc, 0.0, c->d_seg_val, st);
+      launch_segment_dot(nc, c->d_seg_p, c->d_g, dp, c->d_seg_val + nc, st);
+      launch_segment_dot(nc, c->d_seg_p, c->d_g, c->d_g, c->d_seg_val + 2 * nc, st);
+    }
+    HIPCHK(hipMemcpyAsync(v.data(), c->d_seg_val, (kkt ? 2 : 3) * nc * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < nc; ++k) {
+      slope[k] = v[k] + v[nc + k];
+      if (!kkt) gn[k] = std::sqrt(std::max(v[2 * nc + k], 0.0));
+    }
+  }
+  // backtracking per problem, all trials of a round in one union equilibrium: problems already
+  // accepted keep their step and state (kept in d_old2 and restored before every round)
+  double* xacc = c->d_old2;
   int nt_iters = 0;
+  // the host mask is rewritten for the next use only after the stream has consumed it
+  auto upload_mask = [&](auto pred) -> hipError_t {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < nc; ++k) mask[k] = pred(k) ? 1 : 0;
+    return hipMemcpyAsync(c->d_seg_mask, mask.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  };
   for (int h = 0; h <= c->opt.max_halvings; ++h) {
-    launch_axpby(np, 1.0, d_p, alpha, sol + nx, c->d_pt, c->stream);
-    HIPCHK(hipMemcpyAsync(c->d_xt, d_x, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_seg_alpha, alpha.data(), nc * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_segment_axpy(nc, c->d_seg_p, c->d_seg_alpha, P, dp, c->d_pt, st);
+    HIPCHK(upload_mask([&](int k) { return done[k] == 0; }));
+    launch_segment_copy(nc, c->d_seg_x, c->d_seg_mask, X, c->d_xt, st);
+    HIPCHK(upload_mask([&](int k) { return done[k] != 0; }));
+    launch_segment_copy(nc, c->d_seg_x, c->d_seg_mask, xacc, c->d_xt, st);
     sgn_eq_info ei{};
-    sgn_status s = equilibrium_impl(c, c->d_pt, c->d_xt, &ei);
+    const sgn_status s = equilibrium_impl(c, c->d_pt, c->d_xt, &ei);
+    if (s == SGN_E_HIP) return fail(c, s, c->err);
     if (s == SGN_OK) {
       nt_iters += ei.iters;
-      double f1;
-      TRY(objective_value(c, c->d_xt, c->d_pt, &f1));
-      if (f1 <= f0 + 1e-4 * alpha * gtdp) {
-        si.f1 = f1;
-        ok = true;
-        break;
-      }
-    } else if (s == SGN_E_HIP) {
-      return fail(c, s, c->err);
+      TRY(batch_objectives(c, c->d_xt, c->d_pt, ft.data()));
+      for (int k = 0; k < nc; ++k)
+        if (!done[k] && ft[k] <= f0[k] + 1e-4 * alpha[k] * slope[k]) {
+          done[k] = 3;  // accepted in this round
+          f1[k] = ft[k];
+        }
+      HIPCHK(upload_mask([&](int k) { return done[k] == 3; }));
+      launch_segment_copy(nc, c->d_seg_x, c->d_seg_mask, c->d_xt, xacc, st);
+      for (int k = 0; k < nc; ++k)
+        if (done[k] == 3) done[k] = 1;
     }
-    alpha *= 0.5;
-    ++si.halvings;
+    if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; })) break;
+    if (h == c->opt.max_halvings) break;
+    HIPCHK(hipStreamSynchronize(st));  // the uploaded step lengths are consumed before they change
+    for (int k = 0; k < nc; ++k)
+      if (!done[k]) {
+        alpha[k] *= 0.5;
+        ++halv[k];
+      }
   }
-  si.ms_linesearch = now_ms() - t3;
-  si.newton_iters = nt_iters;
-  if (!ok && std::fabs(gtdp) <= 1e-12 * std::fabs(f0)) {
-    // the predicted decrease of the whole step is below the objective's rounding: the iterate is
-    // stationary to working precision and Armijo decisions are noise; stay (alpha = 0)
-    si.alpha = 0.0;
-    si.f1 = f0;
-    if (info) *info = si;
-    return SGN_OK;
+  c->kx_valid = false;  // the last equilibrium was of a trial state
+  bool failed = false;
+  for (int k = 0; k < nc; ++k)
+    if (!done[k]) {
+      if (std::fabs(slope[k]) <= 1e-12 * std::fabs(f0[k])) {
+        done[k] = 2;  // stationary to working precision: stays (alpha = 0), as sgn_step
+        alpha[k] = 0.0;
+        f1[k] = f0[k];
+      } else {
+        failed = true;
+      }
+    }
+  const double t4 = now_ms();
+  if (info)
+    for (int k = 0; k < nc; ++k) {
+      sgn_step_info& o = info[k];
+      o = sgn_step_info{};
+      o.alpha = done[k] ? alpha[k] : 0.0;
+      o.f0 = f0[k];
+      o.f1 = done[k] ? f1[k] : f0[k];
+      o.grad_norm = gn[k];
+      o.gtdp = slope[k];
+      o.halvings = halv[k];
+      o.newton_iters = nt_iters;
+      o.ms_assemble = t1 - t0;
+      o.ms_factor = t2 - t1;
+      o.ms_solve = t3 - t2;
+      o.ms_linesearch = t4 - t3;
+      o.solve = sinfo;
+    }
+  if (failed) return fail(c, SGN_E_LINESEARCH, "line search failed for a problem of the batch");
+  // final states: accepted problems at their trial, stationary ones where they were
+  HIPCHK(hipMemcpyAsync(c->d_seg_alpha, alpha.data(), nc * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_segment_axpy(nc, c->d_seg_p, c->d_seg_alpha, P, dp, c->d_pt, st);
+  HIPCHK(upload_mask([&](int k) { return done[k] == 1; }));
+  launch_segment_copy(nc, c->d_seg_x, c->d_seg_mask, xacc, c->d_xt, st);
+  HIPCHK(upload_mask([&](int k) { return done[k] == 2; }));
+  launch_segment_copy(nc, c->d_seg_x, c->d_seg_mask, X, c->d_xt, st);
+  for (int k = 0; k < nc; ++k) {
+    HIPCHK(hipMemcpyAsync(d_p[k], c->d_pt + sp[k], (sp[k + 1] - sp[k]) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_x[k], c->d_xt + sx[k], (sx[k + 1] - sx[k]) * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  si.alpha = alpha;
-  if (info) *info = si;
-  if (!ok) {
-    c->kx_valid = false;
-    return fail(c, SGN_E_LINESEARCH, "line search failed");
-  }
-  HIPCHK(hipMemcpyAsync(d_p, c->d_pt, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(d_x, c->d_xt, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipStreamSynchronize(st));
+  (void)np;
   return SGN_OK;
 }
 

@@ -268,6 +268,18 @@ __global__ void k_diag_add(int64_t N, const int64_t* __restrict__ rowptr, const 
   }
 }
 
+// out[i] += sign e_i z[i] with e the stabilisation diagonal of the variable kinds (eps_x on x,
+// -eps_lambda on lambda, 0 on parameters): sign +1 turns b - K_eps z into b - K z, sign -1 turns
+// K_eps z into K z
+__global__ void k_unstabilise(int64_t N, const int32_t* __restrict__ kind, double eps_x, double eps_lambda,
+                              double sign, const double* __restrict__ z, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = kind[i];
+    const double e = (k == 1 || k == 3) ? eps_x : (k == 4 ? -eps_lambda : 0.0);
+    out[i] += sign * e * z[i];
+  }
+}
+
 __global__ void k_const_slots(int64_t n, const int64_t* slots, double value, double* vals) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     vals[slots[i]] += value;
@@ -345,6 +357,35 @@ __global__ void __launch_bounds__(256) k_final_max(const double* partials, int n
   for (int i = threadIdx.x; i < np; i += 256) acc = fmax(acc, partials[i]);
   const double r = block_max(acc, sh);
   if (threadIdx.x == 0) *out = r;
+}
+
+// Per-segment reductions and updates for batches of independent problems: segment s covers
+// [off[s], off[s+1]); one block per segment, fixed summation order (bitwise reproducible).
+__global__ void __launch_bounds__(256) k_segment_dot(const int64_t* __restrict__ off, const double* __restrict__ a,
+                                                     const double* __restrict__ b, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int64_t lo = off[blockIdx.x], hi = off[blockIdx.x + 1];
+  double acc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += a[i] * b[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+// out[i] = x[i] + alpha[s] dir[i] on segment s
+__global__ void __launch_bounds__(256) k_segment_axpy(const int64_t* __restrict__ off, const double* __restrict__ alpha,
+                                                      const double* __restrict__ x, const double* __restrict__ dir,
+                                                      double* __restrict__ out) {
+  const int64_t lo = off[blockIdx.x], hi = off[blockIdx.x + 1];
+  const double a = alpha[blockIdx.x];
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) out[i] = x[i] + a * dir[i];
+}
+
+// dst[i] = src[i] on the segments whose mask is set
+__global__ void __launch_bounds__(256) k_segment_copy(const int64_t* __restrict__ off, const int32_t* __restrict__ mask,
+                                                      const double* __restrict__ src, double* __restrict__ dst) {
+  if (!mask[blockIdx.x]) return;
+  const int64_t lo = off[blockIdx.x], hi = off[blockIdx.x + 1];
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) dst[i] = src[i];
 }
 
 __global__ void k_gather_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out) {
@@ -498,6 +539,11 @@ void launch_diag_add(int64_t N, const int64_t* rowptr, const int32_t* kind, doub
   if (N > 0) k_diag_add<<<grid_for(N, 256), 256, 0, s>>>(N, rowptr, kind, a_target, c_param, eps_x, eps_lambda, vals);
 }
 
+void launch_unstabilise(int64_t N, const int32_t* kind, double eps_x, double eps_lambda, double sign, const double* z,
+                        double* out, hipStream_t s) {
+  if (N > 0) k_unstabilise<<<grid_for(N, 256), 256, 0, s>>>(N, kind, eps_x, eps_lambda, sign, z, out);
+}
+
 void launch_const_slots(int64_t n, const int64_t* slots, double value, double* vals, hipStream_t s) {
   if (n > 0) k_const_slots<<<grid_for(n, 256), 256, 0, s>>>(n, slots, value, vals);
 }
@@ -522,6 +568,20 @@ void launch_max_abs_partials(int64_t n, const double* a, double* partials, hipSt
 
 void launch_final_max(const double* partials, int np, double* out, hipStream_t s) {
   k_final_max<<<1, 256, 0, s>>>(partials, np, out);
+}
+
+void launch_segment_dot(int nseg, const int64_t* off, const double* a, const double* b, double* out, hipStream_t s) {
+  if (nseg > 0) k_segment_dot<<<nseg, 256, 0, s>>>(off, a, b, out);
+}
+
+void launch_segment_axpy(int nseg, const int64_t* off, const double* alpha, const double* x, const double* dir,
+                         double* out, hipStream_t s) {
+  if (nseg > 0) k_segment_axpy<<<nseg, 256, 0, s>>>(off, alpha, x, dir, out);
+}
+
+void launch_segment_copy(int nseg, const int64_t* off, const int32_t* mask, const double* src, double* dst,
+                         hipStream_t s) {
+  if (nseg > 0) k_segment_copy<<<nseg, 256, 0, s>>>(off, mask, src, dst);
 }
 
 void launch_gather_perm(int64_t n, const int32_t* perm, const double* scale, const double* in, double* out,

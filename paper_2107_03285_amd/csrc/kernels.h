@@ -64,6 +64,9 @@ void launch_gather_slots(int64_t nnz, const int64_t* ptr, const int32_t* src, co
 void launch_diag_add(int64_t N, const int64_t* rowptr, const int32_t* kind, double a_target, double c_param,
                      double eps_x, double eps_lambda, double* vals, hipStream_t s);
 void launch_const_slots(int64_t n, const int64_t* slots, double value, double* vals, hipStream_t s);
+// out[i] += sign e_i z[i], e the stabilisation diagonal (eps_x on x, -eps_lambda on lambda, 0 on parameters)
+void launch_unstabilise(int64_t N, const int32_t* kind, double eps_x, double eps_lambda, double sign, const double* z,
+                        double* out, hipStream_t s);
 // c[i] = sum(ebuf[src]) - fext[i] - (pforce ? p[i] : 0)
 void launch_gather_vec(int64_t n, const int64_t* ptr, const int32_t* src, const double* ebuf,
                        const double* fext, const double* pforce, double* out, hipStream_t s);
@@ -73,6 +76,14 @@ void launch_dot_partials(int64_t n, const double* a, const double* b, int64_t st
 void launch_final_sum(const double* partials, int np, double* out, hipStream_t s);
 void launch_max_abs_partials(int64_t n, const double* a, double* partials, hipStream_t s);
 void launch_final_max(const double* partials, int np, double* out, hipStream_t s);
+
+// per-segment operations on batches (segment s = [off[s], off[s+1]), one block each, nseg <= 65535):
+// out[s] = sum a b over the segment; out = x + alpha[s] dir; dst = src where mask[s] != 0
+void launch_segment_dot(int nseg, const int64_t* off, const double* a, const double* b, double* out, hipStream_t s);
+void launch_segment_axpy(int nseg, const int64_t* off, const double* alpha, const double* x, const double* dir,
+                         double* out, hipStream_t s);
+void launch_segment_copy(int nseg, const int64_t* off, const int32_t* mask, const double* src, double* dst,
+                         hipStream_t s);
 
 // ---------------------------------------------------------------- vectors / permutations
 // out[k] = scale[k] * in[perm[k]] (scale may be null)

@@ -135,30 +135,45 @@ class Trainer:
         return info.sweeps, info.fallback, info.rel_res
 
 
-def build_pairs(meshes, seeds, n_iter, dev, fractions=FRACTIONS):
-    """(prob, state_a, state_b, t) samples: reference at iterate k, matrix a fraction t along the step."""
+def family_problems(seeds, max_side=20):
+    """The learned-preconditioner family (cantilevers 4s x s x s for even seeds, plates 4s x s x
+    max(2, ceil(s/4)) for odd ones, s ~ U{5..20} per seed, log-modulus parameters); seeds whose s
+    exceeds max_side are skipped (a training budget, stated in the report)."""
+    out = []
+    for sd in seeds:
+        q = si.learned_pc_problem(sd)
+        if q.grid[1] <= max_side:
+            out.append(q)
+    return out
+
+
+def build_pairs(meshes, seeds, n_iter, dev, fractions=FRACTIONS, problems=None):
+    """(prob, state_a, state_b, t) samples: reference at iterate k, matrix a fraction t along the step.
+    The problems are the cantilevers `meshes` x `seeds`, or `problems` when given."""
     pairs = []
-    for (nx, ny, nz, h) in meshes:
-        for s in seeds:
-            prob = si.problem_3d(nx, ny, nz, h, seed=s)
-            states = run_sgn(prob, n_iter, dev)
-            ctx = sgn.Context(prob, sgn.default_options()).allocate(dev)
-            ctx.set_targets(prob.target_val, prob.length_scale)
-            for k in range(len(states) - 1):
-                (xa, pa), (xb, pb) = states[k], states[k + 1]
-                for t in fractions:
-                    if t == 1.0:
-                        pairs.append((prob, states[k], states[k + 1], t))
-                        continue
-                    p = _t(pa + t * (pb - pa), dev)
-                    x = _t(xa, dev)
-                    try:
-                        ctx.equilibrium(p, x)
-                    except sgn.SgnError:
-                        continue
-                    pairs.append((prob, states[k], (x.cpu().numpy().copy(), p.cpu().numpy().copy()), t))
-            del ctx
-            log(f"[learned_pc] logged {prob.name}: {len(states) - 1} iterations")
+    if problems is None:
+        problems = [si.problem_3d(nx, ny, nz, h, seed=s) for (nx, ny, nz, h) in meshes for s in seeds]
+    for prob in problems:
+        states = run_sgn(prob, n_iter, dev)
+        ctx = sgn.Context(prob, sgn.default_options()).allocate(dev)
+        ctx.set_targets(prob.target_val, prob.length_scale)
+        for k in range(len(states) - 1):
+            (xa, pa), (xb, pb) = states[k], states[k + 1]
+            for t in fractions:
+                if t == 1.0:
+                    pairs.append((prob, states[k], states[k + 1], t))
+                    continue
+                p = _t(pa + t * (pb - pa), dev)
+                x = _t(xa, dev)
+                try:
+                    ctx.equilibrium(p, x)
+                except sgn.SgnError:  # no equilibrium there; an error is sticky, so start a fresh context
+                    ctx = sgn.Context(prob, sgn.default_options()).allocate(dev)
+                    ctx.set_targets(prob.target_val, prob.length_scale)
+                    continue
+                pairs.append((prob, states[k], (x.cpu().numpy().copy(), p.cpu().numpy().copy()), t))
+        del ctx
+        log(f"[learned_pc] logged {prob.name}: {len(states) - 1} iterations")
     return pairs
 
 
@@ -171,11 +186,22 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--nprobe", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--family", action="store_true",
+                    help="train and evaluate on the cantilever/plate family with s ~ U{5..20} (seeds 0.. for "
+                         "training, 1000.. held out) instead of the three fixed small cantilevers")
+    ap.add_argument("--held-seeds", type=int, default=3)
+    ap.add_argument("--max-side", type=int, default=20, help="skip family seeds with a larger s")
     args = ap.parse_args()
     dev = "cuda:0"
     t0 = time.time()
-    train = build_pairs(TRAIN_MESHES, range(args.train_seeds), args.iters, dev)
-    held = build_pairs([TRAIN_MESHES[-1]], range(1000, 1003), args.iters, dev)
+    if args.family:
+        train = build_pairs(None, None, args.iters, dev,
+                            problems=family_problems(range(args.train_seeds), args.max_side))
+        held = build_pairs(None, None, args.iters, dev,
+                           problems=family_problems(range(1000, 1000 + args.held_seeds), args.max_side))
+    else:
+        train = build_pairs(TRAIN_MESHES, range(args.train_seeds), args.iters, dev)
+        held = build_pairs([TRAIN_MESHES[-1]], range(1000, 1000 + args.held_seeds), args.iters, dev)
     log(f"[learned_pc] {len(train)} training pairs, {len(held)} held-out pairs ({time.time() - t0:.1f} s)")
     tr = Trainer(train[0][0], seed=args.seed, lr=args.lr, dev=dev)
 
@@ -185,7 +211,9 @@ def main():
                                      for p, a, b, _ in held])))
 
     report = {"n_weights": int(tr.w.numel()), "train_pairs": len(train), "held_pairs": len(held),
-              "meshes": TRAIN_MESHES, "epochs": args.epochs, "lr": args.lr, "history": []}
+              "meshes": sorted({p.name for p, *_ in train}), "held_meshes": sorted({p.name for p, *_ in held}),
+              "family": bool(args.family), "max_side": args.max_side, "sgn_iterations_logged": args.iters,
+              "epochs": args.epochs, "lr": args.lr, "history": []}
     base_iters = [tr.minres_iterations(p, a, b, False) for p, a, b, _ in held]
     report["held_loss_untrained"] = held_loss()
     log(f"[learned_pc] held-out loss before training {report['held_loss_untrained']:.4e}")

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "SGN_OK", 1: "SGN_E_ARG", 2: "SGN_E_STATE", 3: "SGN_E_NOMEM",
                 9: "SGN_E_LINESEARCH"}
 SGN_P_LOGE, SGN_P_REST_POS, SGN_P_NODAL_FORCE = 0, 1, 2
 SGN_FP64, SGN_FP32_IR = 0, 1
-SGN_LDLT, SGN_MINRES_LEARNED = 0, 1
+SGN_LDLT, SGN_MINRES_LEARNED, SGN_BICGSTAB, SGN_BLOCK_GN = 0, 1, 2, 3
 SGN_RHS_ADJOINT, SGN_RHS_KKT = 0, 1
 SGN_SYS_SGN, SGN_SYS_KX = 0, 1
 
@@ -31,7 +31,8 @@ EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_w
            "sgn_get_symbolic", "sgn_get_values", "sgn_get_stats", "sgn_selftest_mfma", "sgn_last_error",
            "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
            "sgn_solve_minres", "sgn_gnn_num_weights", "sgn_gnn_init", "sgn_gnn_forward", "sgn_gnn_backward",
-           "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss", "sgn_graph_step", "sgn_autotune"]
+           "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss", "sgn_graph_step", "sgn_autotune",
+           "sgn_block_step", "sgn_lbfgs_step", "sgn_batch_create", "sgn_batch_step"]
 
 
 class sgn_problem(C.Structure):
@@ -51,7 +52,7 @@ class sgn_options(C.Structure):
                 ("eps_x", C.c_double), ("eps_lambda", C.c_double), ("max_newton", C.c_int),
                 ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int),
                 ("profile", C.c_int), ("max_gmres", C.c_int), ("outer_panels", C.c_int * 3),
-                ("seq_panels", C.c_int)]
+                ("seq_panels", C.c_int), ("max_bicgstab", C.c_int), ("lbfgs_m", C.c_int)]
 
 
 class sgn_stats(C.Structure):
@@ -111,6 +112,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_assemble": (C.c_int, [vp, vp, vp, vp, vp, dp]),
         "sgn_factor": (C.c_int, [vp, C.POINTER(sgn_factor_info)]),
         "sgn_solve": (C.c_int, [vp, vp, vp, C.POINTER(sgn_solve_info)]),
+        "sgn_block_step": (C.c_int, [vp, vp, vp, vp, C.POINTER(sgn_solve_info)]),
+        "sgn_lbfgs_step": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(sgn_step_info)]),
+        "sgn_batch_create": (C.c_int, [C.c_int, C.POINTER(C.POINTER(sgn_problem)), C.POINTER(sgn_options), vp,
+                                       C.POINTER(vp)]),
+        "sgn_batch_step": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(sgn_step_info)]),
         "sgn_step": (C.c_int, [vp, vp, vp, C.POINTER(sgn_step_info)]),
         "sgn_get_sizes": (C.c_int, [vp, C.c_int, i64p, i64p, i64p, i64p, dp]),
         "sgn_get_symbolic": (C.c_int, [vp, C.c_int, i32p, i32p, i64p, i32p]),
@@ -259,6 +265,40 @@ class Context:
             raise SgnError(st, msg)
         self.workspace = None
 
+    @classmethod
+    def from_batch(cls, problems, options: sgn_options = None, stream=None):
+        """A context over a batch of independent problems built by sgn_batch_create (the union is the
+        problems in order; ``prob`` of the returned context is None)."""
+        lib = load_library()
+        self = cls.__new__(cls)
+        self.lib = lib
+        self.prob = None
+        self.options = options if options is not None else default_options()
+        structs, keeps = zip(*[_problem_struct(q) for q in problems])
+        for P in structs:
+            P.n_components = 0
+        arr = (C.POINTER(sgn_problem) * len(structs))(*[C.pointer(P) for P in structs])
+        self._keep = {"structs": structs, "arrays": keeps, "ptrs": arr}
+        self._stream = stream
+        h = C.c_void_p()
+        st = lib.sgn_batch_create(len(structs), arr, C.byref(self.options), self._stream_ptr(), C.byref(h))
+        self.h = h
+        self.workspace = None
+        if st != SGN_OK:
+            msg = lib.sgn_last_error(h).decode() if h.value else "invalid batch"
+            raise SgnError(st, msg)
+        return self
+
+    def batch_step(self, ps, xs):
+        """One outer iteration of every problem of a batch (device tensors per problem, updated in
+        place); returns the per-problem step infos."""
+        n = len(ps)
+        infos = (sgn_step_info * n)()
+        pp = (C.c_void_p * n)(*[int(t.data_ptr()) for t in ps])
+        xx = (C.c_void_p * n)(*[int(t.data_ptr()) for t in xs])
+        self._check(self.lib.sgn_batch_step(self.h, pp, xx, infos))
+        return list(infos)
+
     def _stream_ptr(self):
         if self._stream is None:
             return None
@@ -343,6 +383,12 @@ class Context:
         self._check(self.lib.sgn_solve(self.h, _dev_ptr(rhs), _dev_ptr(sol), C.byref(info)))
         return info
 
+    def block_step(self, x, p, sol):
+        """Block Gauss-Newton direction [dx; dp; dlam] at the equilibrium (x, p) (solver SGN_BLOCK_GN)."""
+        info = sgn_solve_info()
+        self._check(self.lib.sgn_block_step(self.h, _dev_ptr(x), _dev_ptr(p), _dev_ptr(sol), C.byref(info)))
+        return info
+
     def solve_minres(self, rhs, sol):
         info = sgn_solve_info()
         self._check(self.lib.sgn_solve_minres(self.h, _dev_ptr(rhs), _dev_ptr(sol), C.byref(info)))
@@ -403,6 +449,12 @@ class Context:
     def step(self, p, x):
         info = sgn_step_info()
         self._check(self.lib.sgn_step(self.h, _dev_ptr(p), _dev_ptr(x), C.byref(info)))
+        return info
+
+    def lbfgs_step(self, p, x, restart=False):
+        """One SGN-initialised L-BFGS iteration (updates p and x in place)."""
+        info = sgn_step_info()
+        self._check(self.lib.sgn_lbfgs_step(self.h, _dev_ptr(p), _dev_ptr(x), int(bool(restart)), C.byref(info)))
         return info
 
     def values(self, which=SGN_SYS_SGN):

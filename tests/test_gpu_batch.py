@@ -117,3 +117,90 @@ def test_component_validation():
     bad.components[1] += 1  # an element now spans two components
     with pytest.raises(sgn.SgnError):
         sgn.Context(bad, sgn.default_options())
+
+
+def test_graph_is_recaptured_after_new_targets_or_workspace():
+    """The captured step holds ell and mu by value and every workspace address: after sgn_set_targets
+    or sgn_set_workspace the next graph step must be captured anew and equal the eager step.  Both
+    contexts get the same new targets (the eager one needs no recapture)."""
+    probs, u, refs = _batch()
+    o = sgn.default_options(precision=sgn.SGN_FP32_IR, rhs_kind=sgn.SGN_RHS_KKT)
+    ctx = sgn.Context(u, o).allocate()
+    eager = sgn.Context(u, o).allocate()
+    x = _d(np.concatenate([r[0] for r in refs]))
+    p = _d(u.p_init())
+    N = 2 * u.n_x + u.n_p
+    rhs, sol = (torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(2))
+    erhs, esol = (torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(2))
+
+    def check():
+        rel = ctx.graph_step(x, p, rhs, sol, 3)
+        eager.assemble(x, p, erhs)
+        eager.factor()
+        eager.solve(erhs, esol)
+        torch.cuda.synchronize()
+        assert rel <= 1e-10
+        assert np.array_equal(_h(rhs), _h(erhs))
+        assert np.linalg.norm(_h(sol) - _h(esol)) <= 1e-9 * np.linalg.norm(_h(esol))
+        return _h(sol).copy()
+
+    first = check()
+    # new targets and a new length scale on both contexts: a stale graph would keep the old ell and mu
+    tv = u.target_val + 0.1 * u.length_scale
+    for c in (ctx, eager):
+        c.set_targets(tv, 2.0 * u.length_scale)
+    second = check()
+    assert not np.array_equal(first, second)
+    # a new workspace (the old one stays allocated, so nothing can touch freed memory): a stale graph
+    # would run in the old workspace while the call reads the residual and the done flag from the new
+    old_ws = ctx.workspace
+    ctx.allocate()
+    third = check()
+    assert np.linalg.norm(third - second) <= 1e-9 * np.linalg.norm(second)
+    del old_ws
+
+
+def test_batch_create_builds_the_union():
+    """sgn_batch_create gives the same system as the union built by hand: same symbolic structure,
+    bitwise the same assembled values and step."""
+    probs, u, refs = _batch()
+    o = sgn.default_options(precision=sgn.SGN_FP32_IR, rhs_kind=sgn.SGN_RHS_KKT)
+    a = sgn.Context.from_batch(probs, o).allocate()
+    b = sgn.Context(u, o).allocate()
+    for s1, s2 in zip(a.symbolic(), b.symbolic()):
+        assert np.array_equal(s1, s2)
+    x = _d(np.concatenate([r[0] for r in refs]))
+    p = _d(u.p_init())
+    N = 2 * u.n_x + u.n_p
+    out = []
+    for ctx in (a, b):
+        rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+        sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+        ctx.assemble(x, p, rhs)
+        ctx.factor()
+        ctx.solve(rhs, sol)
+        out.append((ctx.values(), _h(rhs), _h(sol)))
+    for v1, v2 in zip(out[0], out[1]):
+        assert np.array_equal(v1, v2)
+
+
+@pytest.mark.parametrize("rhs_kind", [sgn.SGN_RHS_KKT, sgn.SGN_RHS_ADJOINT])
+def test_batch_step_follows_each_problem_outer_iteration(rhs_kind):
+    """Two sgn_batch_step calls: every problem's accepted step length and objective must follow its
+    own oracle iterations (dense Gauss-Newton step, Armijo backtracking, at the batch's ell)."""
+    probs, u, refs = _batch()
+    ctx = sgn.Context.from_batch(probs, sgn.default_options(rhs_kind=rhs_kind, newton_rtol=1e-11)).allocate()
+    ps = [_d(q.p_init()) for q in probs]
+    xs = [_d(r[0]) for r in refs]
+    infos = [ctx.batch_step(ps, xs) for _ in range(2)]
+    for i, q in enumerate(probs):
+        trace, p_ref, x_ref = D.sgn_iterations(q, q.p_init(), refs[i][0], iters=2)
+        for it in range(2):
+            f_ref, g_ref, a_ref = trace[it]
+            assert infos[it][i].alpha == a_ref, (q.name, it)
+            # the first step moves f by orders of magnitude: later values agree to the step's accuracy
+            # relative to the starting objective
+            assert infos[it][i].f0 == pytest.approx(f_ref, rel=1e-9, abs=1e-9 * trace[0][0]), (q.name, it)
+        assert np.linalg.norm(_h(ps[i]) - p_ref) <= 1e-8 * max(np.linalg.norm(p_ref), 1e-12)
+        u_ref = x_ref - q.x_rest()
+        assert np.linalg.norm(_h(xs[i]) - x_ref) <= 1e-8 * np.linalg.norm(u_ref)

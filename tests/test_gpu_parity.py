@@ -122,8 +122,8 @@ def test_step_matches_dense_gauss_newton(name, precision):
     grad = torch.zeros(prob.n_p, dtype=torch.float64, device="cuda")
     ctx.assemble(xd, pd, rhs, grad)
     fi = ctx.factor()
-    if precision == sgn.SGN_FP64:  # the FP32 factor may misjudge near-zero pivots; refinement repairs them
-        assert (fi.n_pos, fi.n_neg, fi.n_zero) == (prob.n_x + prob.n_p, prob.n_x, 0)
+    # inertia by Sylvester's law (the FP32 factor keeps its pivot blocks in FP64)
+    assert (fi.n_pos, fi.n_neg, fi.n_zero) == (prob.n_x + prob.n_p, prob.n_x, 0)
     sol = torch.zeros(N, dtype=torch.float64, device="cuda")
     si_ = ctx.solve(rhs, sol)
     assert si_.rel_res <= 1e-10
@@ -221,9 +221,11 @@ def test_factor_and_solve_are_bitwise_reproducible():
 def test_outer_step_kkt_rhs_matches_adjoint():
     """sgn_step with the KKT right-hand side (no adjoint solve) takes the adjoint-form step: same dp
     (Appendix A, Theorem 2), same slope, hence the same step length and new iterate.  Compared one
-    step at a time from two states (along a trajectory a borderline Armijo trial can be decided by
-    rounding differently by the two forms)."""
-    prob = D.setup_targets(si.problem_3d(4, 2, 2, 0.25, seed=1))
+    step at a time from two states of the 21 x 21 grid, whose full steps the oracle accepts with
+    margin.  (On the small 3D bars of this family the first steps change log E by up to 135, the
+    backtracking stops at 1/16..1/64 of them and whether the Newton solve of such a trial converges
+    depends on rounding, so the two forms' accepted lengths may differ there.)"""
+    prob = D.setup_targets(si.config_2d())
     rng = np.random.default_rng(4)
     for p_start in (prob.p_init(), prob.p_init() + 0.05 * rng.standard_normal(prob.n_p)):
         out = {}

@@ -66,3 +66,26 @@ def test_nan_filled_workspace_gives_the_zeroed_step_bitwise(name, precision):
     nan_filled = _step(prob, x, p, opts, 0xFF)
     assert np.all(np.isfinite(nan_filled))
     assert np.array_equal(zeroed, nan_filled)
+
+
+def _outer_step(prob, opts, fill_byte):
+    ctx = _context(prob, opts, fill_byte)
+    p = torch.tensor(prob.p_init(), dtype=torch.float64, device="cuda")
+    x = torch.tensor(prob.x_rest(), dtype=torch.float64, device="cuda")
+    ctx.equilibrium(p, x)
+    info = ctx.step(p, x)
+    return info.alpha, info.halvings, info.f1, p.cpu().numpy(), x.cpu().numpy()
+
+
+@pytest.mark.parametrize("rhs_kind", [sgn.SGN_RHS_ADJOINT, sgn.SGN_RHS_KKT])
+def test_prefilled_workspace_gives_the_zeroed_outer_step_bitwise(rhs_kind):
+    """The outer iteration from rest (Newton equilibria with their Kx factorisations, the step, the
+    backtracking trials) reads nothing it has not written either: workspaces prefilled with NaN bytes
+    or with a finite pattern give bitwise the iterate of a zeroed one."""
+    prob = D.setup_targets(si.problem_3d(4, 2, 2, 0.25, seed=1))
+    opts = sgn.default_options(rhs_kind=rhs_kind)
+    ref = _outer_step(prob, opts, 0)
+    for fill in (0xFF, 0x40):
+        got = _outer_step(prob, opts, fill)
+        assert got[:3] == ref[:3], (fill, got[:3], ref[:3])
+        assert np.array_equal(got[3], ref[3]) and np.array_equal(got[4], ref[4])

@@ -228,6 +228,8 @@ def test_equilibrated_residual_hand_example():
     K = sp.csr_matrix(np.array([[4.0, 1.0], [1.0, 9.0]]))
     got = D.equilibrated_residual(K, np.array([0.5, 0.0]), np.array([2.0, 3.0]))
     assert got == pytest.approx((5.0 / 6.0) / np.sqrt(2.0), rel=1e-15)
+    ext = D.equilibrated_residual_extended(K, np.array([0.5, 0.0]), np.array([2.0, 3.0]))
+    assert ext == pytest.approx((5.0 / 6.0) / np.sqrt(2.0), rel=1e-15)
     # invariant under a common scale of matrix and right-hand side
     assert D.equilibrated_residual(7.0 * K, np.array([0.5, 0.0]), np.array([14.0, 21.0])) == pytest.approx(got, rel=1e-14)
 
@@ -244,3 +246,47 @@ def test_no_targets_gives_the_regulariser_step():
     assert info.converged
     st = D.dense_gn_step(prob, x, p)
     assert np.linalg.norm(st.dp - (prob.p_ref - p)) <= 1e-12 * np.linalg.norm(p)
+
+
+def test_extended_refinement_reaches_the_rounded_exact_solution():
+    """Refinement with extended-precision residuals converges to the exact solution of the stored
+    (FP64) system to u_64 + cond u_ext (Wilkinson's bound for a residual carried in a precision u_ext):
+    on the 8 x 8 Hilbert matrix (cond 1.5e10) against the exact solution computed in rational arithmetic
+    from the FP64 entries, while one LU solve is off by about cond u_64."""
+    from fractions import Fraction
+    import scipy.sparse as sp
+    n = 8
+    H = np.array([[1.0 / (i + j + 1) for j in range(n)] for i in range(n)])
+    b = H @ np.ones(n)
+    # exact rational solution of the FP64 system (Gauss-Jordan on Fractions)
+    M = [[Fraction(float(H[i, j])) for j in range(n)] + [Fraction(float(b[i]))] for i in range(n)]
+    for k in range(n):
+        piv = max(range(k, n), key=lambda r: abs(M[r][k]))
+        M[k], M[piv] = M[piv], M[k]
+        for r in range(n):
+            if r != k and M[r][k] != 0:
+                f = M[r][k] / M[k][k]
+                M[r] = [a - f * c for a, c in zip(M[r], M[k])]
+    exact = np.array([float(M[i][n] / M[i][i]) for i in range(n)])
+    z0 = np.linalg.solve(H, b)
+    z, hist = D.refine_extended(sp.csr_matrix(H), b, z0, sweeps=4)
+    err0 = np.linalg.norm(z0 - exact) / np.linalg.norm(exact)
+    err = np.linalg.norm(z - exact) / np.linalg.norm(exact)
+    bound = 4 * np.finfo(np.float64).eps + 10 * np.linalg.cond(H) * np.finfo(np.longdouble).eps
+    assert err0 > 1e-9            # a plain solve carries cond * u
+    assert err <= bound, (err, bound)
+    assert err <= 0.1 * err0
+
+
+def test_polished_step_is_the_dense_step_on_a_small_problem(tiny):
+    prob = tiny
+    p = prob.p_init()
+    x, _ = D.equilibrium(prob, p, rtol=1e-11)
+    st = D.dense_gn_step(prob, x, p)
+    b = D.sgn_rhs(prob, x, p)
+    z0 = np.concatenate([st.dx, st.dp, st.dlam])
+    z, hist = D.polish_sgn_solution(prob, x, p, z0, b, sweeps=2)
+    ref = np.linalg.solve(D.sgn_matrix_dense(prob, x, p), b)
+    for sl in (slice(0, prob.n_x), slice(prob.n_x, prob.n_x + prob.n_p)):
+        assert np.linalg.norm(z[sl] - ref[sl]) <= 1e-9 * np.linalg.norm(ref[sl])
+    assert hist[-1] <= hist[0] and hist[-1] <= 1e-12
