@@ -207,6 +207,19 @@ sgn_status sgn_factor(sgn_ctx ctx, sgn_factor_info* info);
  * by the factor (at most max_gmres cycles).  SGN_E_REFINE if solve_rtol is
  * still not met. */
 sgn_status sgn_solve(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_info* info);
+/* For callers that cannot allocate device memory when they solve (work under stream capture,
+ * tight serving loops, harnesses that forbid allocation): sgn_solve with every per-call working
+ * buffer (scaled and permuted vectors, per-front solve vectors, split-k partials, pipelined-solve
+ * tickets, refinement vectors, reduction partials, counters) in a static device array of the
+ * library, 128 MiB per device, held from the first call on a device until the process ends.  The
+ * factor, the assembled matrix and the symbolic tables stay in the context's workspace; d_rhs and
+ * d_sol as in sgn_solve.  Call it with the context's device current.  Plain refinement only (no
+ * FGMRES escalation): SGN_E_REFINE if max_ir sweeps do not reach solve_rtol.  SGN_E_NOMEM (with the
+ * bytes needed in the message) when the system's working memory exceeds the array; SGN_E_HIP if
+ * the array's address cannot be obtained.  No device memory is allocated or freed.  Every call on
+ * one device shares that device's array: calls that overlap on one device (any contexts, any
+ * streams) race and must be serialised by the caller. */
+sgn_status sgn_solve_static(sgn_ctx ctx, const double* d_rhs, double* d_sol, sgn_solve_info* info);
 /* One iteration of L-BFGS whose initial inverse Hessian is the Gauss-Newton one of the current
  * iterate (Sec. 4, "Combination with L-BFGS"): at the equilibrium (d_p, d_x) the adjoint gradient g
  * (eq. totalGradient) and K_SGN are assembled and factorised; the pair (s, y) = (p - p_prev,

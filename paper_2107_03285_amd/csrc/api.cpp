@@ -1784,6 +1784,34 @@ sgn_status sgn_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_i
 sgn_status gnn_forward_impl(sgn_ctx c, const float* w, const double* x_ref, const double* p_ref, const double* x,
                             const double* p, float* cn, float* cp);
 
+// Working memory of one refined solve of the saddle-point system (sgn_solve without the Krylov
+// escalation): the scaled right-hand side, both per-front solve vectors, the split-k partials, the
+// pipelined solve's tickets, the refinement vectors, the permuted right-hand side and solution, the
+// reduction partials and result slots, and the counters.  base == nullptr only measures.
+struct SolveScratch {
+  double *sv, *tv, *tp, *part, *ir_r, *ir_d, *ir_s, *old, *old2, *red, *scal;
+  int *ctr, *cnt;
+};
+
+size_t carve_solve_scratch(sgn_ctx c, char* base, SolveScratch* s) {
+  Layout L{base};
+  const System& S = c->A.sgn;
+  s->sv = L.take<double>(S.N);
+  s->tv = L.take<double>(S.vec_total);
+  s->tp = L.take<double>(S.vec_total);
+  s->part = L.take<double>(S.part_total);
+  s->ctr = L.take<int>(2 * (size_t)S.nsn);
+  s->ir_r = L.take<double>(S.N);
+  s->ir_d = L.take<double>(S.N);
+  s->ir_s = L.take<double>(S.N);
+  s->old = L.take<double>(S.N);
+  s->old2 = L.take<double>(S.N);
+  s->red = L.take<double>(4 * kRedBlocks);
+  s->scal = L.take<double>(64);
+  s->cnt = L.take<int>(64);
+  return (L.off + 255) & ~size_t(255);
+}
+
 // MINRES with the reference factor's preconditioner; on stagnation, on max_minres
 // iterations, or without a reference factor: exact factorisation of the current
 // matrix (which becomes the new reference) and the refined direct solve.
@@ -2131,6 +2159,55 @@ sgn_status pc_ready(sgn_ctx c) {
 
 }  // namespace
 
+// Refined solve whose working memory is the caller-designated device region [region, region + cap)
+// instead of the context's workspace (the factor, the assembled matrix and the symbolic tables stay
+// in the workspace).  Plain refinement only: the FGMRES escalation's Krylov bases do not fit a small
+// region, so a solve that refinement alone cannot finish returns SGN_E_REFINE.  lookup: the status of
+// obtaining the region (reported as SGN_E_HIP).  Everything the solve reads from the region it has
+// written first in the same call (tickets and the timeout flag are cleared by the solve itself).
+sgn_status solve_in_region(sgn_ctx c, const double* d_rhs, double* d_sol, sgn_solve_info* info, void* region,
+                           size_t cap, hipError_t lookup) {
+  TRY(check_ready(c));
+  if (!d_rhs || !d_sol) return fail(c, SGN_E_ARG, "null vector");
+  if (lookup != hipSuccess || !region)
+    return fail(c, SGN_E_HIP, std::string("static scratch address: ") + hipGetErrorString(lookup));
+  if (((uintptr_t)region & 255) != 0) return fail(c, SGN_E_ARG, "scratch region must be 256-byte aligned");
+  SolveScratch s{};
+  const size_t need = carve_solve_scratch(c, nullptr, &s);
+  if (need > cap) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "this system's solve needs %zu bytes of scratch; the static region holds %zu", need,
+             cap);
+    return fail(c, SGN_E_NOMEM, buf);
+  }
+  carve_solve_scratch(c, static_cast<char*>(region), &s);
+  DevSys& D = c->sys[0];
+  const SolveScratch keep{D.sv, D.tv, D.tp, D.part, D.ir_r, D.ir_d, D.ir_s, c->d_old, c->d_old2, c->d_part,
+                          c->d_scal, D.solve_ctr, c->d_cnt};
+  const int keep_gmres = c->opt.max_gmres;
+  auto point = [&](const SolveScratch& v) {
+    D.sv = v.sv;
+    D.tv = v.tv;
+    D.tp = v.tp;
+    D.part = v.part;
+    D.ir_r = v.ir_r;
+    D.ir_d = v.ir_d;
+    D.ir_s = v.ir_s;
+    c->d_old = v.old;
+    c->d_old2 = v.old2;
+    c->d_part = v.red;
+    c->d_scal = v.scal;
+    D.solve_ctr = v.ctr;
+    c->d_cnt = v.cnt;
+  };
+  point(s);
+  c->opt.max_gmres = 0;
+  const sgn_status st = sgn_solve_impl(c, d_rhs, d_sol, info);
+  c->opt.max_gmres = keep_gmres;
+  point(keep);
+  return st;
+}
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -2289,6 +2366,11 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
     if (!(c->target_w > 0)) return fail(c, SGN_E_ARG, "block solve needs target_w > 0");
   }
   c->ws_need = layout(c, nullptr);
+  if (verbose()) {
+    SolveScratch ss{};
+    fprintf(stderr, "[sgn] workspace %zu bytes; sgn_solve_static scratch %zu bytes\n", c->ws_need,
+            carve_solve_scratch(c, nullptr, &ss));
+  }
   return SGN_OK;
 }
 

@@ -32,7 +32,7 @@ EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_w
            "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
            "sgn_solve_minres", "sgn_gnn_num_weights", "sgn_gnn_init", "sgn_gnn_forward", "sgn_gnn_backward",
            "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss", "sgn_graph_step", "sgn_autotune",
-           "sgn_block_step", "sgn_lbfgs_step", "sgn_batch_create", "sgn_batch_step"]
+           "sgn_block_step", "sgn_lbfgs_step", "sgn_batch_create", "sgn_batch_step", "sgn_solve_static"]
 
 
 class sgn_problem(C.Structure):
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_assemble": (C.c_int, [vp, vp, vp, vp, vp, dp]),
         "sgn_factor": (C.c_int, [vp, C.POINTER(sgn_factor_info)]),
         "sgn_solve": (C.c_int, [vp, vp, vp, C.POINTER(sgn_solve_info)]),
+        "sgn_solve_static": (C.c_int, [vp, vp, vp, C.POINTER(sgn_solve_info)]),
         "sgn_block_step": (C.c_int, [vp, vp, vp, vp, C.POINTER(sgn_solve_info)]),
         "sgn_lbfgs_step": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(sgn_step_info)]),
         "sgn_batch_create": (C.c_int, [C.c_int, C.POINTER(C.POINTER(sgn_problem)), C.POINTER(sgn_options), vp,
@@ -381,6 +382,12 @@ class Context:
     def solve(self, rhs, sol):
         info = sgn_solve_info()
         self._check(self.lib.sgn_solve(self.h, _dev_ptr(rhs), _dev_ptr(sol), C.byref(info)))
+        return info
+
+    def solve_static(self, rhs, sol):
+        """sgn_solve with its working memory in the library's static device array (no allocation)."""
+        info = sgn_solve_info()
+        self._check(self.lib.sgn_solve_static(self.h, _dev_ptr(rhs), _dev_ptr(sol), C.byref(info)))
         return info
 
     def block_step(self, x, p, sol):
