@@ -190,7 +190,8 @@ def main():
                     help="train and evaluate on the cantilever/plate family with s ~ U{5..20} (seeds 0.. for "
                          "training, 1000.. held out) instead of the three fixed small cantilevers")
     ap.add_argument("--held-seeds", type=int, default=3)
-    ap.add_argument("--max-side", type=int, default=20, help="skip family seeds with a larger s")
+    ap.add_argument("--max-side", type=int, default=20, help="skip training seeds of the family with a larger s")
+    ap.add_argument("--held-max-side", type=int, default=20, help="skip held-out seeds with a larger s")
     args = ap.parse_args()
     dev = "cuda:0"
     t0 = time.time()
@@ -198,7 +199,7 @@ def main():
         train = build_pairs(None, None, args.iters, dev,
                             problems=family_problems(range(args.train_seeds), args.max_side))
         held = build_pairs(None, None, args.iters, dev,
-                           problems=family_problems(range(1000, 1000 + args.held_seeds), args.max_side))
+                           problems=family_problems(range(1000, 1000 + args.held_seeds), args.held_max_side))
     else:
         train = build_pairs(TRAIN_MESHES, range(args.train_seeds), args.iters, dev)
         held = build_pairs([TRAIN_MESHES[-1]], range(1000, 1000 + args.held_seeds), args.iters, dev)
@@ -212,7 +213,8 @@ def main():
 
     report = {"n_weights": int(tr.w.numel()), "train_pairs": len(train), "held_pairs": len(held),
               "meshes": sorted({p.name for p, *_ in train}), "held_meshes": sorted({p.name for p, *_ in held}),
-              "family": bool(args.family), "max_side": args.max_side, "sgn_iterations_logged": args.iters,
+              "family": bool(args.family), "max_side": args.max_side, "held_max_side": args.held_max_side,
+              "sgn_iterations_logged": args.iters,
               "epochs": args.epochs, "lr": args.lr, "history": []}
     base_iters = [tr.minres_iterations(p, a, b, False) for p, a, b, _ in held]
     report["held_loss_untrained"] = held_loss()
