@@ -23,6 +23,9 @@ Modules:
                solve of the saddle-point system, objective and gradient; the
                variants of Sec. 4: block Gauss-Newton step (Appendix B) and
                L-BFGS initialised with the Gauss-Newton Hessian.
+  newton    -- the Sparse Newton step with inertia control (Sec. 4, eq. totalHessian;
+               Appendix A): second derivatives of lam^T c, the Newton saddle-point matrix,
+               the reduced Newton Hessian, the inertia test and diagonal regularisation.
   symbolic  -- K_SGN pattern, nested-dissection order, permuted CSR, etree.
   krylov    -- the stabilised saddle-point matrix and BiCGSTAB of the paper's robust fall-back
                solve (Sec. 5).
