@@ -81,6 +81,13 @@ enum { SGN_LDLT = 0, SGN_MINRES_LEARNED = 1, SGN_BICGSTAB = 2, SGN_BLOCK_GN = 3 
  * form [-df/dx^T; -df/dp^T; 0] (Appendix A), which gives the same dp and a
  * multiplier block shifted by the adjoint multiplier */
 enum { SGN_RHS_ADJOINT = 0, SGN_RHS_KKT = 1 };
+/* second derivatives in the saddle-point matrix: the Gauss-Newton blocks A = d2f/dx2, B = d2f/dp dx,
+ * C = d2f/dp2 (eq. sparseSystemGN; for the least-squares objective with a Tikhonov term this is also
+ * the generalised Gauss-Newton form of Sec. 4), or the Newton form of Appendix A: the Hessian of the
+ * Lagrangian f + lam^T c at the adjoint multipliers, whose saddle-point solve is the full Newton step
+ * (Sec. 4, eq. totalHessian); log-modulus parameters only, one problem, solver SGN_LDLT, rhs_kind
+ * SGN_RHS_ADJOINT, eps_x = eps_lambda = 0 (SGN_E_ARG otherwise) */
+enum { SGN_HESSIAN_GN = 0, SGN_HESSIAN_NEWTON = 1 };
 /* which system sgn_get_symbolic / sgn_get_sizes describe */
 enum { SGN_SYS_SGN = 0, SGN_SYS_KX = 1 };
 
@@ -132,6 +139,8 @@ typedef struct {
                                    default 8, else 1..8) */
   int max_bicgstab;             /* BiCGSTAB iterations of the SGN_BICGSTAB solver (default 50) */
   int lbfgs_m;                  /* curvature pairs kept by sgn_lbfgs_step (default 5, 0..32) */
+  int hessian;                  /* SGN_HESSIAN_GN (default) | SGN_HESSIAN_NEWTON, fixed at create
+                                   (the Newton form has a larger pattern) */
 } sgn_options;
 
 typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;
@@ -155,6 +164,8 @@ typedef struct {
   int halvings, newton_iters;
   double ms_rhs, ms_assemble, ms_factor, ms_solve, ms_linesearch;
   sgn_solve_info solve;
+  double delta;                 /* sgn_newton_step: diagonal regularisation of the accepted factor */
+  int inertia_trials;           /* sgn_newton_step: factorisations the inertia test took */
 } sgn_step_info;
 
 /* Stage measurements of the last calls (HIP events on the context's stream). */
@@ -276,6 +287,22 @@ sgn_status sgn_block_step(sgn_ctx ctx, const double* d_x, const double* d_p, dou
  * trial fails while |g^T dp| <= 1e-12 |f(0)| (stationary to working
  * precision) the call succeeds with alpha = 0 and leaves (p, x) unchanged. */
 sgn_status sgn_step(sgn_ctx ctx, double* d_p, double* d_x, sgn_step_info* info);
+/* One outer iteration of Sparse Newton with inertia control (Sec. 4, "Generalization to Arbitrary
+ * Objectives", eq. totalHessian; Appendix A, Theorem 2; Sec. 5, which tests positive definiteness on
+ * the null space of the constraint Jacobian by the inertia of the LDL^T factorisation and adds
+ * diagonal regularisation when it fails).  Needs a context created with hessian =
+ * SGN_HESSIAN_NEWTON (SGN_E_STATE otherwise).  At the equilibrium (d_p, d_x) (solved first if the
+ * context holds no Kx factor of it): lam = -Kx^-1 df/dx^T; the saddle-point matrix with
+ *   A = d2f/dx2 + d2(lam^T c)/dx2,  B = d2(lam^T c)/dp dx,  C = d2f/dp2 + d2(lam^T c)/dp2
+ * (element terms: the derivative of the element Hessian along lam, K_e lam_e, lam_e . g_e) is
+ * factorised; while its inertia is not (n_x + n_p, n_x, 0), or a pivot was perturbed, delta I is
+ * added to the x and p diagonal (which turns the reduced Hessian H into H + delta (I + S^T S)) and
+ * it is factorised again, delta taking 0, then 1e-4 (or a third of the delta of the last call that
+ * needed one, at least 1e-20), then eight times the previous value, up to 1e20 (SGN_E_PIVOT
+ * beyond).  The step solves that system with [0; -g; 0] (refined as sgn_solve); the line search and
+ * the stationary rule are those of sgn_step.  restart != 0 forgets the remembered delta.  info as
+ * for sgn_step plus delta and inertia_trials. */
+sgn_status sgn_newton_step(sgn_ctx ctx, double* d_p, double* d_x, int restart, sgn_step_info* info);
 
 /* ---- Learned-preconditioner path.  The paper names preconditioning of the
  * saddle-point system and iterative saddle-point solvers as future work

@@ -141,8 +141,10 @@ def variable_order(prob: Problem) -> np.ndarray:
     return perm
 
 
-def pattern_pairs(prob: Problem):
-    """Unique (row, col) pairs, row >= col, of the lower pattern in the original numbering."""
+def pattern_pairs(prob: Problem, newton: bool = False):
+    """Unique (row, col) pairs, row >= col, of the lower pattern in the original numbering.  newton:
+    the pattern of the Newton form (Appendix A; log-modulus parameters), whose x-x block couples the
+    DOFs of one element (the second derivatives of lam^T c) and whose x-p block has the Kp pattern."""
     d = prob.dim
     nx, npar = prob.n_x, prob.n_p
     lam0 = nx + npar
@@ -174,20 +176,25 @@ def pattern_pairs(prob: Problem):
         add(lam0 + R[m], nx + C[m])
     else:
         add(lam0 + np.arange(nx), nx + np.arange(nx))
+    if newton:
+        if prob.param_kind != P_LOGE:
+            raise ValueError("the Newton form is built for log-modulus parameters")
+        add(R[m], C[m])
+        add(dofs[freem], nx + E[freem])
     # all diagonals
     add(np.arange(N), np.arange(N))
     k = np.unique(np.concatenate(keys))
     return k // N, k % N
 
 
-def permuted_lower_csr(prob: Problem, perm: np.ndarray = None):
+def permuted_lower_csr(prob: Problem, perm: np.ndarray = None, newton: bool = False):
     """(rowptr int64, colind int32) of the lower triangle of P K P^T."""
     if perm is None:
         perm = variable_order(prob)
     N = perm.size
     inv = np.empty(N, dtype=np.int64)
     inv[perm] = np.arange(N)
-    r, c = pattern_pairs(prob)
+    r, c = pattern_pairs(prob, newton)
     nr, nc = inv[r], inv[c]
     hi = np.maximum(nr, nc)
     lo = np.minimum(nr, nc)

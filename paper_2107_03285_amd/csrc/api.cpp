@@ -198,6 +198,7 @@ struct sgn_ctx_s {
   const float* corr_par = nullptr;
   bool kx_valid = false;
   bool sgn_assembled = false;
+  double newton_delta_last = 0.0;     // regularisation of the last sgn_newton_step that needed one
   // L-BFGS memory (sgn_lbfgs_step): newest pair at lb_head - 1 (circular), curvature 1 / s^T y
   double* lb_s = nullptr;             // [lbfgs_m x n_p]
   double* lb_y = nullptr;             // [lbfgs_m x n_p]
@@ -501,7 +502,7 @@ void dev_dot_to(sgn_ctx c, int64_t n, const double* a, const double* b, double* 
 sgn_status run_element(sgn_ctx c, const double* x, const double* p, int mode, int* inverted) {
   const Analysis& A = c->A;
   launch_fill_i32(1, 0, c->d_cnt + 8, c->stream);
-  ElemArgs ea;
+  ElemArgs ea{};
   ea.dim = A.mesh.dim;
   ea.ne = A.mesh.n_elems;
   ea.param_kind = A.mesh.param_kind;
@@ -519,6 +520,10 @@ sgn_status run_element(sgn_ctx c, const double* x, const double* p, int mode, in
   ea.off_kp = A.off_kp;
   ea.off_energy = A.off_energy;
   ea.inverted = c->d_cnt + 8;
+  ea.lam = mode == 3 ? c->d_lam : nullptr;
+  ea.off_t = A.off_t;
+  ea.off_kl = A.off_kl;
+  ea.off_lg = A.off_lg;
   launch_element(ea, c->stream);
   HIPCHK(hipGetLastError());
   int inv = 0;
@@ -1398,13 +1403,42 @@ sgn_status objective_value(sgn_ctx c, const double* x, const double* p, double* 
 }
 
 // Assemble K_SGN at (x, p) and the rhs in boundary order into rhs_old (device).
+// lam = -Kx^-1 df/dx^T (the adjoint multipliers, Appendix A) with the Kx factor of the last
+// equilibrium; df/dx^T in c->d_fx on entry, lam in c->d_lam on exit
+sgn_status adjoint_multipliers(sgn_ctx c) {
+  const int64_t nx = c->A.mesh.n_x;
+  DevSys& K = c->sys[1];
+  launch_gather_perm(nx, K.perm, nullptr, c->d_fx, K.b, c->stream);
+  launch_axpby(nx, -1.0, K.b, 0.0, nullptr, K.b, c->stream);
+  const double keep = c->opt.solve_rtol;
+  c->opt.solve_rtol = 1e-14;
+  sgn_solve_info si{};
+  sgn_status s = refined_solve(c, 1, K.b, K.z, &si);
+  c->opt.solve_rtol = keep;
+  if (s != SGN_OK && s != SGN_E_REFINE) return s;
+  launch_scatter_perm(nx, K.perm, nullptr, K.z, c->d_lam, c->stream);
+  return SGN_OK;
+}
+
 sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rhs_old, double* grad, double* obj) {
   const Analysis& A = c->A;
   const int64_t nx = A.mesh.n_x, np = A.mesh.n_p, N = A.sgn.N;
+  const bool newton = A.newton;
   int inv = 0;
   HIPCHK(ensure_events(c, 0));
+  if (newton) {
+    // the Newton blocks contract the third derivatives with lam: solve for it first
+    if (!c->kx_valid) {
+      c->err = "the Newton form needs the Kx factor of sgn_equilibrium at this state";
+      return SGN_E_STATE;
+    }
+    launch_fill(nx, 0.0, c->d_fx, c->stream);
+    launch_objective_fx((int64_t)c->target_dof.size(), c->d_tdof, c->d_tval, x, c->target_w / (c->ell * c->ell),
+                        c->d_fx, c->stream);
+    TRY(adjoint_multipliers(c));
+  }
   HIPCHK(hipEventRecord(c->ev_a, c->stream));
-  TRY(run_element(c, x, p, 2, &inv));
+  TRY(run_element(c, x, p, newton ? 3 : 2, &inv));
   if (inv) {
     c->err = "inverted element in the given state";
     return SGN_E_INVERTED;
@@ -1443,18 +1477,9 @@ sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rh
       c->err = "adjoint right-hand side needs the Kx factor of sgn_equilibrium at this state";
       return SGN_E_STATE;
     }
-    // lam: Kx lam = -fx
-    DevSys& K = c->sys[1];
-    launch_gather_perm(nx, K.perm, nullptr, c->d_fx, K.b, c->stream);
-    launch_axpby(nx, -1.0, K.b, 0.0, nullptr, K.b, c->stream);
-    const double keep = c->opt.solve_rtol;
-    c->opt.solve_rtol = 1e-14;
-    sgn_solve_info si{};
-    sgn_status s = refined_solve(c, 1, K.b, K.z, &si);
-    c->opt.solve_rtol = keep;
-    if (s != SGN_OK && s != SGN_E_REFINE) return s;
-    launch_scatter_perm(nx, K.perm, nullptr, K.z, c->d_lam, c->stream);
-    // Kp^T lam through the assembled K_SGN: w = K [0; 0; lam], g = fp + w_p
+    if (!newton) TRY(adjoint_multipliers(c));  // the Newton form solved for lam before its element pass
+    // Kp^T lam through the assembled K_SGN: w = K [0; 0; lam], g = fp + w_p (the x-p block of the
+    // Newton form multiplies the zero x part)
     DevSys& D = c->sys[0];
     launch_fill(N, 0.0, c->d_old, c->stream);
     HIPCHK(hipMemcpyAsync(c->d_old + nx + np, c->d_lam, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -2101,7 +2126,7 @@ sgn_status enqueue_step(sgn_ctx c, const double* x, const double* p, double* rhs
   hipStream_t st = c->stream;
   launch_fill_i32(1, 0, c->d_cnt + 8, st);
   launch_fill_i32(1, 0, c->d_cnt + 12, st);
-  ElemArgs ea;
+  ElemArgs ea{};
   ea.dim = A.mesh.dim;
   ea.ne = A.mesh.n_elems;
   ea.param_kind = A.mesh.param_kind;
@@ -2292,6 +2317,19 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
     return fail(c, SGN_E_ARG, "max_bicgstab must be at least 1");
   if (!(c->opt.eps_x >= 0.0) || !(c->opt.eps_lambda >= 0.0)) return fail(c, SGN_E_ARG, "eps_x, eps_lambda must be >= 0");
   c->A.tune.seq_panels = c->opt.seq_panels == 0 ? kSolveSeqPanels : (c->opt.seq_panels < 0 ? 0 : c->opt.seq_panels);
+  if (c->opt.hessian != SGN_HESSIAN_GN && c->opt.hessian != SGN_HESSIAN_NEWTON)
+    return fail(c, SGN_E_ARG, "unknown hessian");
+  if (c->opt.hessian == SGN_HESSIAN_NEWTON) {
+    // Sec. 4 "Generalization to Arbitrary Objectives", Appendix A: the Lagrangian Hessian at the adjoint
+    // multipliers, which the adjoint right-hand side and the refined direct solve serve
+    if (pr->param_kind != SGN_P_LOGE) return fail(c, SGN_E_ARG, "the Newton form is built for log-modulus parameters");
+    if (pr->n_components > 1) return fail(c, SGN_E_ARG, "the Newton form takes one problem, not a batch");
+    if (c->opt.solver != SGN_LDLT) return fail(c, SGN_E_ARG, "the Newton form needs solver = SGN_LDLT");
+    if (c->opt.rhs_kind != SGN_RHS_ADJOINT) return fail(c, SGN_E_ARG, "the Newton form needs rhs_kind = SGN_RHS_ADJOINT");
+    if (c->opt.eps_x != 0.0 || c->opt.eps_lambda != 0.0)
+      return fail(c, SGN_E_ARG, "the Newton form regularises by itself (eps_x = eps_lambda = 0)");
+    c->A.newton = true;
+  }
   std::string err = analyse(c->A);
   if (!err.empty()) return fail(c, SGN_E_ARG, "symbolic analysis: " + err);
   err = build_gnn_graph(m, c->G);
@@ -2589,9 +2627,84 @@ sgn_status sgn_step(sgn_ctx c, double* d_p, double* d_x, sgn_step_info* info) {
   return line_search(c, d_p, d_x, sol + nx, t3, &si, info);
 }
 
+// Sparse Newton step with inertia control (Sec. 4 "Generalization to Arbitrary Objectives", eq.
+// totalHessian; Appendix A, Theorem 2; Sec. 5, the inertia test and diagonal regularisation): the
+// saddle-point matrix with the Lagrangian Hessian at the adjoint multipliers is factorised, and while
+// its inertia is not (n_x + n_p, n_x, 0) (or a pivot had to be perturbed) delta is added to the x and
+// p diagonal and it is factorised again: delta = 0 first, then kNewtonDelta0 (or a third of the last
+// step's delta, at least kNewtonDeltaMin), growing eightfold up to kNewtonDeltaMax.  The step solves
+// the regularised system with the adjoint right-hand side; the line search is the outer one.
+constexpr double kNewtonDelta0 = 1e-4, kNewtonDeltaMin = 1e-20, kNewtonDeltaMax = 1e20;
+
+sgn_status sgn_newton_step(sgn_ctx c, double* d_p, double* d_x, int restart, sgn_step_info* info) {
+  TRY(check_ready(c));
+  if (!d_p || !d_x) return fail(c, SGN_E_ARG, "null state");
+  if (!c->A.newton) return fail(c, SGN_E_STATE, "sgn_newton_step needs a context created with hessian = SGN_HESSIAN_NEWTON");
+  const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p;
+  if (restart) c->newton_delta_last = 0.0;
+  sgn_step_info si{};
+  double t0 = now_ms();
+  if (!c->kx_valid) {
+    sgn_status s = equilibrium_impl(c, d_p, d_x, nullptr);
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  double f0 = 0;
+  double* rhs = c->d_srhs;
+  double* sol = c->d_ssol;
+  {
+    sgn_status s = assemble_impl(c, d_x, d_p, rhs, c->d_g, &f0);
+    if (s != SGN_OK) return fail(c, s, c->err);
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double t1 = now_ms();
+  si.ms_assemble = t1 - t0;
+  const System& S = c->A.sgn;
+  DevSys& D = c->sys[0];
+  const double tol = D.prec ? 1e-12 : 1e-14;
+  double delta = 0.0;
+  const double first = c->newton_delta_last > 0.0 ? std::max(kNewtonDeltaMin, c->newton_delta_last / 3.0) : kNewtonDelta0;
+  for (int trial = 1;; ++trial) {
+    if (trial > 1) {  // the matrix of this delta from the element buffer: same arithmetic every trial
+      launch_gather_slots((int64_t)S.colind.size(), D.slot_ptr, D.slot_src, c->d_ebuf, D.vals, c->stream);
+      launch_diag_add(S.N, D.rowptr, D.diag_kind, c->target_w / (c->ell * c->ell), c->mu_reg, 0.0, 0.0, D.vals,
+                      c->stream);
+      launch_diag_add(S.N, D.rowptr, D.diag_kind, 0.0, delta, delta, 0.0, D.vals, c->stream);
+      D.current = false;
+    }
+    sgn_factor_info fi{};
+    sgn_status s = factor_dispatch(c, 0, tol, &fi);
+    if (s != SGN_OK) return fail(c, s, c->err);
+    si.inertia_trials = trial;
+    if (fi.n_pos == nx + np && fi.n_neg == nx && fi.n_zero == 0 && fi.n_perturbed == 0) break;
+    delta = trial == 1 ? first : delta * 8.0;
+    if (delta > kNewtonDeltaMax) return fail(c, SGN_E_PIVOT, "no diagonal regularisation up to 1e20 gives the inertia of a minimum");
+  }
+  if (delta > 0.0) c->newton_delta_last = delta;
+  si.delta = delta;
+  HIPCHK(hipMemcpyAsync(c->d_x_fac, d_x, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_p_fac, d_p, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double t2 = now_ms();
+  si.ms_factor = t2 - t1;
+  {
+    sgn_status s = sgn_solve_impl(c, rhs, sol, &si.solve);
+    if (s != SGN_OK) return s;
+  }
+  double t3 = now_ms();
+  si.ms_solve = t3 - t2;
+  double v[2];
+  dev_dot(c, np, c->d_g, sol + nx, 12);
+  dev_dot(c, np, c->d_g, c->d_g, 13);
+  TRY(read_scalars(c, 12, 2, v));
+  si.gtdp = v[0];
+  si.grad_norm = std::sqrt(v[1]);
+  si.f0 = f0;
+  return line_search(c, d_p, d_x, sol + nx, t3, &si, info);
+}
+
 sgn_status sgn_lbfgs_step(sgn_ctx c, double* d_p, double* d_x, int restart, sgn_step_info* info) {
   TRY(check_ready(c));
   if (!d_p || !d_x) return fail(c, SGN_E_ARG, "null state");
+  if (c->A.newton) return fail(c, SGN_E_STATE, "L-BFGS is initialised with the Gauss-Newton Hessian (hessian = SGN_HESSIAN_GN)");
   if (c->opt.solver != SGN_LDLT && c->opt.solver != SGN_BICGSTAB)
     return fail(c, SGN_E_STATE, "L-BFGS applies its initial inverse Hessian by the direct solve (SGN_LDLT or SGN_BICGSTAB)");
   const int64_t nx = c->A.mesh.n_x, np = c->A.mesh.n_p, N = c->A.sgn.N;
@@ -3045,6 +3158,7 @@ sgn_status sgn_graph_step(sgn_ctx c, const double* d_x, const double* d_p, doubl
                           double* h_rel) {
   TRY(check_ready(c));
   if (!d_x || !d_p || !d_rhs || !d_sol || n_ir < 0 || n_ir > 16) return fail(c, SGN_E_ARG, "invalid argument");
+  if (c->A.newton) return fail(c, SGN_E_STATE, "the captured step assembles the Gauss-Newton form");
   hipStream_t user = c->stream;
   if (!c->gstream) HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
   const void* key[4] = {d_x, d_p, d_rhs, d_sol};

@@ -54,7 +54,14 @@ __device__ inline void inverse(const double (&M)[D][D], double dt, double (&R)[D
   }
 }
 
-template <int D>
+// Newton form (mode 3, log-modulus parameters), with lam_e the element's entries of the multipliers:
+// the x-x block of d2(lam.g_e) is the derivative of the Hessian along V = sum_b lam_b w_b^T, column by
+// column from the second derivative of P along the rank-one U = e_c w^T and V (G = F^-T):
+//   d2P[U, V] = (lam ln J - mu)(G V^T G U^T G + G U^T G V^T G)
+//               - lam (tr(F^-1 V) G U^T G + tr(F^-1 V F^-1 U) G + tr(F^-1 U) G V^T G),
+// symmetric in U and V; the x-p column is K_e lam_e and the p-p entry lam_e . g_e (both moduli scale
+// with exp(p_e)).
+template <int D, bool NEWTON>
 __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
   constexpr int NV = D + 1;
   constexpr int ND = NV * D;
@@ -115,9 +122,18 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
   double P[D][D];
   for (int i = 0; i < D; ++i)
     for (int j = 0; j < D; ++j) P[i][j] = mu * (F[i][j] - Fi[j][i]) + lam * lnJ * Fi[j][i];
+  // multipliers of the element's DOFs (Newton form; 0 on fixed components)
+  double lv[NEWTON ? ND : 1];
+  if constexpr (NEWTON) {
+    for (int v = 0; v < NV; ++v) {
+      const int f = a.efdof[(int64_t)e * NV + v];
+      for (int c = 0; c < D; ++c) lv[v * D + c] = f >= 0 ? a.lam[f + c] : 0.0;
+    }
+  }
   // G = V0 P Dm^-T : G[c][k] = V0 sum_j P[c][j] Dmi[k][j]
   {
     double g0[D];
+    double lg = 0.0;
     for (int c = 0; c < D; ++c) g0[c] = 0.0;
     for (int k = 0; k < D; ++k)
       for (int c = 0; c < D; ++c) {
@@ -126,11 +142,56 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
         acc *= V0;
         out(a.off_grad + (k + 1) * D + c) = acc;
         g0[c] -= acc;
+        if constexpr (NEWTON) lg += acc * lv[(k + 1) * D + c];
       }
     for (int c = 0; c < D; ++c) out(a.off_grad + c) = g0[c];
+    if constexpr (NEWTON) {
+      for (int c = 0; c < D; ++c) lg += g0[c] * lv[c];
+      out(a.off_lg) = lg;
+    }
   }
   if (a.mode == 1) return;
   const double cA = mu - lam * lnJ;
+  // Newton form: V, W = G V^T G, tr(F^-1 V) and R = F^-1 V F^-1
+  double W[D][D], R[D][D], trV = 0.0, kl[NEWTON ? ND : 1];
+  if constexpr (NEWTON) {
+    double V[D][D];
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < D; ++k) acc += (lv[(k + 1) * D + i] - lv[i]) * Dmi[k][j];
+        V[i][j] = acc;  // sum over nodes b of lam_b[i] w_b[j], w_0 = -(sum of the rows of Dm^-1)
+      }
+    double Q[D][D];  // F^-1 V
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < D; ++k) acc += Fi[i][k] * V[k][j];
+        Q[i][j] = acc;
+      }
+    for (int i = 0; i < D; ++i) trV += Q[i][i];
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < D; ++k) acc += Q[i][k] * Fi[k][j];
+        R[i][j] = acc;
+      }
+    // W = G V^T G: W[i][j] = sum_{q,r} Fi[q][i] V[r][q] Fi[j][r]
+    double VG[D][D];  // V^T G : VG[q][j] = sum_r V[r][q] Fi[j][r]
+    for (int q = 0; q < D; ++q)
+      for (int j = 0; j < D; ++j) {
+        double acc = 0.0;
+        for (int r = 0; r < D; ++r) acc += V[r][q] * Fi[j][r];
+        VG[q][j] = acc;
+      }
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double acc = 0.0;
+        for (int q = 0; q < D; ++q) acc += Fi[q][i] * VG[q][j];
+        W[i][j] = acc;
+      }
+    for (int r = 0; r < ND; ++r) kl[r] = 0.0;
+  }
   for (int b = 0; b < NV; ++b) {
     // w = d(Dm^-1 row) for node b: dF = e_cb w^T
     double w[D];
@@ -168,10 +229,41 @@ __global__ void __launch_bounds__(128) k_element(ElemArgs a) {
           acc *= V0;
           out(((k + 1) * D + c) * ND + col) = acc;
           h0[c] -= acc;
+          if constexpr (NEWTON) kl[(k + 1) * D + c] += acc * lv[col];
         }
       for (int c = 0; c < D; ++c) out(c * ND + col) = h0[c];
+      if constexpr (NEWTON) {
+        for (int c = 0; c < D; ++c) kl[c] += h0[c] * lv[col];
+        // d2P[U, V] for U = e_cb w^T
+        double Ww[D];
+        for (int i = 0; i < D; ++i) {
+          double acc = 0.0;
+          for (int q = 0; q < D; ++q) acc += W[i][q] * w[q];
+          Ww[i] = acc;
+        }
+        double trVU = 0.0;  // tr(F^-1 V F^-1 U) = w^T R e_cb
+        for (int q = 0; q < D; ++q) trVU += w[q] * R[q][cb];
+        double T[D][D];
+        for (int i = 0; i < D; ++i)
+          for (int j = 0; j < D; ++j)
+            T[i][j] = -cA * (Ww[i] * Fi[j][cb] + Fw[i] * W[cb][j]) -
+                      lam * (trV * Fw[i] * Fi[j][cb] + trVU * Fi[j][i] + tr * W[i][j]);
+        double t0[D];
+        for (int c = 0; c < D; ++c) t0[c] = 0.0;
+        for (int k = 0; k < D; ++k)
+          for (int c = 0; c < D; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < D; ++j) acc += T[c][j] * Dmi[k][j];
+            acc *= V0;
+            out(a.off_t + ((k + 1) * D + c) * ND + col) = acc;
+            t0[c] -= acc;
+          }
+        for (int c = 0; c < D; ++c) out(a.off_t + c * ND + col) = t0[c];
+      }
     }
   }
+  if constexpr (NEWTON)
+    for (int r = 0; r < ND; ++r) out(a.off_kl + r) = kl[r];
   if (a.param_kind == 1) {
     // d(grad)/dX along each rest DOF: Dm moves, so dDm^-1 = -Dm^-1 dDm Dm^-1,
     // dF = -F dDm Dm^-1, dV0 = V0 tr(Dm^-1 dDm), dG = dV0 P Dm^-T + V0 dP Dm^-T + V0 P d(Dm^-T)
@@ -525,8 +617,13 @@ inline unsigned grid_for(int64_t n, int bs, int64_t cap = 65536) {
 void launch_element(const ElemArgs& a, hipStream_t s) {
   if (a.ne <= 0) return;
   const unsigned g = (unsigned)((a.ne + 127) / 128);
-  if (a.dim == 2) k_element<2><<<g, 128, 0, s>>>(a);
-  else k_element<3><<<g, 128, 0, s>>>(a);
+  if (a.mode == 3) {
+    if (a.dim == 2) k_element<2, true><<<g, 128, 0, s>>>(a);
+    else k_element<3, true><<<g, 128, 0, s>>>(a);
+  } else {
+    if (a.dim == 2) k_element<2, false><<<g, 128, 0, s>>>(a);
+    else k_element<3, false><<<g, 128, 0, s>>>(a);
+  }
 }
 
 void launch_gather_slots(int64_t nnz, const int64_t* ptr, const int32_t* src, const double* ebuf, double* vals,

@@ -45,7 +45,7 @@ __host__ __device__ inline bool update_tile(int64_t lt, int64_t R, int64_t ct, i
 
 // ---------------------------------------------------------------- element + assembly
 struct ElemArgs {
-  int dim, ne, param_kind, mode;  // mode 0 energy, 1 energy+gradient, 2 + Hessian (+ Kp)
+  int dim, ne, param_kind, mode;  // mode 0 energy, 1 energy+gradient, 2 + Hessian (+ Kp), 3 + Newton terms
   const int32_t* elems;           // [ne*(dim+1)]
   const int32_t* efdof;           // [ne*(dim+1)] free DOF of each element node, -1 fixed
   const double* rest;             // [n_nodes*dim]
@@ -55,6 +55,8 @@ struct ElemArgs {
   double* ebuf;
   int stride, off_grad, off_kp, off_energy;
   int* inverted;                  // counter of elements with J <= 0
+  const double* lam;              // mode 3: multipliers [n_x] (free-DOF order)
+  int off_t, off_kl, off_lg;      // mode 3: d2(lam.g)/dx2, K lam, lam.g in the element buffer
 };
 void launch_element(const ElemArgs& a, hipStream_t s);
 // vals[t] = sum of ebuf[src] over the slot's sources (fixed order)

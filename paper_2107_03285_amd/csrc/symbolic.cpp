@@ -554,6 +554,14 @@ std::string analyse(Analysis& A) {
   A.off_kp = A.off_grad + A.nd;
   A.off_energy = A.off_kp + (m.param_kind == 1 ? A.nd * A.nd : 0);
   A.stride = (A.off_energy + 1 + d - 1) / d * d;  // padded to whole coordinate groups
+  A.off_t = A.off_kl = A.off_lg = -1;
+  if (A.newton) {
+    if (m.param_kind != 0) return "the Newton form is built for log-modulus parameters";
+    A.off_t = A.stride;
+    A.off_kl = A.off_t + A.nd * A.nd;
+    A.off_lg = A.off_kl + A.nd;
+    A.stride = (A.off_lg + 1 + d - 1) / d * d;
+  }
 
   NdResult nd = nested_dissection(m);
   A.node_order = nd.order;
@@ -640,9 +648,11 @@ std::string analyse(Analysis& A) {
               int64_t B_ = m.fdof[vb] + cb;
               add(lam0 + A_, B_);
               if (m.param_kind == 1) add(lam0 + A_, nx + B_);
+              if (A.newton) add(A_, B_);
             }
           }
           if (m.param_kind == 0) add(lam0 + A_, nx + e);
+          if (A.newton) add(A_, nx + e);
         }
       }
     if (m.param_kind == 2)
@@ -674,6 +684,12 @@ std::string analyse(Analysis& A) {
                 if (s2 < 0) return "missing Kp slot";
                 contrib.emplace_back(s2, (int32_t)ebuf_index(A.off_kp + la * A.nd + lb, e, m.n_elems, d));
               }
+              // x-x of the Newton form: each lower entry takes one of the two symmetric values
+              if (A.newton && S.iperm[A_] >= S.iperm[B_]) {
+                int64_t s3 = find_slot(S, S.iperm[A_], S.iperm[B_]);
+                if (s3 < 0) return "missing x-x slot";
+                contrib.emplace_back(s3, (int32_t)ebuf_index(A.off_t + la * A.nd + lb, e, m.n_elems, d));
+              }
             }
           }
           if (m.param_kind == 0) {
@@ -681,7 +697,18 @@ std::string analyse(Analysis& A) {
             if (sl < 0) return "missing Kp slot";
             contrib.emplace_back(sl, (int32_t)ebuf_index(A.off_grad + la, e, m.n_elems, d));
           }
+          if (A.newton) {
+            int64_t sl = find_slot(S, S.iperm[A_], S.iperm[nx + e]);
+            if (sl < 0) return "missing x-p slot";
+            contrib.emplace_back(sl, (int32_t)ebuf_index(A.off_kl + la, e, m.n_elems, d));
+          }
         }
+      }
+    if (A.newton)
+      for (int e = 0; e < m.n_elems; ++e) {
+        int64_t sl = find_slot(S, S.iperm[nx + e], S.iperm[nx + e]);
+        if (sl < 0) return "missing p-p slot";
+        contrib.emplace_back(sl, (int32_t)ebuf_index(A.off_lg, e, m.n_elems, d));
       }
     if ((double)m.n_elems * A.stride > 2147483000.0) return "element buffer index overflow";
     S.slot_ptr.assign(nnz + 1, 0);

@@ -150,12 +150,19 @@ inline int64_t ebuf_index(int64_t j, int64_t e, int64_t n_elems, int g) {
 struct Analysis {
   Mesh mesh;
   Tuning tune;
+  // Newton form of the saddle-point system (Appendix A; log-modulus parameters only): the objective's
+  // blocks plus the second derivatives of lambda^T c, so the x-x block takes the Kx pattern, the x-p
+  // block the Kp pattern and the p-p diagonal the element term; false: the Gauss-Newton pattern
+  bool newton = false;
   std::vector<int64_t> node_order;  // free nodes in ND order
   System sgn, kx;
   // element buffer layout: values in groups of dim (the coordinates of one node), group-major:
   // value j of element e at ebuf_index(j, e, n_elems, dim); stride is padded to a multiple of dim
   int nd = 0;              // dofs per element (d+1)*d
   int off_hess = 0, off_grad = 0, off_kp = 0, off_energy = 0, stride = 0;
+  // Newton form only (else -1): d2(lam.g_e)/dx2 [nd*nd], K_e lam_e [nd] (= d2(lam.g_e)/dx dp_e for
+  // log-modulus parameters) and lam_e.g_e (= d2(lam.g_e)/dp_e2)
+  int off_t = -1, off_kl = -1, off_lg = -1;
 };
 
 // Runs the whole host analysis.  Returns an empty string on success, else an

@@ -24,6 +24,7 @@ SGN_P_LOGE, SGN_P_REST_POS, SGN_P_NODAL_FORCE = 0, 1, 2
 SGN_FP64, SGN_FP32_IR = 0, 1
 SGN_LDLT, SGN_MINRES_LEARNED, SGN_BICGSTAB, SGN_BLOCK_GN = 0, 1, 2, 3
 SGN_RHS_ADJOINT, SGN_RHS_KKT = 0, 1
+SGN_HESSIAN_GN, SGN_HESSIAN_NEWTON = 0, 1
 SGN_SYS_SGN, SGN_SYS_KX = 0, 1
 
 EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_workspace", "sgn_set_targets",
@@ -32,7 +33,8 @@ EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_w
            "sgn_destroy", "sgn_set_pc_correction", "sgn_spmv", "sgn_pc_apply", "sgn_pc_forward", "sgn_pc_grad",
            "sgn_solve_minres", "sgn_gnn_num_weights", "sgn_gnn_init", "sgn_gnn_forward", "sgn_gnn_backward",
            "sgn_adam", "sgn_set_pc_weights", "sgn_pc_train_loss", "sgn_graph_step", "sgn_autotune",
-           "sgn_block_step", "sgn_lbfgs_step", "sgn_batch_create", "sgn_batch_step", "sgn_solve_static"]
+           "sgn_block_step", "sgn_lbfgs_step", "sgn_batch_create", "sgn_batch_step", "sgn_solve_static",
+           "sgn_newton_step"]
 
 
 class sgn_problem(C.Structure):
@@ -52,7 +54,8 @@ class sgn_options(C.Structure):
                 ("eps_x", C.c_double), ("eps_lambda", C.c_double), ("max_newton", C.c_int),
                 ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int),
                 ("profile", C.c_int), ("max_gmres", C.c_int), ("outer_panels", C.c_int * 3),
-                ("seq_panels", C.c_int), ("max_bicgstab", C.c_int), ("lbfgs_m", C.c_int)]
+                ("seq_panels", C.c_int), ("max_bicgstab", C.c_int), ("lbfgs_m", C.c_int),
+                ("hessian", C.c_int)]
 
 
 class sgn_stats(C.Structure):
@@ -81,7 +84,8 @@ class sgn_step_info(C.Structure):
     _fields_ = [("alpha", C.c_double), ("f0", C.c_double), ("f1", C.c_double), ("grad_norm", C.c_double),
                 ("gtdp", C.c_double), ("halvings", C.c_int), ("newton_iters", C.c_int),
                 ("ms_rhs", C.c_double), ("ms_assemble", C.c_double), ("ms_factor", C.c_double),
-                ("ms_solve", C.c_double), ("ms_linesearch", C.c_double), ("solve", sgn_solve_info)]
+                ("ms_solve", C.c_double), ("ms_linesearch", C.c_double), ("solve", sgn_solve_info),
+                ("delta", C.c_double), ("inertia_trials", C.c_int)]
 
 
 _lib = None
@@ -115,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "sgn_solve_static": (C.c_int, [vp, vp, vp, C.POINTER(sgn_solve_info)]),
         "sgn_block_step": (C.c_int, [vp, vp, vp, vp, C.POINTER(sgn_solve_info)]),
         "sgn_lbfgs_step": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(sgn_step_info)]),
+        "sgn_newton_step": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(sgn_step_info)]),
         "sgn_batch_create": (C.c_int, [C.c_int, C.POINTER(C.POINTER(sgn_problem)), C.POINTER(sgn_options), vp,
                                        C.POINTER(vp)]),
         "sgn_batch_step": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(sgn_step_info)]),
@@ -462,6 +467,12 @@ class Context:
         """One SGN-initialised L-BFGS iteration (updates p and x in place)."""
         info = sgn_step_info()
         self._check(self.lib.sgn_lbfgs_step(self.h, _dev_ptr(p), _dev_ptr(x), int(bool(restart)), C.byref(info)))
+        return info
+
+    def newton_step(self, p, x, restart=False):
+        """One Sparse Newton iteration with inertia control (updates p and x in place)."""
+        info = sgn_step_info()
+        self._check(self.lib.sgn_newton_step(self.h, _dev_ptr(p), _dev_ptr(x), int(bool(restart)), C.byref(info)))
         return info
 
     def values(self, which=SGN_SYS_SGN):

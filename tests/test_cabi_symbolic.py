@@ -111,6 +111,28 @@ def test_symbolic_structure_is_bit_exact(name):
     assert sz["n"] == 2 * prob.n_x + prob.n_p and sz["nnz"] == orp[-1]
 
 
+@pytest.mark.parametrize("name", ["grid21", "cant4x2x2"])
+def test_newton_form_structure_is_bit_exact(name):
+    """The Newton form (hessian = SGN_HESSIAN_NEWTON) adds the x-x and x-p couplings of every element
+    to the pattern without changing the variable order; its supernodal structure still holds it
+    (sgn_create would fail on a missing slot)."""
+    _lib()
+    prob = CASES[name]()
+    ctx = sgn.Context(prob, sgn.default_options(hessian=sgn.SGN_HESSIAN_NEWTON))
+    perm, etree, rowptr, colind = ctx.symbolic(sgn.SGN_SYS_SGN)
+    operm = S.variable_order(prob)
+    orp, oci = S.permuted_lower_csr(prob, operm, newton=True)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(rowptr, orp) and np.array_equal(colind, oci)
+    assert np.array_equal(etree, S.etree_liu(orp, oci))
+    grp, _ = S.permuted_lower_csr(prob, operm)
+    assert orp[-1] > grp[-1]
+    # the Kx system is the same as in the Gauss-Newton form
+    gn = sgn.Context(prob)
+    for a, b in zip(ctx.symbolic(sgn.SGN_SYS_KX), gn.symbolic(sgn.SGN_SYS_KX)):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.slow
 def test_symbolic_structure_is_bit_exact_at_200k_dof():
     _lib()
