@@ -363,6 +363,35 @@ def variants_leg(sgn, dev, steps):
     return out
 
 
+def newton_leg(sgn, prob, x, p, dev):
+    """One Sparse Newton iteration with inertia control (Sec. 4 eq. totalHessian, Appendix A, Sec. 5;
+    FP32 factors + FP64 refinement) beside one Gauss-Newton iteration, both from the workload's
+    equilibrium: the direction's stages (for Newton: the multipliers, the Newton-form assembly, every
+    factorisation the inertia test took, the refined solve) and the whole iteration with its line
+    search."""
+    import torch
+    out = {}
+    for label, hess in (("gauss_newton", sgn.SGN_HESSIAN_GN), ("newton", sgn.SGN_HESSIAN_NEWTON)):
+        ctx = sgn.Context(prob, sgn.default_options(precision=sgn.SGN_FP32_IR, hessian=hess)).allocate(dev)
+        ctx.set_targets(prob.target_val, prob.length_scale)
+        xe, pe = x.clone(), p.clone()
+        ctx.equilibrium(pe, xe)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.newton_step(pe, xe, restart=True) if hess == sgn.SGN_HESSIAN_NEWTON else ctx.step(pe, xe)
+        torch.cuda.synchronize()
+        out[label] = {"ms_iteration": 1e3 * (time.perf_counter() - t0),
+                      "ms_direction": info.ms_assemble + info.ms_factor + info.ms_solve,
+                      "ms_assemble": info.ms_assemble, "ms_factor": info.ms_factor, "ms_solve": info.ms_solve,
+                      "alpha": info.alpha, "f0": info.f0, "f1": info.f1, "grad_norm": info.grad_norm,
+                      "rel_res": info.solve.rel_res}
+        if hess == sgn.SGN_HESSIAN_NEWTON:
+            out[label].update(inertia_trials=info.inertia_trials, delta=info.delta)
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def bicgstab_leg(sgn, prob, x, p, dev, steps, dp_ref):
     """BiCGSTAB on K preconditioned by the FP32 LDL^T of the stabilised matrix (eps_x = eps_lambda =
     1e-6, Sec. 5) at the workload's size: one direction (assembly + factorisation + BiCGSTAB)."""
@@ -616,7 +645,7 @@ def main():
                 "avg_launch_us": r["update_avg_us"], "flops_per_launch": r["update_flops_per_launch"]}
     if roof is not None:
         roof["stages"] = stage_rooflines(results)
-    learned = bicg = variants = None
+    learned = bicg = variants = newton = None
     if not args.no_variants:
         nx, npar = prob.n_x, prob.n_p
         dp_ref = sols["fp64"][nx:nx + npar] if "fp64" in sols else None
@@ -626,6 +655,9 @@ def main():
         log("[bench] BiCGSTAB leg")
         bicg = bicgstab_leg(sgn, prob, x, p, dev, max(2, args.steps // 4), dp_ref)
         log(f"[bench] BiCGSTAB: {bicg}")
+        log("[bench] Sparse Newton leg")
+        newton = newton_leg(sgn, prob, x, p, dev)
+        log(f"[bench] Newton vs Gauss-Newton: {newton}")
         log("[bench] block-solve leg")
         variants = variants_leg(sgn, dev, max(3, args.steps // 2))
         log(f"[bench] variants: {variants}")
@@ -658,6 +690,7 @@ def main():
         "learned_pc": learned,
         "bicgstab_stabilised": bicg,
         "block_solve": variants,
+        "newton_vs_gauss_newton": newton,
         "batched_2d_256": batch,
         "cpu_baseline": cpu,
     }

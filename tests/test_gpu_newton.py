@@ -44,6 +44,7 @@ def _problem(name):
             "grid5": lambda: si.problem_2d(5, seed=0),
             "grid7": lambda: si.problem_2d(7, seed=1),
             "cant4x2x2": lambda: si.problem_3d(4, 2, 2, 0.5, seed=0),
+            "cant20x5x5": lambda: si.problem_3d(20, 5, 5, 0.2, seed=0),  # 2,160 states, 2,500 parameters
         }[name]
         prob = D.setup_targets(mk())
         p = prob.p_init()
@@ -98,7 +99,7 @@ def test_newton_matrix_matches_oracle(name):
 
 
 @pytest.mark.parametrize("precision", [sgn.SGN_FP64, sgn.SGN_FP32_IR])
-@pytest.mark.parametrize("name", ["grid5", "grid7", "cant4x2x2"])
+@pytest.mark.parametrize("name", ["grid5", "grid7", "cant4x2x2", "cant20x5x5"])
 def test_newton_step_matches_oracle(name, precision):
     prob, p, x = _problem(name)
     ctx = _ctx(prob, precision=precision)
