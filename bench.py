@@ -303,6 +303,28 @@ def learned_pc_leg(sgn, prob, x, p, dp, dev, steps, fractions=(1.0, 0.05)):
             row[label] = {"steps_per_s": len(times) / sum(times), "ms_per_step": 1e3 * sum(times) / len(times),
                           "minres_iterations": iters[-1], "fallback_rate": float(np.mean(fb)),
                           "rel_res_max": max(res)}
+        # the ablation without a reference factor: MINRES preconditioned by blockdiag(|B_i|^-1) of the
+        # next system's own node-group blocks (its set-up is inside the timed solve)
+        ob = sgn.default_options(precision=sgn.SGN_FP32_IR, solver=sgn.SGN_MINRES_LEARNED,
+                                 rhs_kind=sgn.SGN_RHS_KKT, max_minres=300, pc_kind=sgn.SGN_PC_BLOCK)
+        bctx = sgn.Context(prob, ob).allocate(dev)
+        bctx.set_targets(prob.target_val, prob.length_scale)
+        times, iters, fb, res = [], [], [], []
+        for k in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bctx.assemble(x1, p1, rhs)
+            info = bctx.solve_minres(rhs, sol)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            iters.append(int(info.sweeps))
+            fb.append(int(info.fallback))
+            res.append(info.rel_res)
+        row["block_diagonal_no_reference"] = {
+            "steps_per_s": len(times) / sum(times), "ms_per_step": 1e3 * sum(times) / len(times),
+            "minres_iterations": iters[-1], "fallback_rate": float(np.mean(fb)), "rel_res_max": max(res)}
+        del bctx
+        torch.cuda.empty_cache()
         out["fractions"][str(t0_)] = row
         log(f"[bench] learned-PC t = {t}: {row}")
     del ctx

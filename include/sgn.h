@@ -88,6 +88,10 @@ enum { SGN_RHS_ADJOINT = 0, SGN_RHS_KKT = 1 };
  * (Sec. 4, eq. totalHessian); log-modulus parameters only, one problem, solver SGN_LDLT, rhs_kind
  * SGN_RHS_ADJOINT, eps_x = eps_lambda = 0 (SGN_E_ARG otherwise) */
 enum { SGN_HESSIAN_GN = 0, SGN_HESSIAN_NEWTON = 1 };
+/* preconditioner of sgn_solve_minres: the node-block preconditioner built on the reference factor
+ * (below), or the block-diagonal ablation without a reference factor, M^-1 = S blockdiag_i(|B_i|^-1) S
+ * with B_i the diagonal block of S K S over node group i (eigen-absolute value, no corrections) */
+enum { SGN_PC_FACTOR = 0, SGN_PC_BLOCK = 1 };
 /* which system sgn_get_symbolic / sgn_get_sizes describe */
 enum { SGN_SYS_SGN = 0, SGN_SYS_KX = 1 };
 
@@ -141,6 +145,7 @@ typedef struct {
   int lbfgs_m;                  /* curvature pairs kept by sgn_lbfgs_step (default 5, 0..32) */
   int hessian;                  /* SGN_HESSIAN_GN (default) | SGN_HESSIAN_NEWTON, fixed at create
                                    (the Newton form has a larger pattern) */
+  int pc_kind;                  /* SGN_PC_FACTOR (default) | SGN_PC_BLOCK, fixed at create */
 } sgn_options;
 
 typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;

@@ -261,6 +261,52 @@ class Preconditioner:
         return gn, gp
 
 
+class BlockDiagonalPreconditioner:
+    """The ablation without a reference factor: M = S^-1 blockdiag_i(|B_i|) S^-1 with S the symmetric
+    equilibration of the current matrix and B_i its diagonal block (of S K S) over node group i;
+    |B_i| = V |Lambda| V^T from the symmetric eigendecomposition B_i = V Lambda V^T.  SPD whenever no
+    B_i is singular.  Apply: M^-1 v = S blockdiag(|B_i|^-1) S v (user order)."""
+
+    def __init__(self, prob: Problem, K: np.ndarray):
+        self.prob = prob
+        self.perm = variable_order(prob)
+        self.starts, self.nodes = node_groups(prob)
+        Kn = K[np.ix_(self.perm, self.perm)]
+        self.S = equilibration(Kn)
+        Ks = self.S[:, None] * Kn * self.S[None, :]
+        self.blocks = []
+        for g in range(len(self.starts) - 1):
+            a, b = int(self.starts[g]), int(self.starts[g + 1])
+            lam, V = np.linalg.eigh(Ks[a:b, a:b])
+            self.blocks.append((a, b, V, lam))
+
+    def abs_block(self, g: int) -> np.ndarray:
+        a, b, V, lam = self.blocks[g]
+        return V @ np.diag(np.abs(lam)) @ V.T
+
+    def matrix(self) -> np.ndarray:
+        """M in user order (dense)."""
+        n = self.S.size
+        Mn = np.zeros((n, n))
+        for g in range(len(self.blocks)):
+            a, b = self.blocks[g][:2]
+            Mn[a:b, a:b] = self.abs_block(g)
+        Mn = Mn / self.S[:, None] / self.S[None, :]
+        M = np.zeros((n, n))
+        M[np.ix_(self.perm, self.perm)] = Mn
+        return M
+
+    def apply(self, v: np.ndarray) -> np.ndarray:
+        vn = self.S * v[self.perm]
+        zn = np.zeros_like(vn)
+        for a, b, V, lam in self.blocks:
+            zn[a:b] = V @ ((V.T @ vn[a:b]) / np.abs(lam))
+        zn = self.S * zn
+        z = np.zeros_like(zn)
+        z[self.perm] = zn
+        return z
+
+
 def sgn_matrix(prob: Problem, x: np.ndarray, p: np.ndarray) -> np.ndarray:
     """The assembled K_SGN at (x, p) in user (block) order, from the dense oracle."""
     return D.sgn_matrix_dense(prob, x, p)

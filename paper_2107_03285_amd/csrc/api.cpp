@@ -93,6 +93,9 @@ struct DevSys {
   double* pc_w = nullptr;      // [N] block-solved forward result (pivot order)
   double* cur_scale = nullptr; // [N] row scaling of the currently assembled matrix (residual weights)
   double* mr[10] = {};         // MINRES work vectors
+  int64_t* bp_off = nullptr;   // block-diagonal preconditioner (pc_kind = SGN_PC_BLOCK): offsets of the
+  double* bp_minv = nullptr;   // dense |B_i|^-1 blocks, one per node group
+  bool bp_ready = false;       // the blocks are of the currently assembled matrix
   int prec = 0;  // 0: FP64 fronts, 1: FP32 fronts
   bool factored = false;  // a factorisation is held (the MINRES reference)
   bool current = false;   // ... and it is of the currently assembled matrix
@@ -199,6 +202,7 @@ struct sgn_ctx_s {
   bool kx_valid = false;
   bool sgn_assembled = false;
   double newton_delta_last = 0.0;     // regularisation of the last sgn_newton_step that needed one
+  std::vector<int64_t> bp_off;        // block-diagonal preconditioner: offsets of the groups' blocks
   // L-BFGS memory (sgn_lbfgs_step): newest pair at lb_head - 1 (circular), curvature 1 / s^T y
   double* lb_s = nullptr;             // [lbfgs_m x n_p]
   double* lb_y = nullptr;             // [lbfgs_m x n_p]
@@ -365,6 +369,10 @@ size_t layout(sgn_ctx c, char* base) {
       D.pc_w = L.take<double>(S.N);
       D.cur_scale = L.take<double>(S.N);
       for (double*& v : D.mr) v = L.take<double>(S.N);
+      if (c->opt.pc_kind == SGN_PC_BLOCK) {
+        D.bp_off = L.take<int64_t>(c->bp_off.size());
+        D.bp_minv = L.take<double>((size_t)c->bp_off.back());
+      }
     }
   }
   {
@@ -825,6 +833,10 @@ PcArgs pc_args(sgn_ctx c) {
 sgn_status pc_apply_new(sgn_ctx c, const double* in_new, double* out_new, double* ysave) {
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;
+  if (c->opt.pc_kind == SGN_PC_BLOCK) {
+    launch_blockpc_apply(D.ngroups, D.grp_ptr, D.cur_scale, D.bp_off, D.bp_minv, in_new, out_new, c->stream);
+    return SGN_OK;
+  }
   scale_vec(c, N, D.scale, in_new, D.sv);
   TRY(fwd_sweep(c, 0, D.sv));
   launch_pc_block(pc_args(c), D.tp, ysave, D.pc_w, c->stream);
@@ -1455,6 +1467,7 @@ sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rh
   }
   c->sgn_assembled = true;
   c->sys[0].current = false;
+  c->sys[0].bp_ready = false;
   HIPCHK(hipMemcpyAsync(c->d_x_asm, x, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->d_p_asm, p, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (obj) TRY(objective_value(c, x, p, obj));
@@ -1840,6 +1853,17 @@ size_t carve_solve_scratch(sgn_ctx c, char* base, SolveScratch* s) {
 // MINRES with the reference factor's preconditioner; on stagnation, on max_minres
 // iterations, or without a reference factor: exact factorisation of the current
 // matrix (which becomes the new reference) and the refined direct solve.
+// |B_i|^-1 of the node groups' diagonal blocks of the assembled matrix (block-diagonal preconditioner)
+sgn_status blockpc_setup(sgn_ctx c) {
+  DevSys& D = c->sys[0];
+  const int64_t N = c->A.sgn.N;
+  launch_row_scaling(N, D.frowptr, D.fslot, D.vals, D.cur_scale, c->stream);
+  launch_blockpc_setup(D.ngroups, D.grp_ptr, D.rowptr, D.colind, D.vals, D.cur_scale, D.bp_off, D.bp_minv, c->stream);
+  HIPCHK(hipGetLastError());
+  D.bp_ready = true;
+  return SGN_OK;
+}
+
 sgn_status minres_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solve_info* info) {
   DevSys& D = c->sys[0];
   if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "sgn_solve_minres before sgn_assemble");
@@ -1849,8 +1873,10 @@ sgn_status minres_solve_impl(sgn_ctx c, const double* rhs, double* sol, sgn_solv
   double* zn = c->d_old;
   sgn_solve_info si{};
   bool conv = false;
-  if (D.factored) {
-    if (c->pc_weights) {  // corrections for the move from the reference state to the assembled one
+  const bool block = c->opt.pc_kind == SGN_PC_BLOCK;
+  if (block) TRY(blockpc_setup(c));
+  if (D.factored || block) {
+    if (c->pc_weights && !block) {  // corrections for the move from the reference state to the assembled one
       TRY(gnn_forward_impl(c, c->pc_weights, c->d_x_fac, c->d_p_fac, c->d_x_asm, c->d_p_asm, c->own_cn, c->own_cp));
       c->use_own = true;
     }
@@ -2332,6 +2358,15 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
   }
   std::string err = analyse(c->A);
   if (!err.empty()) return fail(c, SGN_E_ARG, "symbolic analysis: " + err);
+  if (c->opt.pc_kind != SGN_PC_FACTOR && c->opt.pc_kind != SGN_PC_BLOCK) return fail(c, SGN_E_ARG, "unknown pc_kind");
+  if (c->opt.pc_kind == SGN_PC_BLOCK) {
+    const std::vector<int32_t>& gp = c->A.sgn.grp_ptr;
+    c->bp_off.assign(gp.size(), 0);
+    for (size_t q = 0; q + 1 < gp.size(); ++q) {
+      const int64_t g = gp[q + 1] - gp[q];
+      c->bp_off[q + 1] = c->bp_off[q] + g * g;
+    }
+  }
   err = build_gnn_graph(m, c->G);
   if (!err.empty()) return fail(c, SGN_E_ARG, "preconditioner graph: " + err);
   const int64_t nx = m.n_x, np = m.n_p;
@@ -2468,6 +2503,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.sn_part_off, S.sn_part_off, st));
     if (si == 0) {
       HIPCHK(up(D.grp_ptr, S.grp_ptr, st));
+      if (c->opt.pc_kind == SGN_PC_BLOCK) HIPCHK(up(D.bp_off, c->bp_off, st));
       HIPCHK(up(D.grp_node, S.grp_node, st));
       HIPCHK(up(D.grp_vec, S.grp_vec, st));
     }
@@ -3049,7 +3085,13 @@ sgn_status sgn_spmv(sgn_ctx c, const double* d_in, double* d_out) {
 }
 
 sgn_status sgn_pc_apply(sgn_ctx c, const double* d_in, double* d_out, double* d_fwd) {
-  TRY(pc_ready(c));
+  if (c && c->opt.pc_kind == SGN_PC_BLOCK) {
+    TRY(check_ready(c));
+    if (!c->sgn_assembled) return fail(c, SGN_E_STATE, "the block-diagonal preconditioner needs sgn_assemble");
+    if (!c->sys[0].bp_ready) TRY(blockpc_setup(c));
+  } else {
+    TRY(pc_ready(c));
+  }
   if (!d_in || !d_out) return fail(c, SGN_E_ARG, "null vector");
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;

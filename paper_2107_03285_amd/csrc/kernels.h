@@ -113,6 +113,12 @@ void launch_spmv(int64_t N, const int64_t* frowptr, const int32_t* fcol, const i
 void launch_residual(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
                      const double* vals, const double* x, const double* b, double* out, hipStream_t s);
 // scale[i] = 1 / sqrt(max_j |K_ij|) over the full row (1 when the row is empty)
+// block-diagonal preconditioner: per node group (grp_ptr, new numbering) |B_i|^-1 of the diagonal block B_i
+// of S K S (S = scale) stored densely at minv + off[i]; apply: out = S blockdiag(|B_i|^-1) S in
+void launch_blockpc_setup(int64_t ngroups, const int32_t* grp_ptr, const int64_t* rowptr, const int32_t* colind,
+                          const double* vals, const double* scale, const int64_t* off, double* minv, hipStream_t s);
+void launch_blockpc_apply(int64_t ngroups, const int32_t* grp_ptr, const double* scale, const int64_t* off,
+                          const double* minv, const double* in, double* out, hipStream_t s);
 void launch_row_scaling(int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals,
                         double* scale, hipStream_t s);
 // objective pieces on free DOFs: fx = w (x_T - t)/ell^2 on targets (else 0)

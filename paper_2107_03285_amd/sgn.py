@@ -25,6 +25,7 @@ SGN_FP64, SGN_FP32_IR = 0, 1
 SGN_LDLT, SGN_MINRES_LEARNED, SGN_BICGSTAB, SGN_BLOCK_GN = 0, 1, 2, 3
 SGN_RHS_ADJOINT, SGN_RHS_KKT = 0, 1
 SGN_HESSIAN_GN, SGN_HESSIAN_NEWTON = 0, 1
+SGN_PC_FACTOR, SGN_PC_BLOCK = 0, 1
 SGN_SYS_SGN, SGN_SYS_KX = 0, 1
 
 EXPORTS = ["sgn_create", "sgn_default_options", "sgn_workspace_size", "sgn_set_workspace", "sgn_set_targets",
@@ -55,7 +56,7 @@ class sgn_options(C.Structure):
                 ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int),
                 ("profile", C.c_int), ("max_gmres", C.c_int), ("outer_panels", C.c_int * 3),
                 ("seq_panels", C.c_int), ("max_bicgstab", C.c_int), ("lbfgs_m", C.c_int),
-                ("hessian", C.c_int)]
+                ("hessian", C.c_int), ("pc_kind", C.c_int)]
 
 
 class sgn_stats(C.Structure):

@@ -139,3 +139,36 @@ def test_bilinear_gradient_matches_central_differences(case):
     fixed = np.nonzero(prob.fixed)[0]
     if fixed.size:
         assert np.all(gn.reshape(prob.n_nodes, tri)[fixed] == 0)
+
+
+def test_block_diagonal_ablation(case):
+    """The block-diagonal preconditioner without a reference factor: |B_i|^2 = B_i^2 and |B_i| is
+    positive definite for every group (the eigen-absolute value), M is SPD, apply() is M^-1, and on a
+    matrix that is block diagonal over the groups M^-1 K has only the eigenvalues +-1."""
+    prob, x, p, K, _ = case
+    bp = PC.BlockDiagonalPreconditioner(prob, K)
+    perm = bp.perm
+    Kn = K[np.ix_(perm, perm)]
+    Ks = bp.S[:, None] * Kn * bp.S[None, :]
+    for g in range(len(bp.blocks)):
+        a, b = bp.blocks[g][:2]
+        Bg = Ks[a:b, a:b]
+        Ag = bp.abs_block(g)
+        assert np.allclose(Ag @ Ag, Bg @ Bg, rtol=0, atol=1e-12 * max(1.0, np.abs(Bg).max() ** 2))
+        assert np.linalg.eigvalsh(Ag).min() > 0
+    M = bp.matrix()
+    assert np.allclose(M, M.T, rtol=0, atol=1e-12 * np.abs(M).max())
+    assert np.linalg.eigvalsh(M).min() > 0
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(K.shape[0])
+    z = bp.apply(v)
+    assert np.linalg.norm(M @ z - v) <= 1e-13 * np.linalg.norm(M, 2) * np.linalg.norm(z)
+    # K restricted to the group blocks (in new order) gives M^-1 K = blockdiag(|B_i|^-1 B_i): +-1
+    Kb = np.zeros_like(Kn)
+    for a, b, _, _ in bp.blocks:
+        Kb[a:b, a:b] = Kn[a:b, a:b]
+    Ku = np.zeros_like(Kb)
+    Ku[np.ix_(perm, perm)] = Kb
+    bp2 = PC.BlockDiagonalPreconditioner(prob, Ku)
+    ev = np.linalg.eigvals(np.linalg.solve(bp2.matrix(), Ku))
+    assert np.allclose(np.abs(ev.real), 1.0, atol=1e-8) and np.allclose(ev.imag, 0.0, atol=1e-8)
