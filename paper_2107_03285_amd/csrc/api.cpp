@@ -49,7 +49,7 @@ struct DevSys {
   int32_t* child_ptr = nullptr;
   int32_t* child_list = nullptr;
   int32_t* var_group_end = nullptr;
-  int32_t* level_sn = nullptr;
+  int32_t* solve_sn = nullptr;
   int32_t* panel_ptr = nullptr;
   int32_t* panel_col = nullptr;
   int64_t* panel_tasks = nullptr;
@@ -323,7 +323,7 @@ size_t layout(sgn_ctx c, char* base) {
     D.child_ptr = L.take<int32_t>(S.child_ptr.size());
     D.child_list = L.take<int32_t>(S.child_list.size());
     D.var_group_end = L.take<int32_t>(S.var_group_end.size());
-    D.level_sn = L.take<int32_t>(S.level_sn.size());
+    D.solve_sn = L.take<int32_t>(S.solve_sn.size());
     D.panel_ptr = L.take<int32_t>(S.panel_ptr.size());
     D.panel_col = L.take<int32_t>(S.panel_col.size());
     D.panel_tasks = L.take<int64_t>(S.panel_tasks.size());
@@ -582,6 +582,13 @@ sgn_status read_update_events(sgn_ctx c) {
   return SGN_OK;
 }
 
+// Narrow panels per launch from which each panel's diagonal block is factorised by one wavefront
+// instead of eight: four 8-wavefront blocks fill a compute unit, so from 1024 panels on the launch is
+// bound by the issue of the wavefronts' instructions, and the eight wavefronts' repeated pivot
+// searches cost more than the shorter step saves; a 32-row block lets 18 one-wavefront blocks share a
+// compute unit's LDS.
+constexpr int64_t kPanelSpread = 1024;
+
 template <typename T>
 sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   const System& S = si == 0 ? c->A.sgn : c->A.kx;
@@ -646,7 +653,15 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
     bool side_busy = false;
     for (const PanelStep& ps : P.steps) {
       const int64_t nt = ps.task_end - ps.task_begin;
-      launch_panel_diag<T>(nt, D.panel_tasks + ps.task_begin * 3, f, front, st);
+      // narrow panels (listed first) with one wavefront each once there are enough of them to fill
+      // the chip, wide ones with eight (one wavefront holding a 64-row block leaves a compute unit
+      // four of them, too few to hide the step's latencies)
+      const int64_t nn = ps.narrow_end - ps.task_begin;
+      const int pw = c->A.tune.panel_waves;
+      launch_panel_diag<T>(nn, kNarrowPanel, pw != 0 ? pw : (nn >= kPanelSpread ? 1 : 8),
+                           D.panel_tasks + ps.task_begin * 3, f, front, st);
+      launch_panel_diag<T>(ps.task_end - ps.narrow_end, kPanel, pw != 0 ? pw : 8, D.panel_tasks + ps.narrow_end * 3, f,
+                           front, st);
       launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
       HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops, st));
       if (ps.outer_tiles > 0 && side_busy) {
@@ -763,8 +778,10 @@ sgn_status fwd_sweep_t(sgn_ctx c, int si, const double* b_new) {
   int* err = c->d_cnt + 12;
   for (int L = 0; L < S.nlevels; ++L) {
     const LevelPlan& P = S.levels[L];
-    launch_fwd_level<T>(P.sn_end - P.sn_begin, P.max_u, P.max_s, D.level_sn + P.sn_begin, D.solve_fwd_tasks + 2 * P.fwd_begin,
-                        P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr, err, st);
+    launch_fwd_level<T>(P.one_begin - P.sn_begin, P.solve_max_u, P.solve_max_s, D.solve_sn + P.sn_begin,
+                        D.solve_fwd_tasks + 2 * P.fwd_begin, P.fwd_end - P.fwd_begin, a, front, b_new, D.solve_ctr,
+                        err, st);
+    launch_fwd_one<T>(P.sn_end - P.one_begin, D.solve_sn + P.one_begin, a, front, b_new, st);
   }
   HIPCHK(hipGetLastError());
   return SGN_OK;
@@ -783,8 +800,10 @@ sgn_status bwd_sweep_t(sgn_ctx c, int si, double* x_new, const double* wd) {
   int* err = c->d_cnt + 12;
   for (int L = S.nlevels - 1; L >= 0; --L) {
     const LevelPlan& P = S.levels[L];
-    launch_bwd_level<T>(P.sn_end - P.sn_begin, P.max_s, D.level_sn + P.sn_begin, D.solve_bwd_tasks + 2 * P.bwd_begin,
-                        P.bwd_end - P.bwd_begin, a, front, x_new, D.solve_ctr + S.nsn, err, st);
+    launch_bwd_one<T>(P.sn_end - P.one_begin, D.solve_sn + P.one_begin, a, front, x_new, st);
+    launch_bwd_level<T>(P.one_begin - P.sn_begin, P.solve_max_s, D.solve_sn + P.sn_begin,
+                        D.solve_bwd_tasks + 2 * P.bwd_begin, P.bwd_end - P.bwd_begin, a, front, x_new,
+                        D.solve_ctr + S.nsn, err, st);
   }
   HIPCHK(hipGetLastError());
   return SGN_OK;
@@ -2343,6 +2362,9 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
     return fail(c, SGN_E_ARG, "max_bicgstab must be at least 1");
   if (!(c->opt.eps_x >= 0.0) || !(c->opt.eps_lambda >= 0.0)) return fail(c, SGN_E_ARG, "eps_x, eps_lambda must be >= 0");
   c->A.tune.seq_panels = c->opt.seq_panels == 0 ? kSolveSeqPanels : (c->opt.seq_panels < 0 ? 0 : c->opt.seq_panels);
+  if (c->opt.panel_waves != 0 && c->opt.panel_waves != 1 && c->opt.panel_waves != 8)
+    return fail(c, SGN_E_ARG, "panel_waves must be 0, 1 or 8");
+  c->A.tune.panel_waves = c->opt.panel_waves;
   if (c->opt.hessian != SGN_HESSIAN_GN && c->opt.hessian != SGN_HESSIAN_NEWTON)
     return fail(c, SGN_E_ARG, "unknown hessian");
   if (c->opt.hessian == SGN_HESSIAN_NEWTON) {
@@ -2489,7 +2511,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.child_ptr, S.child_ptr, st));
     HIPCHK(up(D.child_list, S.child_list, st));
     HIPCHK(up(D.var_group_end, S.var_group_end, st));
-    HIPCHK(up(D.level_sn, S.level_sn, st));
+    HIPCHK(up(D.solve_sn, S.solve_sn, st));
     HIPCHK(up(D.panel_ptr, S.panel_ptr, st));
     HIPCHK(up(D.panel_col, S.panel_col, st));
     HIPCHK(up(D.panel_tasks, S.panel_tasks, st));

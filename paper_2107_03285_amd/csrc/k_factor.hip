@@ -131,10 +131,10 @@ __global__ void __launch_bounds__(256) k_extend_add(int64_t ncols, const int64_t
   }
 }
 
-// wavefronts of the panel factorisation: each takes every kDiagWaves-th column of a step's update
-constexpr int kDiagWaves = 8;
-
-// Factorisation of one panel's diagonal block (w <= 64) in LDS, FP64, 64 * kDiagWaves threads.
+// Factorisation of one panel's diagonal block (w <= WM <= 64) in LDS, FP64, 64 * WAVES threads.
+// WAVES = 8 shortens a lone panel's step (the update is split over eight wavefronts); WAVES = 1
+// leaves no wavefront repeating another's pivot search, which pays when a step holds enough panels
+// to fill the chip, and WM = 32 lets more of them share a compute unit's LDS.
 // Bunch-Kaufman 1x1/2x2 pivoting restricted to the rows of one node group.  Every
 // wavefront reads the pivot column into registers and takes the same pivot decision
 // (argmax by a shuffle butterfly over |a| bits with the row index in the low bits, so
@@ -142,7 +142,7 @@ constexpr int kDiagWaves = 8;
 // copy by lane broadcasts.  A step has two barriers (two more for an interchange): one after every
 // wavefront has read the pivot columns, before wavefront 0 overwrites them with the multipliers,
 // and one at its end.
-// The symmetric updates use lane = row, wavefront = every kDiagWaves-th column.
+// The symmetric updates use lane = row, wavefront = every WAVES-th column.
 // Alongside L11 the block accumulates X = L11^-1 (unit lower) from the
 // elementary column inverses, X <- L_k^-1 X, stored transposed in the upper
 // part of the finished rows (X[i][j] at A[j][i]); symmetric interchanges swap
@@ -180,12 +180,12 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
   return ((unsigned long long)mh << 32) | ml;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64 * kDiagWaves) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
-                                                    T* __restrict__ front) {
-  __shared__ double A[64][65];
-  __shared__ int pos[64];
-  constexpr int S = kDiagWaves;  // column stride of a wavefront's share of an update
+template <typename T, int WAVES, int WM>
+__global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
+                                                           T* __restrict__ front) {
+  __shared__ double A[WM][WM + 1];
+  __shared__ int pos[WM];
+  constexpr int S = WAVES;  // column stride of a wavefront's share of an update
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform_i(tid >> 6);
   const int sn = (int)tasks[blockIdx.x * 3];
   const int c0 = (int)tasks[blockIdx.x * 3 + 1], c1 = (int)tasks[blockIdx.x * 3 + 2];
@@ -198,16 +198,16 @@ __global__ void __launch_bounds__(64 * kDiagWaves) k_panel_diag(const int64_t* _
     // the panel's lower triangle: all loads of a thread issued unconditionally (clamped to the
     // panel, masked when staged) before the first LDS store
     const int lc = lane < w ? lane : 0;
-    constexpr int NL = 64 / kDiagWaves;
+    constexpr int NL = WM / WAVES;
     T lv[NL];
 #pragma unroll
     for (int t = 0; t < NL; ++t) {
-      const int j = wave + kDiagWaves * t, jc = j < w ? j : 0;
+      const int j = wave + WAVES * t, jc = j < w ? j : 0;
       lv[t] = F[(c0 + lc) + (int64_t)(c0 + jc) * m];
     }
 #pragma unroll
     for (int t = 0; t < NL; ++t) {
-      const int j = wave + kDiagWaves * t;
+      const int j = wave + WAVES * t;
       if (j < w && lane >= j && lane < w) {
         const double v = (double)lv[t];
         A[lane][j] = v;
@@ -215,15 +215,17 @@ __global__ void __launch_bounds__(64 * kDiagWaves) k_panel_diag(const int64_t* _
       }
     }
   }
-  if (tid < 64) pos[tid] = tid;
+  if (tid < WM) pos[tid] = tid;
   const int gend_r = lane < w ? (int)(f.var_group_end[gbase + lane] - gbase) : w;
   int ptype = 0;
   double dv = 0.0, ev = 0.0;
   __syncthreads();
   int npert = 0;
   int k = 0;
+  // lanes past WM hold no row of the block (WM = 32): they read zeros
+  const bool row_lane = WM == 64 || lane < WM;
   while (k < w) {
-    double v = A[lane][k];
+    double v = row_lane ? A[lane][k] : 0.0;
     const int gend = __builtin_amdgcn_readlane(gend_r, k);
     const double cand = (lane > k && lane < gend) ? fabs(v) : 0.0;
     const unsigned long long key =
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(64 * kDiagWaves) k_panel_diag(const int64_t* _
     if (fmax(absakk, colmax) <= tol) {
       pert = true;
     } else if (absakk < kAlphaBK * colmax) {
-      const double u = A[imax][lane];  // row imax
+      const double u = row_lane ? A[imax][lane] : 0.0;  // row imax
       const double c2 = (lane >= k && lane < gend && lane != imax) ? fabs(u) : 0.0;
       const double rowmax = __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(c2)));
       if (absakk * rowmax >= kAlphaBK * colmax * colmax) {
@@ -276,11 +278,11 @@ __global__ void __launch_bounds__(64 * kDiagWaves) k_panel_diag(const int64_t* _
         }
       }
       __syncthreads();
-      v = A[lane][k];
+      v = row_lane ? A[lane][k] : 0.0;
     }
     // every wavefront holds the pivot columns it needs (k, and k + 1 for a 2 x 2 pivot) before any
     // wavefront overwrites them with the step's multipliers
-    const double w2 = kind == 2 ? A[lane][k + 1] : 0.0;
+    const double w2 = kind == 2 && row_lane ? A[lane][k + 1] : 0.0;
     __syncthreads();
     if (kind == 1) {
       double d = lane_bcast(v, k);
@@ -376,7 +378,7 @@ __global__ void __launch_bounds__(64 * kDiagWaves) k_panel_diag(const int64_t* _
   }
   // A holds L below the diagonal and X[j][i] at (i, j) above it: the transposed
   // placement the rows-below solve reads
-  for (int j = wave; j < w; j += kDiagWaves)
+  for (int j = wave; j < w; j += WAVES)
     if (lane < w) F[(c0 + lane) + (int64_t)(c0 + j) * m] = (T)(lane == j ? 1.0 : A[lane][j]);
   if (tid < w) {
     f.dpiv[gbase + tid] = dv;
@@ -738,8 +740,12 @@ void launch_extend_add(int64_t ncols, const int64_t* cols, const FrontArgs& f, T
 }
 
 template <typename T>
-void launch_panel_diag(int64_t ntasks, const int64_t* tasks, const FrontArgs& f, T* front, hipStream_t s) {
-  if (ntasks > 0) k_panel_diag<T><<<(unsigned)ntasks, 64 * kDiagWaves, 0, s>>>(tasks, f, front);
+void launch_panel_diag(int64_t ntasks, int max_w, int waves, const int64_t* tasks, const FrontArgs& f, T* front,
+                       hipStream_t s) {
+  if (ntasks <= 0) return;
+  if (waves == 8) k_panel_diag<T, 8, 64><<<(unsigned)ntasks, 512, 0, s>>>(tasks, f, front);
+  else if (max_w <= 32) k_panel_diag<T, 1, 32><<<(unsigned)ntasks, 64, 0, s>>>(tasks, f, front);
+  else k_panel_diag<T, 1, 64><<<(unsigned)ntasks, 64, 0, s>>>(tasks, f, front);
 }
 
 template <typename T>
@@ -774,8 +780,10 @@ template void launch_zero_fronts<double>(int64_t, const int32_t*, const FrontArg
 template void launch_zero_fronts<float>(int64_t, const int32_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_extend_add<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
 template void launch_extend_add<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
-template void launch_panel_diag<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
-template void launch_panel_diag<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+template void launch_panel_diag<double>(int64_t, int, int, const int64_t*, const FrontArgs&, double*,
+                                         hipStream_t);
+template void launch_panel_diag<float>(int64_t, int, int, const int64_t*, const FrontArgs&, float*,
+                                        hipStream_t);
 template void launch_panel_trsm<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
 template void launch_panel_trsm<float>(int64_t, int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_update<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);

@@ -533,6 +533,180 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
   }
 }
 
+// ---- fronts of one panel (s <= 64 pivots, order m <= kOneMaxM): one wavefront per front
+//
+// Forward: the gathered right-hand side t (pivot entries of b, children's contribution vectors
+// added in the fixed child order) stays in LDS; y = L11^-1 P t_s on the pivot lanes, then the
+// contribution to the parent t_u - L21 y, rows on lanes, the sum over pivot columns in ascending
+// order.  Backward: pivot columns on lanes, each lane's sum of L21[r][k] x[row r] over the rows in
+// ascending order, then v = L11^-T (D^-1 y - L21^T x_u), scattered by the panel's permutation.  No
+// flags and no waits: a front's solve is one wavefront's program order.
+constexpr int kOneWaves = 4;  // fronts per block
+constexpr int kOneChunk = 16;  // factor loads in flight per lane
+
+template <typename T, int SW>
+__device__ void fwd_one(int J, const SolveArgs& a, const T* __restrict__ front, const double* __restrict__ b,
+                        double* tv, double* zy) {
+  const int lane = threadIdx.x & 63;
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J];
+  const int s = (int)(f.sn_begin[J + 1] - g0), m = f.sn_m[J], u = m - s;
+  double* tp = a.tp + a.sn_vec_off[J];
+  for (int k = lane; k < m; k += 64) tv[k] = k < s ? b[g0 + k] : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  for (int32_t q = a.child_ptr[J]; q < a.child_ptr[J + 1]; ++q) {
+    const int C = a.child_list[q];
+    const int64_t sC = f.sn_begin[C + 1] - f.sn_begin[C], uC = f.sn_m[C] - sC;
+    const double* cv = a.tp + a.sn_vec_off[C] + sC;
+    const int32_t* rel = f.relmap + f.relmap_off[C];
+    for (int64_t r = lane; r < uC; r += 64) tv[rel[r]] += cv[r];  // a child's rows land on distinct entries
+    __builtin_amdgcn_wave_barrier();
+  }
+  const T* F = front + f.sn_front_off[J];
+  const double tvl = lane < s ? tv[lane] : 0.0;
+  const int src = lane < s ? f.lperm[g0 + lane] : 0;
+  const double zs = __shfl(tvl, src, 64);
+  const double z = lane < s ? zs : 0.0;  // zero past s: the products below add nothing there
+  zy[lane] = z;  // read back as broadcasts
+  __builtin_amdgcn_wave_barrier();
+  // y = L11^-1 z; (L11^-1)[lane][j], j < lane, is kept at F[j + lane m] (the diagonal block's upper
+  // triangle); clamped loads, masked at use
+  double y = z;
+  {
+    const rsrc_t rs = buffer_rsrc(F, (int32_t)(((int64_t)(s - 1) * m + s) * (int64_t)sizeof(T)));
+    const uint32_t voff = (uint32_t)((lane < s ? lane : 0) * m * (int64_t)sizeof(T));
+#pragma unroll 1
+    for (int j0 = 0; j0 < SW; j0 += kOneChunk) {
+      T fv[kOneChunk];
+#pragma unroll
+      for (int j = 0; j < kOneChunk; ++j) fv[j] = buffer_load<T>(rs, voff, (j0 + j < s ? j0 + j : 0) * (int)sizeof(T));
+#pragma unroll
+      for (int j = 0; j < kOneChunk; ++j) y += (j0 + j < lane ? (double)fv[j] : 0.0) * zy[j0 + j];
+    }
+  }
+  if (lane < s) tp[lane] = y;
+  __builtin_amdgcn_wave_barrier();
+  zy[lane] = lane < s ? y : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  if (u <= 0) return;
+  // rows below: lane = row, columns past s read column 0 and meet y = 0
+  const rsrc_t rs = buffer_rsrc(F + s, (int32_t)(((int64_t)(s - 1) * m + u) * (int64_t)sizeof(T)));
+  const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
+  for (int r0 = 0; r0 < u; r0 += 64) {
+    const int r = r0 + lane;
+    const uint32_t voff = (uint32_t)((r < u ? r : 0) * (int)sizeof(T));
+    double acc = 0.0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < SW; k0 += kOneChunk) {
+      T fv[kOneChunk];
+#pragma unroll
+      for (int k = 0; k < kOneChunk; ++k) fv[k] = buffer_load<T>(rs, voff, (k0 + k < s ? k0 + k : 0) * cstr);
+#pragma unroll
+      for (int k = 0; k < kOneChunk; ++k) acc += (double)fv[k] * zy[k0 + k];
+    }
+    if (r < u) tp[s + r] = tv[s + r] - acc;
+  }
+}
+
+template <typename T, int SW>
+__device__ void bwd_one(int J, const SolveArgs& a, const T* __restrict__ front, double* __restrict__ x, double* zy) {
+  const int lane = threadIdx.x & 63;
+  const FrontArgs& f = a.f;
+  const int64_t g0 = f.sn_begin[J];
+  const int s = (int)(f.sn_begin[J + 1] - g0), m = f.sn_m[J], u = m - s;
+  const double* tp = a.tp + a.sn_vec_off[J];
+  const int32_t* rows = f.sn_rows + f.sn_rows_ptr[J];
+  const T* F = front + f.sn_front_off[J];
+  const int kc = lane < s ? lane : 0;  // this lane's pivot column (clamped)
+  // sum over the rows of L21[r][lane] x[row r]: a lane walks its own column, x of 64 rows at a time
+  // in registers of the lanes and broadcast
+  double sum = 0.0;
+  if (u > 0) {
+    const rsrc_t rs = buffer_rsrc(F + s, (int32_t)(((int64_t)(s - 1) * m + u) * (int64_t)sizeof(T)));
+    const uint32_t voff = (uint32_t)(kc * m * (int64_t)sizeof(T));
+    for (int r0 = 0; r0 < u; r0 += 64) {
+      const int r = r0 + lane;
+      const double xr = x[rows[r < u ? r : 0]];
+      const double xm = r < u ? xr : 0.0;
+      const int nr = u - r0 < 64 ? u - r0 : 64;
+#pragma unroll 1
+      for (int q0 = 0; q0 < nr; q0 += kOneChunk) {
+        T fv[kOneChunk];
+#pragma unroll
+        for (int q = 0; q < kOneChunk; ++q)
+          fv[q] = buffer_load<T>(rs, voff, (r0 + (q0 + q < nr ? q0 + q : 0)) * (int)sizeof(T));
+#pragma unroll
+        for (int q = 0; q < kOneChunk; ++q)
+          if (q0 + q < nr) sum += (double)fv[q] * lane_bcast(xm, (q0 + q) & 63);
+      }
+    }
+  }
+  // z = D^-1 y - L21^T x_u on the pivot lanes
+  double z = 0.0;
+  if (lane < s) {
+    const int64_t k = lane;
+    const int t = f.pivtype[g0 + k];
+    double w;
+    if (a.wd) {
+      w = a.wd[g0 + k];
+    } else if (t == 0) {
+      w = tp[k] / f.dpiv[g0 + k];
+    } else if (t == 1) {
+      const double A = f.dpiv[g0 + k], B = f.epiv[g0 + k], C = f.dpiv[g0 + k + 1];
+      w = (C * tp[k] - B * tp[k + 1]) / (A * C - B * B);
+    } else {
+      const double A = f.dpiv[g0 + k - 1], B = f.epiv[g0 + k - 1], C = f.dpiv[g0 + k];
+      w = (A * tp[k] - B * tp[k - 1]) / (A * C - B * B);
+    }
+    z = w - sum;
+  }
+  zy[lane] = z;  // read back as broadcasts (zero past s)
+  __builtin_amdgcn_wave_barrier();
+  // v = L11^-T z: (L11^-1)[j][lane], j > lane, is kept at F[lane + j m]
+  double v = z;
+  {
+    const rsrc_t rs = buffer_rsrc(F, (int32_t)(((int64_t)(s - 1) * m + s) * (int64_t)sizeof(T)));
+    const uint32_t voff = (uint32_t)(kc * (int)sizeof(T));
+    const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
+#pragma unroll 1
+    for (int j0 = 0; j0 < SW; j0 += kOneChunk) {
+      T fv[kOneChunk];
+#pragma unroll
+      for (int j = 0; j < kOneChunk; ++j) fv[j] = buffer_load<T>(rs, voff, (j0 + j < s ? j0 + j : 0) * cstr);
+#pragma unroll
+      for (int j = 0; j < kOneChunk; ++j) v += (lane < j0 + j ? (double)fv[j] : 0.0) * zy[j0 + j];
+    }
+  }
+  if (lane < s) x[g0 + f.lperm[g0 + lane]] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kOneWaves) k_fwd_one(const int32_t* __restrict__ fronts, int64_t n, SolveArgs a,
+                                                            const T* __restrict__ front, const double* __restrict__ b) {
+  __shared__ double tvs[kOneWaves][kOneMaxM];
+  __shared__ double zys[kOneWaves][64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t q = (int64_t)blockIdx.x * kOneWaves + wave;
+  if (q >= n) return;  // the wavefronts of a block share no data and no barrier
+  const int J = fronts[q];
+  const int s = (int)(a.f.sn_begin[J + 1] - a.f.sn_begin[J]);
+  if (s <= 32) fwd_one<T, 32>(J, a, front, b, tvs[wave], zys[wave]);
+  else fwd_one<T, 64>(J, a, front, b, tvs[wave], zys[wave]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kOneWaves) k_bwd_one(const int32_t* __restrict__ fronts, int64_t n, SolveArgs a,
+                                                            const T* __restrict__ front, double* __restrict__ x) {
+  __shared__ double zys[kOneWaves][64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t q = (int64_t)blockIdx.x * kOneWaves + wave;
+  if (q >= n) return;
+  const int J = fronts[q];
+  const int s = (int)(a.f.sn_begin[J + 1] - a.f.sn_begin[J]);
+  if (s <= 32) bwd_one<T, 32>(J, a, front, x, zys[wave]);
+  else bwd_one<T, 64>(J, a, front, x, zys[wave]);
+}
+
 }  // namespace
 
 template <typename T>
@@ -562,6 +736,22 @@ void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const
     k_bwd_panels<T><<<(unsigned)ntasks, 256, 0, s>>>(tasks, ntasks, a, front, x, counter, err);
 }
 
+template <typename T>
+void launch_fwd_one(int64_t n, const int32_t* fronts, const SolveArgs& a, const T* front, const double* b,
+                    hipStream_t s) {
+  if (n > 0) k_fwd_one<T><<<(unsigned)((n + kOneWaves - 1) / kOneWaves), 64 * kOneWaves, 0, s>>>(fronts, n, a, front, b);
+}
+
+template <typename T>
+void launch_bwd_one(int64_t n, const int32_t* fronts, const SolveArgs& a, const T* front, double* x, hipStream_t s) {
+  if (n > 0) k_bwd_one<T><<<(unsigned)((n + kOneWaves - 1) / kOneWaves), 64 * kOneWaves, 0, s>>>(fronts, n, a, front, x);
+}
+
+template void launch_fwd_one<double>(int64_t, const int32_t*, const SolveArgs&, const double*, const double*,
+                                     hipStream_t);
+template void launch_fwd_one<float>(int64_t, const int32_t*, const SolveArgs&, const float*, const double*, hipStream_t);
+template void launch_bwd_one<double>(int64_t, const int32_t*, const SolveArgs&, const double*, double*, hipStream_t);
+template void launch_bwd_one<float>(int64_t, const int32_t*, const SolveArgs&, const float*, double*, hipStream_t);
 template void launch_fwd_level<double>(int64_t, int64_t, int64_t, const int32_t*, const int32_t*, int64_t,
                                        const SolveArgs&, const double*, const double*, int*, int*, hipStream_t);
 template void launch_fwd_level<float>(int64_t, int64_t, int64_t, const int32_t*, const int32_t*, int64_t,

@@ -152,7 +152,8 @@ void launch_zero_fronts(int64_t ntasks, const int32_t* tasks, const FrontArgs& f
 template <typename T>
 void launch_extend_add(int64_t ncols, const int64_t* cols, const FrontArgs& f, T* front, hipStream_t s);
 template <typename T>
-void launch_panel_diag(int64_t ntasks, const int64_t* tasks, const FrontArgs& f, T* front, hipStream_t s);
+void launch_panel_diag(int64_t ntasks, int max_w, int waves, const int64_t* tasks, const FrontArgs& f, T* front,
+                       hipStream_t s);
 template <typename T>
 void launch_panel_trsm(int64_t ntasks, int64_t max_rows, const int64_t* tasks, const FrontArgs& f, T* front,
                        hipStream_t s);
@@ -186,6 +187,14 @@ void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* 
 template <typename T>
 void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
                       const SolveArgs& a, const T* front, double* x, int* counter, int* err, hipStream_t s);
+// The same level step for fronts of one panel (s <= 64) and order m <= kOneMaxM, one wavefront each:
+// forward gather, permutation, unit lower solve and contribution vector; backward D^-1 y (or wd),
+// the rows-below product and the transposed unit lower solve.
+template <typename T>
+void launch_fwd_one(int64_t n, const int32_t* fronts, const SolveArgs& a, const T* front, const double* b,
+                    hipStream_t s);
+template <typename T>
+void launch_bwd_one(int64_t n, const int32_t* fronts, const SolveArgs& a, const T* front, double* x, hipStream_t s);
 
 // ---------------------------------------------------------------- node-block preconditioner
 struct PcArgs {

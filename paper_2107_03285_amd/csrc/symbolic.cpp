@@ -383,6 +383,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.nlevels = 0;
   for (int t = 0; t < nt; ++t) S.nlevels = std::max(S.nlevels, S.sn_level[t] + 1);
   S.level_sn.clear();
+  S.solve_sn.clear();
   S.levels.assign(S.nlevels, LevelPlan());
   S.panel_tasks.clear();
   S.upd_tasks.clear();
@@ -405,10 +406,23 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         P.max_u = std::max<int64_t>(P.max_u, S.sn_m[t] - (S.sn_begin[t + 1] - S.sn_begin[t]));
       }
     P.sn_end = (int64_t)S.level_sn.size();
+    auto one_panel = [&](int t) { return S.panel_ptr[t + 1] - S.panel_ptr[t] - 1 == 1 && S.sn_m[t] <= kOneMaxM; };
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) P.one_begin = (int64_t)S.solve_sn.size();
+      for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
+        const int t = S.level_sn[q];
+        if (one_panel(t) != (pass == 1)) continue;
+        S.solve_sn.push_back(t);
+        if (pass == 0) {
+          P.solve_max_s = std::max<int64_t>(P.solve_max_s, S.sn_begin[t + 1] - S.sn_begin[t]);
+          P.solve_max_u = std::max<int64_t>(P.solve_max_u, S.sn_m[t] - (S.sn_begin[t + 1] - S.sn_begin[t]));
+        }
+      }
+    }
     P.fwd_begin = (int64_t)S.solve_fwd_tasks.size() / 2;
     P.bwd_begin = (int64_t)S.solve_bwd_tasks.size() / 2;
-    for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
-      const int t = S.level_sn[q];
+    for (int64_t q = P.sn_begin; q < P.one_begin; ++q) {
+      const int t = S.solve_sn[q];
       const int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
       if (np >= 1 && np <= tune.seq_panels) {  // short panel chain: one block walks it
         S.solve_fwd_tasks.push_back(t);
@@ -449,13 +463,19 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     for (int k = 0; k < maxp; ++k) {
       PanelStep ps;
       ps.task_begin = (int64_t)S.panel_tasks.size() / 3;
-      for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
-        int t = S.level_sn[q];
-        int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
-        if (k >= np) continue;
-        S.panel_tasks.push_back(t);
-        S.panel_tasks.push_back(S.panel_col[S.panel_ptr[t] + k]);
-        S.panel_tasks.push_back(S.panel_col[S.panel_ptr[t] + k + 1]);
+      // panels of at most kNarrowPanel columns first (their own launch can use a smaller block)
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
+          int t = S.level_sn[q];
+          int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
+          if (k >= np) continue;
+          const int c0 = S.panel_col[S.panel_ptr[t] + k], c1 = S.panel_col[S.panel_ptr[t] + k + 1];
+          if ((c1 - c0 <= kNarrowPanel) != (pass == 0)) continue;
+          S.panel_tasks.push_back(t);
+          S.panel_tasks.push_back(c0);
+          S.panel_tasks.push_back(c1);
+        }
+        if (pass == 0) ps.narrow_end = (int64_t)S.panel_tasks.size() / 3;
       }
       ps.task_end = (int64_t)S.panel_tasks.size() / 3;
       ps.trsm_rows = 0;

@@ -11,6 +11,8 @@
 namespace sgn {
 
 constexpr int kPanel = 64;        // panel width of the blocked front factorisation
+constexpr int kNarrowPanel = 32;  // panels this narrow are listed first in each step's task range
+constexpr int kOneMaxM = 512;     // one-panel fronts up to this order are solved by one wavefront each
 constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
 constexpr int kTile = 64;         // update tile edge (equal to the kernels' kUpdTile)
 constexpr int kSolveKC = 256;     // k-chunk of the split-k L21 y product in the forward solve
@@ -27,6 +29,7 @@ constexpr int64_t kTuneBucketEdge[kTuneBuckets - 1] = {1024, 4096};
 struct Tuning {
   int outer_panels[kTuneBuckets] = {kOuterPanels, kOuterPanels, kOuterPanels};
   int seq_panels = kSolveSeqPanels;
+  int panel_waves = 0;  // wavefronts per panel factorisation: 1, 8, or 0 (by the step's panel count)
 };
 inline int tune_bucket(int64_t m) {
   int b = 0;
@@ -58,6 +61,7 @@ struct PanelStep {
   int64_t far_begin, far_end;      // range in the update task table (outer, k = block): the columns
                                    // beyond the next block, free to run beside its panels
   int64_t upd_tiles, outer_tiles, far_tiles;  // tiles of each update launch
+  int64_t narrow_end;              // tasks [task_begin, narrow_end) have at most kNarrowPanel columns
   int64_t trsm_rows;               // max rows below the panel over the step's tasks
   double upd_flops, outer_flops, far_flops;   // algorithmic flops of the update launches
 };
@@ -69,6 +73,9 @@ struct LevelPlan {
   std::vector<int64_t> ea_col_begin;               // per round: its first column record in ea_cols
   std::vector<PanelStep> steps;
   int64_t max_m = 0, max_s = 0, max_u = 0;
+  // solves: solve_sn[sn_begin, one_begin) are solved by the level kernels (solve_max_s, solve_max_u
+  // over them), solve_sn[one_begin, sn_end) are one-panel fronts solved by one wavefront each
+  int64_t one_begin = 0, solve_max_s = 0, solve_max_u = 0;
   int64_t fwd_begin = 0, fwd_end = 0;  // range (pairs) in solve_fwd_tasks: panels ascending per front
   int64_t bwd_begin = 0, bwd_end = 0;  // range (pairs) in solve_bwd_tasks: panels descending per front
 };
@@ -115,6 +122,7 @@ struct System {
   // schedule
   int nlevels = 0;
   std::vector<int32_t> level_sn;         // supernodes grouped by level
+  std::vector<int32_t> solve_sn;         // the same per level, one-panel fronts of order <= kOneMaxM last
   std::vector<LevelPlan> levels;
   // task tables (flattened int64 quintuples, see kernels)
   std::vector<int64_t> panel_tasks;      // (sn, c0, c1) per task: 3 entries

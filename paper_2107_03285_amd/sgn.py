@@ -56,7 +56,7 @@ class sgn_options(C.Structure):
                 ("max_ir", C.c_int), ("max_minres", C.c_int), ("max_halvings", C.c_int),
                 ("profile", C.c_int), ("max_gmres", C.c_int), ("outer_panels", C.c_int * 3),
                 ("seq_panels", C.c_int), ("max_bicgstab", C.c_int), ("lbfgs_m", C.c_int),
-                ("hessian", C.c_int), ("pc_kind", C.c_int)]
+                ("hessian", C.c_int), ("pc_kind", C.c_int), ("panel_waves", C.c_int)]
 
 
 class sgn_stats(C.Structure):

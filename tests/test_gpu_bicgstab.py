@@ -85,14 +85,22 @@ def test_bicgstab_recovers_the_unstabilised_step_from_a_strong_stabilisation(nam
     gap = np.linalg.norm(z_s[nx:nx + npar] - st.dp) / np.linalg.norm(st.dp)
     assert gap > 1e-6, gap
     # BiCGSTAB on the unstabilised system recovers the Gauss-Newton step: it solves the oracle's
-    # unstabilised system to the tolerance, and dp agrees to what that residual allows (the 4 x 4 grid's
-    # equilibrated matrix has condition number 4e7)
+    # unstabilised system to the tolerance, and the solution agrees with the dense solve to what that
+    # residual allows: in the equilibrated variables w = S^-1 z the relative forward error is at most
+    # cond(S K S) times the equilibrated relative residual (the 4 x 4 grid's is 4e7)
     info, z, b2 = _solve(prob, x, p, solver=sgn.SGN_BICGSTAB, eps_x=eps, eps_lambda=eps)
     assert info.rel_res <= 1e-10
     assert info.sweeps >= 2
     K = D.sgn_matrix_sparse(prob, x, p)
-    assert D.equilibrated_residual(K, z, b2) <= 1e-10
-    assert np.linalg.norm(z[nx:nx + npar] - st.dp) <= 1e-8 * np.linalg.norm(st.dp)
+    res = D.equilibrated_residual(K, z, b2)
+    assert res <= 1e-10
+    Kd = K.toarray()
+    sc = 1.0 / np.sqrt(np.abs(Kd).max(axis=1))
+    kappa = np.linalg.cond(sc[:, None] * Kd * sc[None, :])
+    zref = np.linalg.solve(Kd, b2)
+    assert np.linalg.norm(zref[nx:nx + npar] - st.dp) <= 1e-9 * np.linalg.norm(st.dp)  # the same system
+    bound = kappa * (res + 1e-15)  # plus the dense solve's own rounding
+    assert np.linalg.norm((z - zref) / sc) <= bound * np.linalg.norm(zref / sc)
 
 
 def test_outer_step_with_bicgstab_matches_ldlt():
