@@ -582,12 +582,16 @@ sgn_status read_update_events(sgn_ctx c) {
   return SGN_OK;
 }
 
-// Narrow panels per launch from which each panel's diagonal block is factorised by one wavefront
-// instead of eight: four 8-wavefront blocks fill a compute unit, so from 1024 panels on the launch is
-// bound by the issue of the wavefronts' instructions, and the eight wavefronts' repeated pivot
-// searches cost more than the shorter step saves; a 32-row block lets 18 one-wavefront blocks share a
-// compute unit's LDS.
-constexpr int64_t kPanelSpread = 1024;
+// Wavefronts per panel's diagonal-block factorisation for a launch of n panels.  Every wavefront
+// repeats the pivot search, the update of a step is split among them: with few panels the step's
+// latency decides (eight), with many the issue of all wavefronts' instructions does, since four
+// blocks of a 64-row LDS block fill a compute unit (four from 512 panels on), and narrow panels (a
+// 32-row block, 18 blocks per compute unit) do best with one from 1024 on.  Measured on the
+// 256-membrane union and the 100 x 25 x 25 cantilever; the factor is the same bits whatever the count.
+int panel_waves_for(int64_t n, bool narrow) {
+  if (narrow && n >= 1024) return 1;
+  return n >= 512 ? 4 : 8;
+}
 
 template <typename T>
 sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
@@ -653,14 +657,13 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
     bool side_busy = false;
     for (const PanelStep& ps : P.steps) {
       const int64_t nt = ps.task_end - ps.task_begin;
-      // narrow panels (listed first) with one wavefront each once there are enough of them to fill
-      // the chip, wide ones with eight (one wavefront holding a 64-row block leaves a compute unit
-      // four of them, too few to hide the step's latencies)
-      const int64_t nn = ps.narrow_end - ps.task_begin;
+      // narrow panels (listed first) and wide ones in launches of their own, each with the
+      // wavefront count that suits its panel count
+      const int64_t nn = ps.narrow_end - ps.task_begin, nw = ps.task_end - ps.narrow_end;
       const int pw = c->A.tune.panel_waves;
-      launch_panel_diag<T>(nn, kNarrowPanel, pw != 0 ? pw : (nn >= kPanelSpread ? 1 : 8),
-                           D.panel_tasks + ps.task_begin * 3, f, front, st);
-      launch_panel_diag<T>(ps.task_end - ps.narrow_end, kPanel, pw != 0 ? pw : 8, D.panel_tasks + ps.narrow_end * 3, f,
+      launch_panel_diag<T>(nn, kNarrowPanel, pw != 0 ? pw : panel_waves_for(nn, true), D.panel_tasks + ps.task_begin * 3,
+                           f, front, st);
+      launch_panel_diag<T>(nw, kPanel, pw != 0 ? pw : panel_waves_for(nw, false), D.panel_tasks + ps.narrow_end * 3, f,
                            front, st);
       launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
       HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops, st));
@@ -2362,8 +2365,9 @@ sgn_status sgn_create(const sgn_problem* pr, const sgn_options* opt, void* strea
     return fail(c, SGN_E_ARG, "max_bicgstab must be at least 1");
   if (!(c->opt.eps_x >= 0.0) || !(c->opt.eps_lambda >= 0.0)) return fail(c, SGN_E_ARG, "eps_x, eps_lambda must be >= 0");
   c->A.tune.seq_panels = c->opt.seq_panels == 0 ? kSolveSeqPanels : (c->opt.seq_panels < 0 ? 0 : c->opt.seq_panels);
-  if (c->opt.panel_waves != 0 && c->opt.panel_waves != 1 && c->opt.panel_waves != 8)
-    return fail(c, SGN_E_ARG, "panel_waves must be 0, 1 or 8");
+  if (c->opt.panel_waves != 0 && c->opt.panel_waves != 1 && c->opt.panel_waves != 2 && c->opt.panel_waves != 4 &&
+      c->opt.panel_waves != 8)
+    return fail(c, SGN_E_ARG, "panel_waves must be 0, 1, 2, 4 or 8");
   c->A.tune.panel_waves = c->opt.panel_waves;
   if (c->opt.hessian != SGN_HESSIAN_GN && c->opt.hessian != SGN_HESSIAN_NEWTON)
     return fail(c, SGN_E_ARG, "unknown hessian");

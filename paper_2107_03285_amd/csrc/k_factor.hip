@@ -744,6 +744,8 @@ void launch_panel_diag(int64_t ntasks, int max_w, int waves, const int64_t* task
                        hipStream_t s) {
   if (ntasks <= 0) return;
   if (waves == 8) k_panel_diag<T, 8, 64><<<(unsigned)ntasks, 512, 0, s>>>(tasks, f, front);
+  else if (waves == 4) k_panel_diag<T, 4, 64><<<(unsigned)ntasks, 256, 0, s>>>(tasks, f, front);
+  else if (waves == 2) k_panel_diag<T, 2, 64><<<(unsigned)ntasks, 128, 0, s>>>(tasks, f, front);
   else if (max_w <= 32) k_panel_diag<T, 1, 32><<<(unsigned)ntasks, 64, 0, s>>>(tasks, f, front);
   else k_panel_diag<T, 1, 64><<<(unsigned)ntasks, 64, 0, s>>>(tasks, f, front);
 }

@@ -536,15 +536,17 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
 // ---- fronts of one panel (s <= 64 pivots, order m <= kOneMaxM): one wavefront per front
 //
 // Forward: the gathered right-hand side t (pivot entries of b, children's contribution vectors
-// added in the fixed child order) stays in LDS; y = L11^-1 P t_s on the pivot lanes, then the
+// added in the fixed child order) stays in LDS; y = L11^-1 P t_s by substitution with the unit
+// lower block (rows on lanes, so every factor load is one contiguous column piece), then the
 // contribution to the parent t_u - L21 y, rows on lanes, the sum over pivot columns in ascending
-// order.  Backward: pivot columns on lanes, each lane's sum of L21[r][k] x[row r] over the rows in
-// ascending order, then v = L11^-T (D^-1 y - L21^T x_u), scattered by the panel's permutation.  No
-// flags and no waits: a front's solve is one wavefront's program order.
+// order.  Backward: L21^T x_u with rows on lanes (contiguous loads again), per 16 pivot columns a
+// butterfly that halves the set of columns a lane carries at each exchange leaves each column's
+// sum on the lanes congruent to it mod 16; then v = L11^-T (D^-1 y - L21^T x_u), scattered by the
+// panel's permutation.  No flags and no waits: a front's solve is one wavefront's program order.
 constexpr int kOneWaves = 4;  // fronts per block
 constexpr int kOneChunk = 16;  // factor loads in flight per lane
 
-template <typename T, int SW>
+template <typename T>
 __device__ void fwd_one(int J, const SolveArgs& a, const T* __restrict__ front, const double* __restrict__ b,
                         double* tv, double* zy) {
   const int lane = threadIdx.x & 63;
@@ -566,22 +568,22 @@ __device__ void fwd_one(int J, const SolveArgs& a, const T* __restrict__ front, 
   const double tvl = lane < s ? tv[lane] : 0.0;
   const int src = lane < s ? f.lperm[g0 + lane] : 0;
   const double zs = __shfl(tvl, src, 64);
-  const double z = lane < s ? zs : 0.0;  // zero past s: the products below add nothing there
-  zy[lane] = z;  // read back as broadcasts
-  __builtin_amdgcn_wave_barrier();
-  // y = L11^-1 z; (L11^-1)[lane][j], j < lane, is kept at F[j + lane m] (the diagonal block's upper
-  // triangle); clamped loads, masked at use
+  const double z = lane < s ? zs : 0.0;
+  // y = L11^-1 z: L11[lane][j], j < lane, is kept at F[lane + j m] (below the diagonal of the
+  // panel's block); y_j is final once the steps before j are done.  Clamped loads, masked at use.
   double y = z;
   {
     const rsrc_t rs = buffer_rsrc(F, (int32_t)(((int64_t)(s - 1) * m + s) * (int64_t)sizeof(T)));
-    const uint32_t voff = (uint32_t)((lane < s ? lane : 0) * m * (int64_t)sizeof(T));
+    const uint32_t voff = (uint32_t)((lane < s ? lane : 0) * (int)sizeof(T));
+    const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
 #pragma unroll 1
-    for (int j0 = 0; j0 < SW; j0 += kOneChunk) {
+    for (int j0 = 0; j0 < s; j0 += kOneChunk) {
       T fv[kOneChunk];
 #pragma unroll
-      for (int j = 0; j < kOneChunk; ++j) fv[j] = buffer_load<T>(rs, voff, (j0 + j < s ? j0 + j : 0) * (int)sizeof(T));
+      for (int j = 0; j < kOneChunk; ++j) fv[j] = buffer_load<T>(rs, voff, (j0 + j < s ? j0 + j : 0) * cstr);
 #pragma unroll
-      for (int j = 0; j < kOneChunk; ++j) y += (j0 + j < lane ? (double)fv[j] : 0.0) * zy[j0 + j];
+      for (int j = 0; j < kOneChunk; ++j)
+        if (j0 + j < s) y -= (lane > j0 + j ? (double)fv[j] : 0.0) * lane_bcast(y, j0 + j);
     }
   }
   if (lane < s) tp[lane] = y;
@@ -597,7 +599,7 @@ __device__ void fwd_one(int J, const SolveArgs& a, const T* __restrict__ front, 
     const uint32_t voff = (uint32_t)((r < u ? r : 0) * (int)sizeof(T));
     double acc = 0.0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < SW; k0 += kOneChunk) {
+    for (int k0 = 0; k0 < s; k0 += kOneChunk) {  // k0 + k < 64: zy is zero past s
       T fv[kOneChunk];
 #pragma unroll
       for (int k = 0; k < kOneChunk; ++k) fv[k] = buffer_load<T>(rs, voff, (k0 + k < s ? k0 + k : 0) * cstr);
@@ -608,7 +610,7 @@ __device__ void fwd_one(int J, const SolveArgs& a, const T* __restrict__ front, 
   }
 }
 
-template <typename T, int SW>
+template <typename T>
 __device__ void bwd_one(int J, const SolveArgs& a, const T* __restrict__ front, double* __restrict__ x, double* zy) {
   const int lane = threadIdx.x & 63;
   const FrontArgs& f = a.f;
@@ -618,27 +620,45 @@ __device__ void bwd_one(int J, const SolveArgs& a, const T* __restrict__ front, 
   const int32_t* rows = f.sn_rows + f.sn_rows_ptr[J];
   const T* F = front + f.sn_front_off[J];
   const int kc = lane < s ? lane : 0;  // this lane's pivot column (clamped)
-  // sum over the rows of L21[r][lane] x[row r]: a lane walks its own column, x of 64 rows at a time
-  // in registers of the lanes and broadcast
+  // sum over the rows of L21[r][lane] x[row r]
   double sum = 0.0;
   if (u > 0) {
     const rsrc_t rs = buffer_rsrc(F + s, (int32_t)(((int64_t)(s - 1) * m + u) * (int64_t)sizeof(T)));
-    const uint32_t voff = (uint32_t)(kc * m * (int64_t)sizeof(T));
-    for (int r0 = 0; r0 < u; r0 += 64) {
-      const int r = r0 + lane;
-      const double xr = x[rows[r < u ? r : 0]];
-      const double xm = r < u ? xr : 0.0;
-      const int nr = u - r0 < 64 ? u - r0 : 64;
+    const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
 #pragma unroll 1
-      for (int q0 = 0; q0 < nr; q0 += kOneChunk) {
+    for (int k0 = 0; k0 < s; k0 += kOneChunk) {
+      // c[i]: this lane's rows' part of column k0 + i
+      double c[kOneChunk];
+#pragma unroll
+      for (int i = 0; i < kOneChunk; ++i) c[i] = 0.0;
+#pragma unroll 1
+      for (int r0 = 0; r0 < u; r0 += 64) {
+        const int r = r0 + lane;
+        const uint32_t voff = (uint32_t)((r < u ? r : 0) * (int)sizeof(T));
         T fv[kOneChunk];
 #pragma unroll
-        for (int q = 0; q < kOneChunk; ++q)
-          fv[q] = buffer_load<T>(rs, voff, (r0 + (q0 + q < nr ? q0 + q : 0)) * (int)sizeof(T));
+        for (int i = 0; i < kOneChunk; ++i) fv[i] = buffer_load<T>(rs, voff, (k0 + i < s ? k0 + i : 0) * cstr);
+        const double xr = x[rows[r < u ? r : 0]];
+        const double xm = r < u ? xr : 0.0;
 #pragma unroll
-        for (int q = 0; q < kOneChunk; ++q)
-          if (q0 + q < nr) sum += (double)fv[q] * lane_bcast(xm, (q0 + q) & 63);
+        for (int i = 0; i < kOneChunk; ++i) c[i] += (double)fv[i] * xm;
       }
+      // exchanges across lane bits 3..0: a lane keeps the columns whose bit equals its own and adds
+      // the partner's part of them; then the four groups of 16 lanes are added
+#pragma unroll
+      for (int h = kOneChunk / 2; h >= 1; h >>= 1) {
+        const bool up = (lane & h) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+          const double keep = up ? c[i + h] : c[i];
+          const double send = up ? c[i] : c[i + h];
+          c[i] = keep + __shfl_xor(send, h, 64);
+        }
+      }
+      double t = c[0];  // column k0 + (lane & 15), over this lane's group of 16
+      t += __shfl_xor(t, 16, 64);
+      t += __shfl_xor(t, 32, 64);
+      if ((lane & ~(kOneChunk - 1)) == k0) sum = t;
     }
   }
   // z = D^-1 y - L21^T x_u on the pivot lanes
@@ -669,7 +689,7 @@ __device__ void bwd_one(int J, const SolveArgs& a, const T* __restrict__ front, 
     const uint32_t voff = (uint32_t)(kc * (int)sizeof(T));
     const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
 #pragma unroll 1
-    for (int j0 = 0; j0 < SW; j0 += kOneChunk) {
+    for (int j0 = 0; j0 < s; j0 += kOneChunk) {
       T fv[kOneChunk];
 #pragma unroll
       for (int j = 0; j < kOneChunk; ++j) fv[j] = buffer_load<T>(rs, voff, (j0 + j < s ? j0 + j : 0) * cstr);
@@ -689,9 +709,7 @@ __global__ void __launch_bounds__(64 * kOneWaves) k_fwd_one(const int32_t* __res
   const int64_t q = (int64_t)blockIdx.x * kOneWaves + wave;
   if (q >= n) return;  // the wavefronts of a block share no data and no barrier
   const int J = fronts[q];
-  const int s = (int)(a.f.sn_begin[J + 1] - a.f.sn_begin[J]);
-  if (s <= 32) fwd_one<T, 32>(J, a, front, b, tvs[wave], zys[wave]);
-  else fwd_one<T, 64>(J, a, front, b, tvs[wave], zys[wave]);
+  fwd_one<T>(J, a, front, b, tvs[wave], zys[wave]);
 }
 
 template <typename T>
@@ -702,9 +720,7 @@ __global__ void __launch_bounds__(64 * kOneWaves) k_bwd_one(const int32_t* __res
   const int64_t q = (int64_t)blockIdx.x * kOneWaves + wave;
   if (q >= n) return;
   const int J = fronts[q];
-  const int s = (int)(a.f.sn_begin[J + 1] - a.f.sn_begin[J]);
-  if (s <= 32) bwd_one<T, 32>(J, a, front, x, zys[wave]);
-  else bwd_one<T, 64>(J, a, front, x, zys[wave]);
+  bwd_one<T>(J, a, front, x, zys[wave]);
 }
 
 }  // namespace

@@ -221,13 +221,14 @@ def test_factor_and_solve_are_bitwise_reproducible():
 @pytest.mark.parametrize("precision", [sgn.SGN_FP64, sgn.SGN_FP32_IR])
 @pytest.mark.parametrize("name", ["grid21", "cant8x3x3"])
 def test_panel_wavefront_count_leaves_the_factor_unchanged(name, precision):
-    """The panel's diagonal block factorised by eight wavefronts, by one (block of 64 rows) and by one
-    with a 32-row block where every panel fits: the same operations on every entry, so the same bits
-    in the solution, the pivots and the inertia (the pivot search reads the same column either way)."""
+    """The panel's diagonal block factorised by eight, four, two or one wavefronts (one: a 32-row block
+    for the narrow panels) and by the automatic choice: the same operations on every entry, so the same
+    bits in the solution, the pivots and the inertia (the pivot search reads the same column either
+    way)."""
     prob, p, x = _problem(name)
     N = 2 * prob.n_x + prob.n_p
     out = []
-    for waves in (8, 1, 0):
+    for waves in (8, 4, 2, 1, 0):
         ctx = _ctx(prob, precision=precision, newton_rtol=1e-11, panel_waves=waves)
         xd, pd = _cuda(x), _cuda(p)
         ctx.equilibrium(pd, xd)
@@ -241,7 +242,7 @@ def test_panel_wavefront_count_leaves_the_factor_unchanged(name, precision):
         assert inertia == out[0][0]
         assert np.array_equal(sol.view(np.uint64), out[0][1].view(np.uint64))
     with pytest.raises(sgn.SgnError) as e:
-        sgn.Context(prob, sgn.default_options(panel_waves=4))
+        sgn.Context(prob, sgn.default_options(panel_waves=3))
     assert e.value.status == sgn.SGN_E_ARG
 
 
