@@ -55,6 +55,7 @@ struct DevSys {
   int64_t* panel_tasks = nullptr;
   int64_t* upd_tasks = nullptr;
   int64_t* ea_cols = nullptr;
+  int64_t* ea_kids = nullptr;
   int32_t* fill_tasks = nullptr;
   int64_t* vec_ptr = nullptr;
   int32_t* vec_src = nullptr;
@@ -329,6 +330,7 @@ size_t layout(sgn_ctx c, char* base) {
     D.panel_tasks = L.take<int64_t>(S.panel_tasks.size());
     D.upd_tasks = L.take<int64_t>(S.upd_tasks.size());
     D.ea_cols = L.take<int64_t>(S.ea_cols.size());
+    D.ea_kids = L.take<int64_t>(S.ea_kid_recs.size());
     D.fill_tasks = L.take<int32_t>(S.fill_tasks.size());
     D.vec_ptr = L.take<int64_t>(S.vec_ptr.size());
     D.vec_src = L.take<int32_t>(S.vec_src.size());
@@ -648,8 +650,10 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   };
   for (int L = 0; L < S.nlevels; ++L) {
     const LevelPlan& P = S.levels[L];
-    for (size_t r = 0; r < P.ea_work.size(); ++r)
+    for (size_t r = 0; r < P.ea_work.size(); ++r) {
+      launch_extend_add_small<T>(P.ea_kids[r], D.ea_kids + P.ea_kid_begin[r] * 5, f, front, st);
       launch_extend_add<T>(P.ea_work[r], D.ea_cols + P.ea_col_begin[r] * 4, f, front, st);
+    }
     // Look-ahead: the delayed update of a block's columns beyond the next block runs on the second
     // stream, beside the next block's panels (which touch only the next block's columns and its W
     // rows).  The main stream waits for it before the next delayed update of the next block's
@@ -2521,6 +2525,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.panel_tasks, S.panel_tasks, st));
     HIPCHK(up(D.upd_tasks, S.upd_tasks, st));
     HIPCHK(up(D.ea_cols, S.ea_cols, st));
+    HIPCHK(up(D.ea_kids, S.ea_kid_recs, st));
     HIPCHK(up(D.fill_tasks, S.fill_tasks, st));
     HIPCHK(up(D.vec_ptr, S.vec_ptr, st));
     HIPCHK(up(D.vec_src, S.vec_src, st));

@@ -131,6 +131,49 @@ __global__ void __launch_bounds__(256) k_extend_add(int64_t ncols, const int64_t
   }
 }
 
+// Extend-add of a whole small child (u <= kSmallChild) by one block: the lower triangle of its
+// update block, column-major, flattened over the threads (short columns would leave most lanes of a
+// per-column wavefront idle).  Entry e sits in column c with off(c) <= e < off(c + 1),
+// off(c) = c u - c (c - 1) / 2, the smaller root of a quadratic taken in FP32 (exact integers below
+// 2^24) and corrected by one step either way.  Every load of a thread (clamped to entry 0) before
+// its first store; the relative map is injective, so a block's parent entries are distinct, and
+// the children of one round have different parents.
+template <typename T>
+__global__ void __launch_bounds__(256) k_extend_add_small(const int64_t* __restrict__ kids, FrontArgs f,
+                                                          T* __restrict__ front) {
+  constexpr int R = 4;
+  const int tid = threadIdx.x;
+  const int64_t* rec = kids + 5 * (int64_t)blockIdx.x;
+  const T* src = front + rec[0];
+  T* dst = front + rec[1];
+  const int32_t* rel = f.relmap + rec[2];
+  const int64_t mc = rec[3];
+  const int64_t mp = rec[4] >> 32;
+  const int u = (int)(rec[4] & 0xffffffffll);
+  const int total = u * (u + 1) / 2;
+  const float b2 = 2.0f * (float)u + 1.0f;
+  for (int e0 = 0; e0 < total; e0 += 256 * R) {
+    T v[R], o[R];
+    int64_t d[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = e0 + tid + 256 * q, ec = e < total ? e : 0;
+      int c = (int)((b2 - sqrtf(b2 * b2 - 8.0f * (float)ec)) * 0.5f);
+      c = c < 0 ? 0 : (c > u - 1 ? u - 1 : c);
+      c -= (c * u - c * (c - 1) / 2 > ec) ? 1 : 0;
+      c += (c + 1 < u && (c + 1) * u - (c + 1) * c / 2 <= ec) ? 1 : 0;
+      const int r = c + (ec - (c * u - c * (c - 1) / 2));
+      v[q] = src[r + c * mc];
+      d[q] = (int64_t)rel[r] + (int64_t)rel[c] * mp;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) o[q] = dst[d[q]];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (e0 + tid + 256 * q < total) dst[d[q]] = o[q] + v[q];
+  }
+}
+
 // Factorisation of one panel's diagonal block (w <= WM <= 64) in LDS, FP64, 64 * WAVES threads.
 // WAVES = 8 shortens a lone panel's step (the update is split over eight wavefronts); WAVES = 1
 // leaves no wavefront repeating another's pivot search, which pays when a step holds enough panels
@@ -740,6 +783,11 @@ void launch_extend_add(int64_t ncols, const int64_t* cols, const FrontArgs& f, T
 }
 
 template <typename T>
+void launch_extend_add_small(int64_t nkids, const int64_t* kids, const FrontArgs& f, T* front, hipStream_t s) {
+  if (nkids > 0) k_extend_add_small<T><<<(unsigned)nkids, 256, 0, s>>>(kids, f, front);
+}
+
+template <typename T>
 void launch_panel_diag(int64_t ntasks, int max_w, int waves, const int64_t* tasks, const FrontArgs& f, T* front,
                        hipStream_t s) {
   if (ntasks <= 0) return;
@@ -782,6 +830,8 @@ template void launch_zero_fronts<double>(int64_t, const int32_t*, const FrontArg
 template void launch_zero_fronts<float>(int64_t, const int32_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_extend_add<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
 template void launch_extend_add<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+template void launch_extend_add_small<double>(int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
+template void launch_extend_add_small<float>(int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
 template void launch_panel_diag<double>(int64_t, int, int, const int64_t*, const FrontArgs&, double*,
                                          hipStream_t);
 template void launch_panel_diag<float>(int64_t, int, int, const int64_t*, const FrontArgs&, float*,

@@ -149,6 +149,10 @@ void launch_csr_to_fronts(int64_t nnz, const int32_t* slot_row, const int32_t* c
 // ntasks (sn, first column) pairs
 template <typename T>
 void launch_zero_fronts(int64_t ntasks, const int32_t* tasks, const FrontArgs& f, T* front, hipStream_t s);
+// Extend-add of whole small children (u <= kSmallChild), one block each: kids holds 5 int64 per
+// child (see System::ea_kid_recs).
+template <typename T>
+void launch_extend_add_small(int64_t nkids, const int64_t* kids, const FrontArgs& f, T* front, hipStream_t s);
 template <typename T>
 void launch_extend_add(int64_t ncols, const int64_t* cols, const FrontArgs& f, T* front, hipStream_t s);
 template <typename T>

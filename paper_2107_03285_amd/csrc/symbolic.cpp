@@ -388,6 +388,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.panel_tasks.clear();
   S.upd_tasks.clear();
   S.ea_cols.clear();
+  S.ea_kid_recs.clear();
   S.solve_fwd_tasks.clear();
   S.solve_bwd_tasks.clear();
   S.n_panels = (int64_t)S.panel_col.size();
@@ -442,13 +443,24 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     P.bwd_end = (int64_t)S.solve_bwd_tasks.size() / 2;
     for (int r = 0; r < P.max_children; ++r) {
       P.ea_col_begin.push_back((int64_t)S.ea_cols.size() / 4);
-      int64_t work = 0;
+      P.ea_kid_begin.push_back((int64_t)S.ea_kid_recs.size() / 5);
+      int64_t work = 0, kids = 0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
         int t = S.level_sn[q];
         if (S.child_ptr[t + 1] - S.child_ptr[t] > r) {
           int c = S.child_list[S.child_ptr[t] + r];
           const int64_t uc = S.sn_rows_ptr[c + 1] - S.sn_rows_ptr[c];
           const int64_t sc = S.sn_begin[c + 1] - S.sn_begin[c], mc = S.sn_m[c], mp = S.sn_m[t];
+          if (uc == 0) continue;
+          if (uc <= kSmallChild) {  // one block per child, its lower triangle flattened
+            S.ea_kid_recs.push_back(S.sn_front_off[c] + sc + sc * mc);
+            S.ea_kid_recs.push_back(S.sn_front_off[t]);
+            S.ea_kid_recs.push_back(S.relmap_off[c]);
+            S.ea_kid_recs.push_back(mc);
+            S.ea_kid_recs.push_back((mp << 32) | uc);
+            ++kids;
+            continue;
+          }
           for (int64_t j = 0; j < uc; ++j) {  // one wavefront per child column
             S.ea_cols.push_back(S.sn_front_off[c] + sc + (sc + j) * mc);
             S.ea_cols.push_back(S.sn_front_off[t] + (int64_t)S.relmap[S.relmap_off[c] + j] * mp);
@@ -459,6 +471,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         }
       }
       P.ea_work.push_back(work);
+      P.ea_kids.push_back(kids);
     }
     for (int k = 0; k < maxp; ++k) {
       PanelStep ps;

@@ -13,6 +13,7 @@ namespace sgn {
 constexpr int kPanel = 64;        // panel width of the blocked front factorisation
 constexpr int kNarrowPanel = 32;  // panels this narrow are listed first in each step's task range
 constexpr int kOneMaxM = 512;     // one-panel fronts up to this order are solved by one wavefront each
+constexpr int kSmallChild = 128;  // update blocks up to this order are added by one block per child
 constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
 constexpr int kTile = 64;         // update tile edge (equal to the kernels' kUpdTile)
 constexpr int kSolveKC = 256;     // k-chunk of the split-k L21 y product in the forward solve
@@ -69,8 +70,9 @@ struct PanelStep {
 struct LevelPlan {
   int64_t sn_begin, sn_end;            // range in level_sn (supernodes of this level)
   int max_children;                    // extend-add rounds
-  std::vector<int64_t> ea_work;                    // per round: child columns
+  std::vector<int64_t> ea_work;                    // per round: child columns (children past kSmallChild)
   std::vector<int64_t> ea_col_begin;               // per round: its first column record in ea_cols
+  std::vector<int64_t> ea_kids, ea_kid_begin;      // per round: children of u <= kSmallChild, first record
   std::vector<PanelStep> steps;
   int64_t max_m = 0, max_s = 0, max_u = 0;
   // solves: solve_sn[sn_begin, one_begin) are solved by the level kernels (solve_max_s, solve_max_u
@@ -131,6 +133,9 @@ struct System {
   // column's rows c.. follow), front offset of the parent column it adds into, offset of the child's
   // relative map, (c << 32) | uC
   std::vector<int64_t> ea_cols;
+  // per small child of a round, 5 entries: front offset of its entry (sC, sC), front offset of the
+  // parent, offset of its relative map, mC, (mP << 32) | uC
+  std::vector<int64_t> ea_kid_recs;
   std::vector<int32_t> solve_fwd_tasks;  // (sn, panel index) pairs, per level; (sn, -1): whole front in one block
   std::vector<int32_t> solve_bwd_tasks;
   int64_t n_panels = 0;                  // total panels (ready flags of the pipelined solves)
