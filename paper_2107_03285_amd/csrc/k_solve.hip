@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(256) k_bwd_panels(const int32_t* __restrict__ 
   }
 }
 
-// ---- fronts of one panel (s <= 64 pivots, order m <= kOneMaxM): one wavefront per front
+// ---- fronts of one panel (s <= 64 pivots, u <= kOneMaxU rows below them): one wavefront per front
 //
 // Forward: the gathered right-hand side t (pivot entries of b, children's contribution vectors
 // added in the fixed child order) stays in LDS; y = L11^-1 P t_s by substitution with the unit

@@ -191,7 +191,7 @@ void launch_fwd_level(int64_t nsn, int64_t max_u, int64_t max_s, const int32_t* 
 template <typename T>
 void launch_bwd_level(int64_t nsn, int64_t max_s, const int32_t* level_sn, const int32_t* tasks, int64_t ntasks,
                       const SolveArgs& a, const T* front, double* x, int* counter, int* err, hipStream_t s);
-// The same level step for fronts of one panel (s <= 64) and order m <= kOneMaxM, one wavefront each:
+// The same level step for fronts of one panel (s <= 64) and u = m - s <= kOneMaxU, one wavefront each:
 // forward gather, permutation, unit lower solve and contribution vector; backward D^-1 y (or wd),
 // the rows-below product and the transposed unit lower solve.
 template <typename T>

@@ -407,7 +407,9 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         P.max_u = std::max<int64_t>(P.max_u, S.sn_m[t] - (S.sn_begin[t + 1] - S.sn_begin[t]));
       }
     P.sn_end = (int64_t)S.level_sn.size();
-    auto one_panel = [&](int t) { return S.panel_ptr[t + 1] - S.panel_ptr[t] - 1 == 1 && S.sn_m[t] <= kOneMaxM; };
+    auto one_panel = [&](int t) {
+      return S.panel_ptr[t + 1] - S.panel_ptr[t] - 1 == 1 && S.sn_m[t] - (S.sn_begin[t + 1] - S.sn_begin[t]) <= kOneMaxU;
+    };
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1) P.one_begin = (int64_t)S.solve_sn.size();
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
