@@ -341,9 +341,22 @@ __device__ inline double sum_sources(int64_t q0, int64_t q1, const int32_t* __re
   return acc;
 }
 
+// Index of this workgroup once renumbered so that each of the 8 dies (workgroups go to them
+// round-robin by index, each die with its own L2) takes one contiguous run of [0, gridDim.x).
+__device__ inline int64_t die_contiguous_block() {
+  const int64_t n = gridDim.x, x = blockIdx.x & 7;
+  int64_t before = 0;
+  for (int64_t y = 0; y < x; ++y) before += (n - y + 7) >> 3;
+  return before + (blockIdx.x >> 3);
+}
+
+// Workgroups go to the 8 dies (each with its own L2) round-robin by index; renumbered, each die takes
+// one contiguous run of the slots (rows of the elimination order, so a region of the mesh), and the
+// element values of that region are fetched into its L2 once instead of once per die.
 __global__ void k_gather_slots(int64_t nnz, const int64_t* __restrict__ ptr, const int32_t* __restrict__ src,
                                const double* __restrict__ ebuf, double* __restrict__ vals) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * blockDim.x)
+  const int64_t b = die_contiguous_block();
+  for (int64_t t = b * blockDim.x + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * blockDim.x)
     vals[t] = sum_sources(ptr[t], ptr[t + 1], src, ebuf);
 }
 
