@@ -584,16 +584,15 @@ sgn_status read_update_events(sgn_ctx c) {
   return SGN_OK;
 }
 
-// Wavefronts per panel's diagonal-block factorisation for a launch of n panels.  Every wavefront
-// repeats the pivot search, the update of a step is split among them: with few panels the step's
-// latency decides (eight), with many the issue of all wavefronts' instructions does, since four
-// blocks of a 64-row LDS block fill a compute unit (four from 512 panels on), and narrow panels (a
-// 32-row block, 18 blocks per compute unit) do best with one from 1024 on.  Measured on the
-// 256-membrane union and the 100 x 25 x 25 cantilever; the factor is the same bits whatever the count.
-int panel_waves_for(int64_t n, bool narrow) {
-  if (narrow && n >= 1024) return 1;
-  return n >= 512 ? 4 : 8;
-}
+// Wavefronts per panel's diagonal-block factorisation for a launch of n panels (of up to 64
+// columns).  Every wavefront repeats the pivot search, the update of a step is split among them:
+// with few panels the step's latency decides (eight), with many the issue of all wavefronts'
+// instructions does, since four blocks of a 64-row LDS block fill a compute unit (four from 512
+// panels on).  Narrow panels (a 32-row block, 18 blocks per compute unit) do best with one
+// wavefront once a step has kNarrowSpread of them.  Measured on the 256-membrane union and the
+// 100 x 25 x 25 cantilever; the factor is the same bits whatever the count.
+constexpr int64_t kNarrowSpread = 1024;
+int panel_waves_for(int64_t n) { return n >= 512 ? 4 : 8; }
 
 template <typename T>
 sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
@@ -661,14 +660,19 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
     bool side_busy = false;
     for (const PanelStep& ps : P.steps) {
       const int64_t nt = ps.task_end - ps.task_begin;
-      // narrow panels (listed first) and wide ones in launches of their own, each with the
-      // wavefront count that suits its panel count
+      // narrow panels (listed first) in a launch of their own when there are enough of them for the
+      // one-wavefront form, else every panel of the step in one launch (a second launch on this
+      // chain costs more than it saves)
       const int64_t nn = ps.narrow_end - ps.task_begin, nw = ps.task_end - ps.narrow_end;
       const int pw = c->A.tune.panel_waves;
-      launch_panel_diag<T>(nn, kNarrowPanel, pw != 0 ? pw : panel_waves_for(nn, true), D.panel_tasks + ps.task_begin * 3,
-                           f, front, st);
-      launch_panel_diag<T>(nw, kPanel, pw != 0 ? pw : panel_waves_for(nw, false), D.panel_tasks + ps.narrow_end * 3, f,
-                           front, st);
+      if (pw == 1 || (pw == 0 && nn >= kNarrowSpread)) {
+        launch_panel_diag<T>(nn, kNarrowPanel, 1, D.panel_tasks + ps.task_begin * 3, f, front, st);
+        launch_panel_diag<T>(nw, kPanel, pw != 0 ? pw : panel_waves_for(nw), D.panel_tasks + ps.narrow_end * 3, f,
+                             front, st);
+      } else {
+        launch_panel_diag<T>(nt, kPanel, pw != 0 ? pw : panel_waves_for(nt), D.panel_tasks + ps.task_begin * 3, f,
+                             front, st);
+      }
       launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
       HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops, st));
       if (ps.outer_tiles > 0 && side_busy) {

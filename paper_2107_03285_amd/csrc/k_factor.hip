@@ -559,9 +559,7 @@ __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ 
 }
 
 // C[r, c] -= sum_{k in [k0,k1)} L[r,k] (L D)[c,k] on one 64 x 64 tile, MFMA 16x16x4.
-// KC k-values per chunk; DB: two LDS buffers, one barrier per chunk (the next chunk is staged into the
-// other buffer after this one's products), else one buffer and two barriers.
-template <typename T, int KC, bool DB>
+template <typename T>
 __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* __restrict__ tasks, FrontArgs f,
                                                 T* __restrict__ front) {
   // 64 x 64 tile per block, 32 x 32 per wave (2 x 2 MFMA blocks of 16 x 16); the next k-chunk's loads
@@ -571,19 +569,17 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
   // k = (KC/4) g + s to both operands, so each lane reads its KC/4 W values of a chunk with 16-byte
   // LDS loads.
   constexpr int TM = kUpdTile;
+  constexpr int KC = sizeof(T) == 8 ? 16 : 32;  // k per chunk (FP64 halves it to keep the occupancy)
   constexpr int KS = KC / 4;                  // MFMA steps per chunk
   constexpr int NQ = TM * KC / 256;           // loads per thread and chunk, each of L and W
   constexpr int CQ = 256 / KC;                // W columns covered by one load instruction of the block
-  // sL rows KS = 4 apart (one lane group to the next) start 4 SL = 272 (FP32) or 544 (FP64) banks
-  // apart: 16 or 32 of the 64 banks, so the four groups' reads never collide
-  static_assert(KS == 4, "the sL row stride is chosen for four MFMA steps per chunk");
-  constexpr int SL = TM + 4;
+  // sL rows KS apart (one lane group to the next) start 16 (FP32) or 32 (FP64) banks apart
+  constexpr int SL = sizeof(T) == 8 ? TM + 4 : TM + 2;
   constexpr int SW = KC + 16 / (int)sizeof(T);  // 16-byte rows; 16 lanes reading 16 B each cover all banks
   constexpr int VW = 16 / (int)sizeof(T);     // elements per 16-byte LDS read
   typedef T vecw __attribute__((ext_vector_type(VW)));
-  constexpr int NB = DB ? 2 : 1;
-  __shared__ T sLb[NB][KC][SL];                    // sL[k][r]
-  __shared__ __attribute__((aligned(16))) T sWb[NB][TM][SW];  // sW[c][k]
+  __shared__ T sL[KC][SL];                    // sL[k][r]
+  __shared__ __attribute__((aligned(16))) T sW[TM][SW];  // sW[c][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // Workgroups are handed to the 8 dies (each with its own L2) round-robin by index; renumber so that
   // each die takes one contiguous run of tiles.  In that run the tiles of one row of a column group
@@ -654,13 +650,21 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
       accf[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
     }
   const int g = lane >> 4, li = lane & 15;
-  auto compute = [&](int buf) {
+  load(k0);
+  for (int64_t kb = k0; kb < k1; kb += KC) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      sL[kl + 4 * q][rr] = rl[q];
+      sW[cw + CQ * q][kw] = rw[q];
+    }
+    __syncthreads();
+    if (kb + KC < k1) load(kb + KC);
     T aw[2][KS];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int v = 0; v < KS / VW; ++v) {
-        const vecw x = *(const vecw*)&sWb[buf][wc + bj * 16 + li][KS * g + VW * v];
+        const vecw x = *(const vecw*)&sW[wc + bj * 16 + li][KS * g + VW * v];
 #pragma unroll
         for (int e = 0; e < VW; ++e) aw[bj][VW * v + e] = x[e];
       }
@@ -668,7 +672,7 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
     for (int st = 0; st < KS; ++st) {
       T bv[2];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi) bv[bi] = sLb[buf][KS * g + st][wr + bi * 16 + li];
+      for (int bi = 0; bi < 2; ++bi) bv[bi] = sL[KS * g + st][wr + bi * 16 + li];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -680,37 +684,7 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
           }
         }
     }
-  };
-  auto stage = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      sLb[buf][kl + 4 * q][rr] = rl[q];
-      sWb[buf][cw + CQ * q][kw] = rw[q];
-    }
-  };
-  load(k0);
-  if constexpr (DB) {
-    // two LDS buffers: the next chunk is staged into the other buffer after this one's products, so
-    // one barrier per chunk separates a buffer's readers from its next writers
-    stage(0);
     __syncthreads();
-    int buf = 0;
-    for (int64_t kb = k0; kb < k1; kb += KC) {
-      const bool more = kb + KC < k1;
-      if (more) load(kb + KC);
-      compute(buf);
-      if (more) stage(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
-    }
-  } else {
-    for (int64_t kb = k0; kb < k1; kb += KC) {
-      stage(0);
-      __syncthreads();
-      if (kb + KC < k1) load(kb + KC);
-      compute(0);
-      __syncthreads();
-    }
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -835,10 +809,7 @@ void launch_panel_trsm(int64_t ntasks, int64_t max_rows, const int64_t* tasks, c
 template <typename T>
 void launch_update(int64_t ntasks, int64_t ntiles, const int64_t* tasks, const FrontArgs& f, T* front,
                    hipStream_t s) {
-  if (ntasks <= 0 || ntiles <= 0) return;
-  // FP32: k-chunks of 16 through two LDS buffers (18.7 KB, eight wavefronts per SIMD); FP64: chunks of
-  // 16 through one (a second would halve its occupancy)
-  k_update<T, 16, sizeof(T) == 4><<<(unsigned)ntiles, 256, 0, s>>>(ntasks, tasks, f, front);
+  if (ntasks > 0 && ntiles > 0) k_update<T><<<(unsigned)ntiles, 256, 0, s>>>(ntasks, tasks, f, front);
 }
 
 void launch_inertia(int64_t N, const double* dpiv, const double* epiv, const int32_t* pivtype,

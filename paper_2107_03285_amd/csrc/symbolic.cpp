@@ -410,11 +410,16 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     auto one_panel = [&](int t) {
       return S.panel_ptr[t + 1] - S.panel_ptr[t] - 1 == 1 && S.sn_m[t] - (S.sn_begin[t + 1] - S.sn_begin[t]) <= kOneMaxU;
     };
+    // the one-wavefront form pays only with many such fronts in the level (with few, the level
+    // kernels' several blocks per front finish sooner)
+    int64_t n_one = 0;
+    for (int64_t q = P.sn_begin; q < P.sn_end; ++q) n_one += one_panel(S.level_sn[q]) ? 1 : 0;
+    const bool use_one = n_one >= kOneMinFronts;
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1) P.one_begin = (int64_t)S.solve_sn.size();
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
         const int t = S.level_sn[q];
-        if (one_panel(t) != (pass == 1)) continue;
+        if ((use_one && one_panel(t)) != (pass == 1)) continue;
         S.solve_sn.push_back(t);
         if (pass == 0) {
           P.solve_max_s = std::max<int64_t>(P.solve_max_s, S.sn_begin[t + 1] - S.sn_begin[t]);

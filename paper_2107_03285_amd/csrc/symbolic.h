@@ -13,7 +13,8 @@ namespace sgn {
 constexpr int kPanel = 64;        // panel width of the blocked front factorisation
 constexpr int kNarrowPanel = 32;  // panels this narrow are listed first in each step's task range
 constexpr int kOneMaxU = 128;     // one-panel fronts with at most this many rows below the pivots are
-constexpr int kOneMaxM = kPanel + kOneMaxU;  // solved by one wavefront each (order <= kOneMaxM)
+constexpr int kOneMaxM = kPanel + kOneMaxU;  // solved by one wavefront each (order <= kOneMaxM) when a
+constexpr int kOneMinFronts = 1024;          // level has at least kOneMinFronts of them
 constexpr int kSmallChild = 128;  // update blocks up to this order are added by one block per child
 constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
 constexpr int kTile = 64;         // update tile edge (equal to the kernels' kUpdTile)
@@ -125,7 +126,8 @@ struct System {
   // schedule
   int nlevels = 0;
   std::vector<int32_t> level_sn;         // supernodes grouped by level
-  std::vector<int32_t> solve_sn;         // the same per level, one-panel fronts with u <= kOneMaxU last
+  std::vector<int32_t> solve_sn;         // the same per level, one-panel fronts with u <= kOneMaxU last (in
+                                         // levels with at least kOneMinFronts of them)
   std::vector<LevelPlan> levels;
   // task tables (flattened int64 quintuples, see kernels)
   std::vector<int64_t> panel_tasks;      // (sn, c0, c1) per task: 3 entries
