@@ -470,11 +470,12 @@ void sgn_destroy(sgn_ctx ctx);
  * with hipMalloc on the current device, everything freed before the next) and is timed as the best
  * of `reps` (1..100) rounds of assembly + factorisation + solve of a right-hand side of ones, after
  * one warm-up round, in host wall milliseconds on `stream`.  Coordinate descent from *base: each
- * bucket's outer_panels in {1, 2, 4, 8, 16}, then seq_panels in {-1, 2, 4, 8}; a candidate replaces the
- * incumbent only if it is at least 1% faster.  *best receives *base with the chosen setting;
- * h_ms (optional, host, room for 16) the milliseconds of the candidates in the order tried, the
- * first being *base itself (the first 16 only); *n_cand (optional) the number tried: 16 when
- * *base's settings are among the candidates, up to 20 otherwise.  Errors of a candidate's
+ * bucket's outer_panels in {1, 2, 4, 8, 16}, then seq_panels in {-1, 2, 4, 8}, then the panel
+ * factorisation's wavefront policy panel_waves in {0, 8, 4}; a candidate replaces the incumbent only
+ * if it is at least 1% faster.  *best receives *base with the chosen setting; h_ms (optional, host,
+ * room for 24) the milliseconds of the candidates in the order tried, the first being *base itself;
+ * *n_cand (optional) the number tried: 18 when *base's settings are among the candidates, up to 23
+ * otherwise.  Errors of a candidate's
  * context (e.g. SGN_E_NOMEM when the device cannot hold it) end the search and are returned. */
 sgn_status sgn_autotune(const sgn_problem* prob, const sgn_options* base, const double* d_x, const double* d_p,
                         int reps, void* stream, sgn_options* best, double* h_ms, int* n_cand);

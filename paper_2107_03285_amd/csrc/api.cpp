@@ -3412,7 +3412,7 @@ sgn_status sgn_autotune(const sgn_problem* prob, const sgn_options* base, const 
   double cur_ms = 0.0;
   sgn_status st = time_candidate(prob, cur, d_x, d_p, reps, stream, &cur_ms);
   if (st != SGN_OK) return st;
-  constexpr int kRecorded = 16;  // entries of h_ms the caller provides
+  constexpr int kRecorded = 24;  // entries of h_ms the caller provides
   if (h_ms) h_ms[nc] = cur_ms;
   ++nc;
   auto consider = [&](const sgn_options& cand) -> sgn_status {
@@ -3444,6 +3444,16 @@ sgn_status sgn_autotune(const sgn_problem* prob, const sgn_options* base, const 
       if (v == inc) continue;
       sgn_options cand = cur;
       cand.seq_panels = v;
+      if ((st = consider(cand)) != SGN_OK) return st;
+    }
+  }
+  {
+    static const int kWaves[] = {0, 8, 4};  // 0: by each launch's panel count
+    const int inc = cur.panel_waves;
+    for (int v : kWaves) {
+      if (v == inc) continue;
+      sgn_options cand = cur;
+      cand.panel_waves = v;
       if ((st = consider(cand)) != SGN_OK) return st;
     }
   }

@@ -213,7 +213,8 @@ def _problem_struct(prob):
 
 def tuning_of(o: sgn_options) -> dict:
     """The schedule-blocking fields of an options struct."""
-    return {"outer_panels": [int(v) for v in o.outer_panels], "seq_panels": int(o.seq_panels)}
+    return {"outer_panels": [int(v) for v in o.outer_panels], "seq_panels": int(o.seq_panels),
+            "panel_waves": int(o.panel_waves)}
 
 
 def apply_tuning(o: sgn_options, tuning: dict) -> sgn_options:
@@ -221,6 +222,7 @@ def apply_tuning(o: sgn_options, tuning: dict) -> sgn_options:
     for b, v in enumerate(tuning["outer_panels"]):
         o.outer_panels[b] = int(v)
     o.seq_panels = int(tuning["seq_panels"])
+    o.panel_waves = int(tuning.get("panel_waves", 0))  # records from before this field: by launch
     return o
 
 
@@ -232,14 +234,14 @@ def autotune(prob, x, p, options: sgn_options = None, reps: int = 3, stream=None
     P, keep = _problem_struct(prob)
     base = options if options is not None else default_options()
     best = sgn_options()
-    ms = (C.c_double * 16)()
+    ms = (C.c_double * 24)()
     n = C.c_int(0)
     sp = C.c_void_p(int(stream.cuda_stream)) if stream is not None else None
     st = lib.sgn_autotune(C.byref(P), C.byref(base), _dev_ptr(x), _dev_ptr(p), int(reps), sp, C.byref(best), ms,
                           C.byref(n))
     if st != SGN_OK:
         raise SgnError(st, "autotune: a candidate context failed")
-    rec = dict(tuning_of(best), base=tuning_of(base), candidate_ms=[float(v) for v in ms[:min(n.value, 16)]],
+    rec = dict(tuning_of(best), base=tuning_of(base), candidate_ms=[float(v) for v in ms[:min(n.value, 24)]],
                reps=int(reps), problem=getattr(prob, "name", ""))
     if path:
         with open(path, "w") as f:

@@ -71,7 +71,8 @@ def test_schedule_blocking_leaves_the_symbolic_structure_unchanged():
     _lib()
     prob = si.config_cantilever_small()
     ref = sgn.Context(prob).symbolic(sgn.SGN_SYS_SGN)
-    for tun in ({"outer_panels": [1, 2, 8], "seq_panels": -1}, {"outer_panels": [8, 1, 2], "seq_panels": 2}):
+    for tun in ({"outer_panels": [1, 2, 8], "seq_panels": -1, "panel_waves": 0},
+                {"outer_panels": [8, 1, 2], "seq_panels": 2, "panel_waves": 4}):
         ctx = sgn.Context(prob, sgn.apply_tuning(sgn.default_options(), tun))
         for a, b in zip(ctx.symbolic(sgn.SGN_SYS_SGN), ref):
             assert np.array_equal(a, b)

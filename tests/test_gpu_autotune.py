@@ -83,7 +83,7 @@ def test_autotune_returns_a_valid_setting_with_the_same_step(tmp_path):
     path = tmp_path / "tuning.json"
     rec = sgn.autotune(prob, xd, pd, base, reps=1, path=str(path))
     assert rec == json.loads(path.read_text())
-    assert len(rec["candidate_ms"]) == 16 and all(v > 0 for v in rec["candidate_ms"])
+    assert len(rec["candidate_ms"]) == 18 and all(v > 0 for v in rec["candidate_ms"])
     assert all(v in (0, 1, 2, 4, 8, 16) for v in rec["outer_panels"])
     assert rec["seq_panels"] in (0, -1, 2, 4, 8)
     tuned = sgn.apply_tuning(sgn.default_options(precision=sgn.SGN_FP32_IR, newton_rtol=1e-11), rec)
@@ -91,4 +91,6 @@ def test_autotune_returns_a_valid_setting_with_the_same_step(tmp_path):
     _, s_base = _step(prob, x, p, base)
     assert _rel(s_tuned, s_base) <= 1e-9
     # the record round-trips into options
-    assert sgn.tuning_of(tuned) == {"outer_panels": rec["outer_panels"], "seq_panels": rec["seq_panels"]}
+    assert rec["panel_waves"] in (0, 4, 8)
+    assert sgn.tuning_of(tuned) == {"outer_panels": rec["outer_panels"], "seq_panels": rec["seq_panels"],
+                                    "panel_waves": rec["panel_waves"]}
