@@ -71,6 +71,34 @@ def test_union_step_matches_each_problem(precision):
 
 
 @pytest.mark.parametrize("precision", [sgn.SGN_FP64, sgn.SGN_FP32_IR])
+def test_large_union_one_wavefront_forms_match_each_problem(precision):
+    """96 membranes of 8..16 nodes per side: the union's leaf level has 1,670 one-panel fronts with
+    at most 128 rows below the pivots and 1,358 panels of at most 32 columns (host analysis of this
+    union), past the 1,024 from which the solves take one wavefront per front and the narrow panels
+    one wavefront each, so both forms run here (the smaller unions above keep the level kernels).
+    Every problem's dp must still be its own dense Gauss-Newton step, and the solve's residual
+    small."""
+    probs, u, refs = _batch(96, 8, 16)
+    ctx = sgn.Context(u, sgn.default_options(precision=precision, rhs_kind=sgn.SGN_RHS_KKT)).allocate()
+    p = _d(u.p_init())
+    x = _d(np.concatenate([r[0] for r in refs]))
+    N = 2 * u.n_x + u.n_p
+    rhs = torch.zeros(N, dtype=torch.float64, device="cuda")
+    sol = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.assemble(x, p, rhs)
+    fi = ctx.factor()
+    assert (fi.n_pos, fi.n_neg, fi.n_zero) == (u.n_x + u.n_p, u.n_x, 0)
+    info = ctx.solve(rhs, sol)
+    assert info.rel_res <= 1e-10
+    dp = _h(sol)[u.n_x:u.n_x + u.n_p]
+    po, _ = _offsets(probs)
+    tol = 1e-9 if precision == sgn.SGN_FP64 else 1e-8
+    for i, (q, (x0, dref)) in enumerate(zip(probs, refs)):
+        got = dp[po[i]:po[i + 1]]
+        assert np.linalg.norm(got - dref) <= tol * np.linalg.norm(dref), q.name
+
+
+@pytest.mark.parametrize("precision", [sgn.SGN_FP64, sgn.SGN_FP32_IR])
 def test_graph_step_replays_match_eager(precision):
     probs, u, refs = _batch()
     o = sgn.default_options(precision=precision, rhs_kind=sgn.SGN_RHS_KKT)
