@@ -148,8 +148,9 @@ typedef struct {
   int pc_kind;                  /* SGN_PC_FACTOR (default) | SGN_PC_BLOCK, fixed at create */
   int panel_waves;              /* wavefronts per panel's diagonal-block factorisation (no effect on
                                    the results): 1, 2, 4, 8, or 0 = by the launch (panels of at most
-                                   32 columns: one when a step has at least 1024 of them; otherwise
-                                   four from 512 panels, else eight) */
+                                   32 columns: one when a step has at least 1024 of them; of at most
+                                   48 columns: four in a 48-row block from 512 of them; otherwise four
+                                   from 512 panels, else eight) */
 } sgn_options;
 
 typedef struct { int iters; int halvings; double res_norm; double f_ext_norm; int converged; } sgn_eq_info;

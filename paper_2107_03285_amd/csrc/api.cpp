@@ -592,6 +592,7 @@ sgn_status read_update_events(sgn_ctx c) {
 // wavefront once a step has kNarrowSpread of them.  Measured on the 256-membrane union and the
 // 100 x 25 x 25 cantilever; the factor is the same bits whatever the count.
 constexpr int64_t kNarrowSpread = 1024;
+constexpr int64_t kMediumSpread = 512;
 int panel_waves_for(int64_t n) { return n >= 512 ? 4 : 8; }
 
 template <typename T>
@@ -660,19 +661,24 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
     bool side_busy = false;
     for (const PanelStep& ps : P.steps) {
       const int64_t nt = ps.task_end - ps.task_begin;
-      // narrow panels (listed first) in a launch of their own when there are enough of them for the
-      // one-wavefront form, else every panel of the step in one launch (a second launch on this
-      // chain costs more than it saves)
-      const int64_t nn = ps.narrow_end - ps.task_begin, nw = ps.task_end - ps.narrow_end;
+      // Width classes (narrow, medium, wide; listed in that order) get launches of their own only
+      // when there are enough of them for the smaller block to pay (narrow: one wavefront and a
+      // 32-row block; medium: four wavefronts and a 48-row block, eight blocks per compute unit);
+      // the rest of the step goes in one launch (another launch on this chain costs more than it
+      // saves).
       const int pw = c->A.tune.panel_waves;
-      if (pw == 1 || (pw == 0 && nn >= kNarrowSpread)) {
-        launch_panel_diag<T>(nn, kNarrowPanel, 1, D.panel_tasks + ps.task_begin * 3, f, front, st);
-        launch_panel_diag<T>(nw, kPanel, pw != 0 ? pw : panel_waves_for(nw), D.panel_tasks + ps.narrow_end * 3, f,
-                             front, st);
-      } else {
-        launch_panel_diag<T>(nt, kPanel, pw != 0 ? pw : panel_waves_for(nt), D.panel_tasks + ps.task_begin * 3, f,
-                             front, st);
+      int64_t b = ps.task_begin;
+      if (pw == 1 || (pw == 0 && ps.narrow_end - b >= kNarrowSpread)) {
+        launch_panel_diag<T>(ps.narrow_end - b, kNarrowPanel, 1, D.panel_tasks + b * 3, f, front, st);
+        b = ps.narrow_end;
       }
+      if (pw == 4 || (pw == 0 && ps.medium_end - std::max(b, ps.narrow_end) >= kMediumSpread)) {
+        // narrow panels not launched above join the medium ones (a 48-row block holds them)
+        launch_panel_diag<T>(ps.medium_end - b, kMediumPanel, 4, D.panel_tasks + b * 3, f, front, st);
+        b = ps.medium_end;
+      }
+      launch_panel_diag<T>(ps.task_end - b, kPanel, pw != 0 ? pw : panel_waves_for(ps.task_end - b),
+                           D.panel_tasks + b * 3, f, front, st);
       launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
       HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops, st));
       if (ps.outer_tiles > 0 && side_busy) {

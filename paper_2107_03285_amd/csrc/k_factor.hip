@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
   __syncthreads();
   int npert = 0;
   int k = 0;
-  // lanes past WM hold no row of the block (WM = 32): they read zeros
+  // lanes past WM hold no row of the block (WM < 64): they read zeros
   const bool row_lane = WM == 64 || lane < WM;
   while (k < w) {
     double v = row_lane ? A[lane][k] : 0.0;
@@ -792,6 +792,7 @@ void launch_panel_diag(int64_t ntasks, int max_w, int waves, const int64_t* task
                        hipStream_t s) {
   if (ntasks <= 0) return;
   if (waves == 8) k_panel_diag<T, 8, 64><<<(unsigned)ntasks, 512, 0, s>>>(tasks, f, front);
+  else if (waves == 4 && max_w <= 48) k_panel_diag<T, 4, 48><<<(unsigned)ntasks, 256, 0, s>>>(tasks, f, front);
   else if (waves == 4) k_panel_diag<T, 4, 64><<<(unsigned)ntasks, 256, 0, s>>>(tasks, f, front);
   else if (waves == 2) k_panel_diag<T, 2, 64><<<(unsigned)ntasks, 128, 0, s>>>(tasks, f, front);
   else if (max_w <= 32) k_panel_diag<T, 1, 32><<<(unsigned)ntasks, 64, 0, s>>>(tasks, f, front);

@@ -483,19 +483,22 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
     for (int k = 0; k < maxp; ++k) {
       PanelStep ps;
       ps.task_begin = (int64_t)S.panel_tasks.size() / 3;
-      // panels of at most kNarrowPanel columns first (their own launch can use a smaller block)
-      for (int pass = 0; pass < 2; ++pass) {
+      // panels by width class: at most kNarrowPanel columns, at most kMediumPanel, the rest (their own
+      // launches can use smaller blocks)
+      for (int pass = 0; pass < 3; ++pass) {
         for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
           int t = S.level_sn[q];
           int np = S.panel_ptr[t + 1] - S.panel_ptr[t] - 1;
           if (k >= np) continue;
           const int c0 = S.panel_col[S.panel_ptr[t] + k], c1 = S.panel_col[S.panel_ptr[t] + k + 1];
-          if ((c1 - c0 <= kNarrowPanel) != (pass == 0)) continue;
+          const int cls = c1 - c0 <= kNarrowPanel ? 0 : (c1 - c0 <= kMediumPanel ? 1 : 2);
+          if (cls != pass) continue;
           S.panel_tasks.push_back(t);
           S.panel_tasks.push_back(c0);
           S.panel_tasks.push_back(c1);
         }
         if (pass == 0) ps.narrow_end = (int64_t)S.panel_tasks.size() / 3;
+        if (pass == 1) ps.medium_end = (int64_t)S.panel_tasks.size() / 3;
       }
       ps.task_end = (int64_t)S.panel_tasks.size() / 3;
       ps.trsm_rows = 0;

@@ -11,7 +11,8 @@
 namespace sgn {
 
 constexpr int kPanel = 64;        // panel width of the blocked front factorisation
-constexpr int kNarrowPanel = 32;  // panels this narrow are listed first in each step's task range
+constexpr int kNarrowPanel = 32;  // panels this narrow are listed first in each step's task range,
+constexpr int kMediumPanel = 48;  // then those of at most this many columns
 constexpr int kOneMaxU = 128;     // one-panel fronts with at most this many rows below the pivots are
 constexpr int kOneMaxM = kPanel + kOneMaxU;  // solved by one wavefront each (order <= kOneMaxM) when a
 constexpr int kOneMinFronts = 1024;          // level has at least kOneMinFronts of them
@@ -64,7 +65,8 @@ struct PanelStep {
   int64_t far_begin, far_end;      // range in the update task table (outer, k = block): the columns
                                    // beyond the next block, free to run beside its panels
   int64_t upd_tiles, outer_tiles, far_tiles;  // tiles of each update launch
-  int64_t narrow_end;              // tasks [task_begin, narrow_end) have at most kNarrowPanel columns
+  int64_t narrow_end;              // tasks [task_begin, narrow_end) have at most kNarrowPanel columns,
+  int64_t medium_end;              // [narrow_end, medium_end) at most kMediumPanel
   int64_t trsm_rows;               // max rows below the panel over the step's tasks
   double upd_flops, outer_flops, far_flops;   // algorithmic flops of the update launches
 };
