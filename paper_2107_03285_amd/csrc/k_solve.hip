@@ -570,20 +570,28 @@ __device__ void fwd_one(int J, const SolveArgs& a, const T* __restrict__ front, 
   const double zs = __shfl(tvl, src, 64);
   const double z = lane < s ? zs : 0.0;
   // y = L11^-1 z: L11[lane][j], j < lane, is kept at F[lane + j m] (below the diagonal of the
-  // panel's block); y_j is final once the steps before j are done.  Clamped loads, masked at use.
+  // panel's block); y_j is final once the steps before j are done.  Clamped loads, masked at use;
+  // each chunk's loads are issued while the previous chunk is used.
   double y = z;
   {
     const rsrc_t rs = buffer_rsrc(F, (int32_t)(((int64_t)(s - 1) * m + s) * (int64_t)sizeof(T)));
     const uint32_t voff = (uint32_t)((lane < s ? lane : 0) * (int)sizeof(T));
     const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
+    T cur[kOneChunk], nxt[kOneChunk];
+#pragma unroll
+    for (int j = 0; j < kOneChunk; ++j) cur[j] = buffer_load<T>(rs, voff, (j < s ? j : 0) * cstr);
 #pragma unroll 1
     for (int j0 = 0; j0 < s; j0 += kOneChunk) {
-      T fv[kOneChunk];
+      const int j1 = j0 + kOneChunk;
+      if (j1 < s) {
 #pragma unroll
-      for (int j = 0; j < kOneChunk; ++j) fv[j] = buffer_load<T>(rs, voff, (j0 + j < s ? j0 + j : 0) * cstr);
+        for (int j = 0; j < kOneChunk; ++j) nxt[j] = buffer_load<T>(rs, voff, (j1 + j < s ? j1 + j : 0) * cstr);
+      }
 #pragma unroll
       for (int j = 0; j < kOneChunk; ++j)
-        if (j0 + j < s) y -= (lane > j0 + j ? (double)fv[j] : 0.0) * lane_bcast(y, j0 + j);
+        if (j0 + j < s) y -= (lane > j0 + j ? (double)cur[j] : 0.0) * lane_bcast(y, j0 + j);
+#pragma unroll
+      for (int j = 0; j < kOneChunk; ++j) cur[j] = nxt[j];
     }
   }
   if (lane < s) tp[lane] = y;
@@ -591,22 +599,33 @@ __device__ void fwd_one(int J, const SolveArgs& a, const T* __restrict__ front, 
   zy[lane] = lane < s ? y : 0.0;
   __builtin_amdgcn_wave_barrier();
   if (u <= 0) return;
-  // rows below: lane = row, columns past s read column 0 and meet y = 0
+  // rows below: lane = row, columns past s read column 0 and meet y = 0; the (row block, column
+  // chunk) pieces in order, each piece's loads issued while the previous one is used
   const rsrc_t rs = buffer_rsrc(F + s, (int32_t)(((int64_t)(s - 1) * m + u) * (int64_t)sizeof(T)));
   const int32_t cstr = (int32_t)(m * (int64_t)sizeof(T));
-  for (int r0 = 0; r0 < u; r0 += 64) {
-    const int r = r0 + lane;
+  const int nk = (s + kOneChunk - 1) / kOneChunk, npieces = nk * ((u + 63) / 64);
+  auto load_piece = [&](int q, T* dst) {
+    const int r = (q / nk) * 64 + lane, k0 = (q % nk) * kOneChunk;
     const uint32_t voff = (uint32_t)((r < u ? r : 0) * (int)sizeof(T));
-    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kOneChunk; ++k) dst[k] = buffer_load<T>(rs, voff, (k0 + k < s ? k0 + k : 0) * cstr);
+  };
+  T cur[kOneChunk], nxt[kOneChunk];
+  load_piece(0, cur);
+  double acc = 0.0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < s; k0 += kOneChunk) {  // k0 + k < 64: zy is zero past s
-      T fv[kOneChunk];
+  for (int q = 0; q < npieces; ++q) {
+    if (q + 1 < npieces) load_piece(q + 1, nxt);
+    const int k0 = (q % nk) * kOneChunk;  // k0 + k < 64: zy is zero past s
 #pragma unroll
-      for (int k = 0; k < kOneChunk; ++k) fv[k] = buffer_load<T>(rs, voff, (k0 + k < s ? k0 + k : 0) * cstr);
-#pragma unroll
-      for (int k = 0; k < kOneChunk; ++k) acc += (double)fv[k] * zy[k0 + k];
+    for (int k = 0; k < kOneChunk; ++k) acc += (double)cur[k] * zy[k0 + k];
+    if (q % nk == nk - 1) {  // the row block's last chunk
+      const int r = (q / nk) * 64 + lane;
+      if (r < u) tp[s + r] = tv[s + r] - acc;
+      acc = 0.0;
     }
-    if (r < u) tp[s + r] = tv[s + r] - acc;
+#pragma unroll
+    for (int k = 0; k < kOneChunk; ++k) cur[k] = nxt[k];
   }
 }
 
