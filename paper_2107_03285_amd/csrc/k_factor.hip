@@ -63,7 +63,8 @@ __global__ void k_csr_to_fronts(int64_t nnz, const int32_t* __restrict__ slot_ro
   }
 }
 
-// Zeroes rows >= column - 63 of 64 columns of one front: the lower triangle, which the assembly
+// Zeroes rows >= column - 63 of 64 columns of one front (or a whole small front): the lower
+// triangle, which the assembly
 // and the extend-add accumulate into, and a band of 63 entries above the diagonal.  The trailing
 // update reads that band (its diagonal tiles, and the L columns of a partial last k-chunk, which
 // are multiplied by zeroed W entries), so the band must hold finite values; entries further above
@@ -79,6 +80,21 @@ __global__ void __launch_bounds__(256) k_zero_fronts(const int32_t* __restrict__
   const int sn = tasks[2 * blockIdx.x], c0 = tasks[2 * blockIdx.x + 1];
   const int64_t m = f.sn_m[sn];
   T* F = front + f.sn_front_off[sn];
+  if (c0 < 0) {
+    // a small front whole (c0 = -1): its m x m entries are one contiguous range, zeroed by the block
+    // with 16-byte stores (the entries above the band are written before they are read anyway)
+    const int tid = threadIdx.x;
+    const int64_t n = m * m;
+    int64_t head = (int64_t)(((16 - ((uintptr_t)F & 15)) & 15) / sizeof(T));
+    if (head > n) head = n;
+    if (tid < head) F[tid] = (T)0;
+    const int64_t nv = (n - head) / V;
+    uint4* vb = reinterpret_cast<uint4*>(F + head);
+    for (int64_t v = tid; v < nv; v += 256) vb[v] = make_uint4(0u, 0u, 0u, 0u);
+    const int64_t rt = head + nv * V;
+    if (rt + tid < n) F[rt + tid] = (T)0;
+    return;
+  }
   const int64_t c1 = c0 + 64 < m ? c0 + 64 : m;
   for (int64_t c = c0 + wave; c < c1; c += 4) {
     T* col = F + c * m;

@@ -292,13 +292,19 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.part_total = S.sn_part_off[nt];
   S.front_total = S.sn_front_off[nt];
   // zeroing tasks: the lower triangle and the band above the diagonal of every front, 64 columns
-  // per task
+  // per task, or (column -1) the whole of a front of order <= kZeroWhole
   S.fill_tasks.clear();
-  for (int t = 0; t < nt; ++t)
+  for (int t = 0; t < nt; ++t) {
+    if (S.sn_m[t] <= kZeroWhole) {  // one task zeroes the whole front
+      S.fill_tasks.push_back(t);
+      S.fill_tasks.push_back(-1);
+      continue;
+    }
     for (int64_t c0 = 0; c0 < S.sn_m[t]; c0 += 64) {
       S.fill_tasks.push_back(t);
       S.fill_tasks.push_back((int32_t)c0);
     }
+  }
   S.vec_total = S.sn_vec_off[nt];
   // relative maps child struct -> parent front index
   S.relmap_off.assign(nt + 1, 0);
