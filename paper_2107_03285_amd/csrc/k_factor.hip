@@ -456,8 +456,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ tasks, FrontArgs f,
                                                     T* __restrict__ front) {
   __shared__ T sV[16][68];
-  __shared__ T sX[16][68];
-  __shared__ T sC[64][65];
+  __shared__ T sC[64][65];  // first X11^T (sC[k][c] = X[c][k]), then the block's X tile (sC[c][r])
   __shared__ double dd[64], ee[64];
   __shared__ int ty[64], ps[64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -490,19 +489,27 @@ __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ 
     }
   // every operand the block needs, loaded up front and unconditionally (clamped to in-front
   // addresses, masked when staged): 32 loads in flight per thread instead of one at a time.
-  // Element q of a thread is (row rr = tid & 63, k = (tid + 256 q) >> 6).
+  // V element q of a thread is (row rr = tid & 63, k = (tid + 256 q) >> 6); X11 element q is
+  // X[c][k] with k = tid & 63 and c = (tid + 256 q) >> 6, kept at (row c0 + k, column c0 + c) for
+  // c > k, so consecutive threads read consecutive rows of one column.
   T pv[16], px[16];
   {
     const int rr = tid & 63;
     const int64_t rc = r0 + rr < m ? r0 + rr : r0;
-    const int cc = rr < w ? rr : 0;
+    const int kx = rr < w ? rr : 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = (tid + 256 * q) >> 6;
-      const int kc = k < w ? k : 0;
+      const int cx = k < w ? k : 0;
       pv[q] = F[rc + (int64_t)(c0 + ps[k]) * m];  // ps[k] = 0 past w
-      px[q] = F[(c0 + kc) + (int64_t)(c0 + cc) * m];
+      px[q] = F[(c0 + kx) + (int64_t)(c0 + cx) * m];
     }
+  }
+  // X11^T in LDS once: sC[k][c] = X[c][k] (1 on the diagonal, 0 above it and past w)
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = tid & 63, c = (tid + 256 * q) >> 6;
+    sC[k][c] = (k < w && c < w) ? (c == k ? (T)1 : (c > k ? px[q] : (T)0)) : (T)0;
   }
 #pragma unroll
   for (int kb = 0; kb < 64; kb += 16) {
@@ -513,9 +520,6 @@ __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ 
       const int rr = idx & 63, k = idx >> 6, kk = k - kb;
       const int64_t r = r0 + rr;
       sV[kk][rr] = (k < w && r < m) ? pv[q] : (T)0;
-      // sX[kk][c] = X[c][k]: 1 on the diagonal, stored at (row c0+k, column c0+c) for c > k
-      const int c = rr;
-      sX[kk][c] = (k < w && c < w) ? (c == k ? (T)1 : (c > k ? px[q] : (T)0)) : (T)0;
     }
     __syncthreads();
 #pragma unroll
@@ -525,7 +529,7 @@ __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ 
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          const T av = sX[kr][wc + bj * 16 + (lane & 15)];
+          const T av = sC[kb + kr][wc + bj * 16 + (lane & 15)];
           const T bv = sV[kr][wr + bi * 16 + (lane & 15)];
           if constexpr (sizeof(T) == 8) {
             accd[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accd[bi][bj], 0, 0, 0);
