@@ -54,6 +54,7 @@ struct DevSys {
   int32_t* panel_col = nullptr;
   int64_t* panel_tasks = nullptr;
   int64_t* upd_tasks = nullptr;
+  int32_t* upd_tile_task = nullptr;
   int64_t* ea_cols = nullptr;
   int64_t* ea_kids = nullptr;
   int32_t* fill_tasks = nullptr;
@@ -329,6 +330,7 @@ size_t layout(sgn_ctx c, char* base) {
     D.panel_col = L.take<int32_t>(S.panel_col.size());
     D.panel_tasks = L.take<int64_t>(S.panel_tasks.size());
     D.upd_tasks = L.take<int64_t>(S.upd_tasks.size());
+    D.upd_tile_task = L.take<int32_t>(S.upd_tile_task.size());
     D.ea_cols = L.take<int64_t>(S.ea_cols.size());
     D.ea_kids = L.take<int64_t>(S.ea_kid_recs.size());
     D.fill_tasks = L.take<int32_t>(S.fill_tasks.size());
@@ -632,14 +634,14 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
         need += 2 * ((ps.upd_tiles > 0) + (ps.outer_tiles > 0) + (ps.far_tiles > 0));
     HIPCHK(ensure_events(c, need));
   }
-  auto timed_update = [&](int64_t ntask, int64_t ntiles, const int64_t* tasks, double flops,
-                          hipStream_t ls) -> hipError_t {
+  auto timed_update = [&](int64_t ntask, int64_t ntiles, const int64_t* tasks, const int32_t* tile_task,
+                          double flops, hipStream_t ls) -> hipError_t {
     if (ntask <= 0 || ntiles <= 0) return hipSuccess;
     if (prof) {  // events on the stream the launch goes to
       hipError_t e = hipEventRecord(c->ev_pool[nev], ls);
       if (e != hipSuccess) return e;
     }
-    launch_update<T>(ntask, ntiles, tasks, f, front, ls);
+    launch_update<T>(ntask, ntiles, tasks, tile_task, f, front, ls);
     if (prof) {
       hipError_t e = hipEventRecord(c->ev_pool[nev + 1], ls);
       if (e != hipSuccess) return e;
@@ -680,18 +682,19 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
       launch_panel_diag<T>(ps.task_end - b, kPanel, pw != 0 ? pw : panel_waves_for(ps.task_end - b),
                            D.panel_tasks + b * 3, f, front, st);
       launch_panel_trsm<T>(nt, ps.trsm_rows, D.panel_tasks + ps.task_begin * 3, f, front, st);
-      HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6, ps.upd_flops, st));
+      HIPCHK(timed_update(ps.upd_end - ps.upd_begin, ps.upd_tiles, D.upd_tasks + ps.upd_begin * 6,
+                          D.upd_tile_task + ps.upd_map, ps.upd_flops, st));
       if (ps.outer_tiles > 0 && side_busy) {
         HIPCHK(hipStreamWaitEvent(st, c->ev_join, 0));
         side_busy = false;
       }
       HIPCHK(timed_update(ps.outer_end - ps.outer_begin, ps.outer_tiles, D.upd_tasks + ps.outer_begin * 6,
-                          ps.outer_flops, st));
+                          D.upd_tile_task + ps.outer_map, ps.outer_flops, st));
       if (ps.far_tiles > 0) {  // after everything the main stream has so far; after earlier far updates
         HIPCHK(hipEventRecord(c->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
         HIPCHK(timed_update(ps.far_end - ps.far_begin, ps.far_tiles, D.upd_tasks + ps.far_begin * 6,
-                            ps.far_flops, c->side));
+                            D.upd_tile_task + ps.far_map, ps.far_flops, c->side));
         HIPCHK(hipEventRecord(c->ev_join, c->side));
         side_busy = true;
       }
@@ -2534,6 +2537,7 @@ sgn_status sgn_set_workspace(sgn_ctx c, void* d_ws, size_t bytes) {
     HIPCHK(up(D.panel_col, S.panel_col, st));
     HIPCHK(up(D.panel_tasks, S.panel_tasks, st));
     HIPCHK(up(D.upd_tasks, S.upd_tasks, st));
+    HIPCHK(up(D.upd_tile_task, S.upd_tile_task, st));
     HIPCHK(up(D.ea_cols, S.ea_cols, st));
     HIPCHK(up(D.ea_kids, S.ea_kid_recs, st));
     HIPCHK(up(D.fill_tasks, S.fill_tasks, st));

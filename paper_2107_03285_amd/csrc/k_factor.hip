@@ -580,7 +580,8 @@ __global__ void __launch_bounds__(256) k_panel_trsm(const int64_t* __restrict__ 
 
 // C[r, c] -= sum_{k in [k0,k1)} L[r,k] (L D)[c,k] on one 64 x 64 tile, MFMA 16x16x4.
 template <typename T>
-__global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* __restrict__ tasks, FrontArgs f,
+__global__ void __launch_bounds__(256) k_update(const int64_t* __restrict__ tasks,
+                                                const int32_t* __restrict__ tile_task, FrontArgs f,
                                                 T* __restrict__ front) {
   // 64 x 64 tile per block, 32 x 32 per wave (2 x 2 MFMA blocks of 16 x 16); the next k-chunk's loads
   // are in flight while the current one runs on the matrix cores.  (A 128 x 128 tile halves the
@@ -611,13 +612,9 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
     for (int64_t y = 0; y < x; ++y) before += (n - y + 7) >> 3;
     b = before + (blockIdx.x >> 3);
   }
-  int64_t lo = 0, hi = ntasks - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (tasks[mid * 6 + 5] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  const int64_t* tk = tasks + lo * 6;
+  // The tile's task from the host-built map: one load, where a search over the tasks' tile offsets
+  // took a chain of dependent loads before any of the tile's work could start.
+  const int64_t* tk = tasks + (int64_t)tile_task[b] * 6;
   const int sn = (int)tk[0];
   const int64_t k0 = tk[1], k1 = tk[2], cb = tk[3], ce = tk[4];
   const int64_t m = f.sn_m[sn];
@@ -724,6 +721,7 @@ __global__ void __launch_bounds__(256) k_update(int64_t ntasks, const int64_t* _
 __global__ void k_inertia(int64_t N, const double* dpiv, const double* epiv, const int32_t* pivtype,
                           unsigned long long* counts, double* minabs_partials) {
   __shared__ double sh[256];
+  __shared__ unsigned long long shc[3][256];
   unsigned long long np = 0, nn = 0, nz = 0;
   double mn = __builtin_inf();
   for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < N; k += (int64_t)gridDim.x * 256) {
@@ -750,16 +748,29 @@ __global__ void k_inertia(int64_t N, const double* dpiv, const double* epiv, con
       mn = fmin(mn, fmin(fabs(h - r), fabs(h + r)));
     }
   }
-  if (np) atomicAdd(&counts[0], np);
-  if (nn) atomicAdd(&counts[1], nn);
-  if (nz) atomicAdd(&counts[2], nz);
+  // the counts are summed over the block first: one atomic per counter and block, where atomics from
+  // every thread on the same three addresses queue up at their memory channel
   sh[threadIdx.x] = mn;
+  shc[0][threadIdx.x] = np;
+  shc[1][threadIdx.x] = nn;
+  shc[2][threadIdx.x] = nz;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    const int t = threadIdx.x;
+    if (t < w) {
+      sh[t] = fmin(sh[t], sh[t + w]);
+      shc[0][t] += shc[0][t + w];
+      shc[1][t] += shc[1][t + w];
+      shc[2][t] += shc[2][t + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) minabs_partials[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) {
+    minabs_partials[blockIdx.x] = sh[0];
+    if (shc[0][0]) atomicAdd(&counts[0], shc[0][0]);
+    if (shc[1][0]) atomicAdd(&counts[1], shc[1][0]);
+    if (shc[2][0]) atomicAdd(&counts[2], shc[2][0]);
+  }
 }
 
 __global__ void k_mfma_probe_f64(const double* a, const double* b, double* out) {
@@ -828,9 +839,9 @@ void launch_panel_trsm(int64_t ntasks, int64_t max_rows, const int64_t* tasks, c
 }
 
 template <typename T>
-void launch_update(int64_t ntasks, int64_t ntiles, const int64_t* tasks, const FrontArgs& f, T* front,
-                   hipStream_t s) {
-  if (ntasks > 0 && ntiles > 0) k_update<T><<<(unsigned)ntiles, 256, 0, s>>>(ntasks, tasks, f, front);
+void launch_update(int64_t ntasks, int64_t ntiles, const int64_t* tasks, const int32_t* tile_task,
+                   const FrontArgs& f, T* front, hipStream_t s) {
+  if (ntasks > 0 && ntiles > 0) k_update<T><<<(unsigned)ntiles, 256, 0, s>>>(tasks, tile_task, f, front);
 }
 
 void launch_inertia(int64_t N, const double* dpiv, const double* epiv, const int32_t* pivtype,
@@ -859,7 +870,9 @@ template void launch_panel_diag<float>(int64_t, int, int, const int64_t*, const 
                                         hipStream_t);
 template void launch_panel_trsm<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
 template void launch_panel_trsm<float>(int64_t, int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
-template void launch_update<double>(int64_t, int64_t, const int64_t*, const FrontArgs&, double*, hipStream_t);
-template void launch_update<float>(int64_t, int64_t, const int64_t*, const FrontArgs&, float*, hipStream_t);
+template void launch_update<double>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, double*,
+                                    hipStream_t);
+template void launch_update<float>(int64_t, int64_t, const int64_t*, const int32_t*, const FrontArgs&, float*,
+                                   hipStream_t);
 
 }  // namespace sgn

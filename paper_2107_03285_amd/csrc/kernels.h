@@ -162,8 +162,8 @@ template <typename T>
 void launch_panel_trsm(int64_t ntasks, int64_t max_rows, const int64_t* tasks, const FrontArgs& f, T* front,
                        hipStream_t s);
 template <typename T>
-void launch_update(int64_t ntasks, int64_t ntiles, const int64_t* tasks, const FrontArgs& f, T* front,
-                   hipStream_t s);
+void launch_update(int64_t ntasks, int64_t ntiles, const int64_t* tasks, const int32_t* tile_task,
+                   const FrontArgs& f, T* front, hipStream_t s);
 // inertia: counts[0..2] += (pos, neg, zero); minabs via partial mins
 void launch_inertia(int64_t N, const double* dpiv, const double* epiv, const int32_t* pivtype,
                     unsigned long long* counts, double* minabs_partials, hipStream_t s);

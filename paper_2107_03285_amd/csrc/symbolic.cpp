@@ -393,6 +393,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.levels.assign(S.nlevels, LevelPlan());
   S.panel_tasks.clear();
   S.upd_tasks.clear();
+  S.upd_tile_task.clear();
   S.ea_cols.clear();
   S.ea_kid_recs.clear();
   S.solve_fwd_tasks.clear();
@@ -511,6 +512,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
       for (int64_t q = ps.task_begin; q < ps.task_end; ++q)
         ps.trsm_rows = std::max<int64_t>(ps.trsm_rows, S.sn_m[S.panel_tasks[q * 3]] - S.panel_tasks[q * 3 + 2]);
       ps.upd_begin = (int64_t)S.upd_tasks.size() / 6;
+      ps.upd_map = (int64_t)S.upd_tile_task.size();
       int64_t tiles = 0;
       double fl = 0.0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
@@ -526,6 +528,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
           int64_t m = S.sn_m[t];
           S.upd_tasks.insert(S.upd_tasks.end(), {t, c0, c1, c1, oend, tiles});
           tiles += update_tiles(m, c1, oend);
+          S.upd_tile_task.resize(ps.upd_map + tiles, (int32_t)(S.upd_tasks.size() / 6 - 1 - ps.upd_begin));
           fl += update_flops(m, c1, oend, c1 - c0);
         }
       }
@@ -533,6 +536,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
       ps.upd_tiles = tiles;
       ps.upd_flops = fl;
       ps.outer_begin = ps.upd_end;
+      ps.outer_map = (int64_t)S.upd_tile_task.size();
       tiles = 0;
       fl = 0.0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
@@ -549,6 +553,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         if (c1 < nb) {  // rows c1.. of the next block's columns
           S.upd_tasks.insert(S.upd_tasks.end(), {t, kb, c1, c1, nb, tiles});
           tiles += update_tiles(m, c1, nb);
+          S.upd_tile_task.resize(ps.outer_map + tiles, (int32_t)(S.upd_tasks.size() / 6 - 1 - ps.outer_begin));
           fl += update_flops(m, c1, nb, c1 - kb);
         }
       }
@@ -556,6 +561,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
       ps.outer_tiles = tiles;
       ps.outer_flops = fl;
       ps.far_begin = ps.outer_end;
+      ps.far_map = (int64_t)S.upd_tile_task.size();
       tiles = 0;
       fl = 0.0;
       for (int64_t q = P.sn_begin; q < P.sn_end; ++q) {
@@ -572,6 +578,7 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
         if (nb < m) {  // rows nb.. of the columns beyond the next block
           S.upd_tasks.insert(S.upd_tasks.end(), {t, kb, c1, nb, m, tiles});
           tiles += update_tiles(m, nb, m);
+          S.upd_tile_task.resize(ps.far_map + tiles, (int32_t)(S.upd_tasks.size() / 6 - 1 - ps.far_begin));
           fl += update_flops(m, nb, m, c1 - kb);
         }
       }

@@ -66,6 +66,7 @@ struct PanelStep {
   int64_t far_begin, far_end;      // range in the update task table (outer, k = block): the columns
                                    // beyond the next block, free to run beside its panels
   int64_t upd_tiles, outer_tiles, far_tiles;  // tiles of each update launch
+  int64_t upd_map, outer_map, far_map;        // where each launch's tiles start in the tile -> task map
   int64_t narrow_end;              // tasks [task_begin, narrow_end) have at most kNarrowPanel columns,
   int64_t medium_end;              // [narrow_end, medium_end) at most kMediumPanel
   int64_t trsm_rows;               // max rows below the panel over the step's tasks
@@ -135,6 +136,7 @@ struct System {
   // task tables (flattened int64 quintuples, see kernels)
   std::vector<int64_t> panel_tasks;      // (sn, c0, c1) per task: 3 entries
   std::vector<int64_t> upd_tasks;        // (sn, k0, k1, cb, ce, tile_prefix): 6 entries
+  std::vector<int32_t> upd_tile_task;    // per update tile: its task, counted from its launch's first
   // per child column c of a round, 4 entries: front offset of the child's entry (sC, sC + c) (the
   // column's rows c.. follow), front offset of the parent column it adds into, offset of the child's
   // relative map, (c << 32) | uC
