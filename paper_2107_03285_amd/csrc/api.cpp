@@ -99,6 +99,7 @@ struct DevSys {
   double* bp_minv = nullptr;   // dense |B_i|^-1 blocks, one per node group
   bool bp_ready = false;       // the blocks are of the currently assembled matrix
   int prec = 0;  // 0: FP64 fronts, 1: FP32 fronts
+  int row_lanes = 16;  // lanes per row of the SpMV-shaped kernels
   bool factored = false;  // a factorisation is held (the MINRES reference)
   bool current = false;   // ... and it is of the currently assembled matrix
   int64_t inertia[3] = {0, 0, 0};
@@ -311,6 +312,7 @@ size_t layout(sgn_ctx c, char* base) {
     D.slot_src = L.take<int32_t>(S.slot_src.size());
     D.diag_kind = L.take<int32_t>(S.diag_kind.size());
     D.frowptr = L.take<int64_t>(S.frowptr.size());
+    D.row_lanes = row_lanes_for(S.N, S.frowptr.empty() ? 0 : S.frowptr.back());
     D.fcol = L.take<int32_t>(S.fcol.size());
     D.fslot = L.take<int32_t>(S.fslot.size());
     D.perm = L.take<int32_t>(S.perm.size());
@@ -604,7 +606,7 @@ sgn_status factor_system(sgn_ctx c, int si, double piv_tol) {
   hipStream_t st = c->stream;
   T* front = reinterpret_cast<T*>(D.front);
   HIPCHK(ensure_side(c));
-  launch_row_scaling(S.N, D.frowptr, D.fslot, D.vals, D.scale, st);
+  launch_row_scaling(D.row_lanes, S.N, D.frowptr, D.fslot, D.vals, D.scale, st);
   FrontArgs f;
   f.sn_begin = D.sn_begin;
   f.sn_m = D.sn_m;
@@ -927,7 +929,7 @@ sgn_status fgmres_cycle(sgn_ctx c, int si, double* z_new, const double* rs, doub
     TRY(fwd_sweep(c, si, vj));
     TRY(bwd_sweep(c, si, zj, nullptr));
     scale_vec(c, N, D.scale, zj, D.sv);
-    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, D.sv, vn, st);
+    launch_spmv(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, D.sv, vn, st);
     scale_vec(c, N, D.scale, vn, vn);
     for (int pass = 0; pass < 2; ++pass) {
       for (int i = 0; i <= j; ++i) dev_dot_to(c, N, V + (int64_t)i * N, vn, c->d_gm + 64 * pass + i);
@@ -997,7 +999,7 @@ sgn_status refined_solve(sgn_ctx c, int si, const double* b_new, double* z_new, 
   // Krylov escalation serves the saddle-point system only
   const int max_gmres = si == 0 ? c->opt.max_gmres : 0;
   for (;;) {
-    launch_residual(S.N, D.frowptr, D.fcol, D.fslot, D.vals, z_new, b_new, D.ir_r, c->stream);
+    launch_residual(D.row_lanes, S.N, D.frowptr, D.fcol, D.fslot, D.vals, z_new, b_new, D.ir_r, c->stream);
     scale_vec(c, S.N, D.scale, D.ir_r, D.ir_s);
     dev_dot(c, S.N, D.ir_s, D.ir_s, 1);
     dev_dot(c, S.N, D.ir_r, D.ir_r, 2);
@@ -1076,7 +1078,7 @@ sgn_status bicgstab_solve(sgn_ctx c, const double* b_new, double* z_new, sgn_sol
   // out = S K S w (K unstabilised)
   auto matvec = [&](const double* w, double* out) {
     scale_vec(c, N, D.scale, w, tmp);
-    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, tmp, out, st);
+    launch_spmv(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, tmp, out, st);
     if (ex != 0.0 || el != 0.0) launch_unstabilise(N, D.diag_kind, ex, el, -1.0, tmp, out, st);
     scale_vec(c, N, D.scale, out, out);
   };
@@ -1171,7 +1173,7 @@ sgn_status bicgstab_solve(sgn_ctx c, const double* b_new, double* z_new, sgn_sol
   if (sb == 0.0) rel = 0.0;
   scale_vec(c, N, D.scale, u, z_new);
   // raw residual |b - K z| / |b| for the report
-  launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, z_new, b_new, D.ir_r, st);
+  launch_residual(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, z_new, b_new, D.ir_r, st);
   if (ex != 0.0 || el != 0.0) launch_unstabilise(N, D.diag_kind, ex, el, 1.0, z_new, D.ir_r, st);
   dev_dot(c, N, D.ir_r, D.ir_r, 41);
   double raw2;
@@ -1217,7 +1219,7 @@ sgn_status minres_new(sgn_ctx c, const double* b, double* x, int max_iter, int w
   double *w_prev = D.mr[5], *w = D.mr[6], *w_next = D.mr[7], *q = D.mr[8], *r = D.mr[9];
   *converged = false;
   *iters = 0;
-  launch_row_scaling(N, D.frowptr, D.fslot, D.vals, D.cur_scale, st);
+  launch_row_scaling(D.row_lanes, N, D.frowptr, D.fslot, D.vals, D.cur_scale, st);
   launch_fill(N, 0.0, x, st);
   launch_fill(N, 0.0, v_prev, st);
   launch_fill(N, 0.0, w_prev, st);
@@ -1245,7 +1247,7 @@ sgn_status minres_new(sgn_ctx c, const double* b, double* x, int max_iter, int w
   double rel = 1.0;
   for (int j = 1; j <= max_iter; ++j) {
     launch_lincomb3(N, 1.0 / gam, z, 0.0, nullptr, 0.0, nullptr, z, st);  // z_j normalised
-    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, z, q, st);
+    launch_spmv(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, z, q, st);
     dev_dot(c, N, q, z, 20);
     double dl;
     TRY(read_scalars(c, 20, 1, &dl));
@@ -1266,7 +1268,7 @@ sgn_status minres_new(sgn_ctx c, const double* b, double* x, int max_iter, int w
     launch_axpby(N, 1.0, x, c_next * eta, w_next, x, st);
     eta = -s_next * eta;
     // true equilibrated residual of the iterate
-    launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, x, b, r, st);
+    launch_residual(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, x, b, r, st);
     scale_vec(c, N, D.cur_scale, r, r);
     dev_dot(c, N, r, r, 22);
     double rn;
@@ -1536,7 +1538,7 @@ sgn_status assemble_impl(sgn_ctx c, const double* x, const double* p, double* rh
     launch_fill(N, 0.0, c->d_old, c->stream);
     HIPCHK(hipMemcpyAsync(c->d_old + nx + np, c->d_lam, nx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     launch_gather_perm(N, D.perm, nullptr, c->d_old, D.t, c->stream);
-    launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, D.t, D.r, c->stream);
+    launch_spmv(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, D.t, D.r, c->stream);
     launch_scatter_perm(N, D.perm, nullptr, D.r, c->d_old2, c->stream);
     launch_axpby(np, 1.0, c->d_fp, 1.0, c->d_old2 + nx, c->d_g, c->stream);
     if (grad && grad != c->d_g)
@@ -1555,7 +1557,7 @@ void sgn_matvec_boundary(sgn_ctx c, const double* v_old, double* y_old) {
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;
   launch_gather_perm(N, D.perm, nullptr, v_old, D.t, c->stream);
-  launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, D.t, D.r, c->stream);
+  launch_spmv(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, D.t, D.r, c->stream);
   launch_scatter_perm(N, D.perm, nullptr, D.r, y_old, c->stream);
 }
 
@@ -1896,7 +1898,7 @@ size_t carve_solve_scratch(sgn_ctx c, char* base, SolveScratch* s) {
 sgn_status blockpc_setup(sgn_ctx c) {
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;
-  launch_row_scaling(N, D.frowptr, D.fslot, D.vals, D.cur_scale, c->stream);
+  launch_row_scaling(D.row_lanes, N, D.frowptr, D.fslot, D.vals, D.cur_scale, c->stream);
   launch_blockpc_setup(D.ngroups, D.grp_ptr, D.rowptr, D.colind, D.vals, D.cur_scale, D.bp_off, D.bp_minv, c->stream);
   HIPCHK(hipGetLastError());
   D.bp_ready = true;
@@ -2116,7 +2118,7 @@ sgn_status t_apply(sgn_ctx c, const PcArgs& pa, const double* v, double* out, do
   launch_pc_half_bwd(pa, v, D.pc_w, c->stream);
   TRY(bwd_sweep(c, 0, z, D.pc_w));
   scale_vec(c, N, D.scale, z, z);
-  launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, z, q, c->stream);
+  launch_spmv(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, z, q, c->stream);
   scale_vec(c, N, D.scale, q, D.sv);
   TRY(fwd_sweep(c, 0, D.sv));
   launch_pc_half_fwd(pa, D.tp, out, c->stream);
@@ -2226,13 +2228,13 @@ sgn_status enqueue_step(sgn_ctx c, const double* x, const double* p, double* rhs
   launch_gather_perm(N, D.perm, nullptr, rhs, b, st);
   TRY(solve_once(c, 0, b, z));
   for (int k = 0; k < n_ir; ++k) {
-    launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, z, b, D.ir_r, st);
+    launch_residual(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, z, b, D.ir_r, st);
     TRY(solve_once(c, 0, D.ir_r, D.ir_d));
     launch_axpby(N, 1.0, z, 1.0, D.ir_d, z, st);
   }
   scale_vec(c, N, D.scale, b, D.ir_s);
   dev_dot(c, N, D.ir_s, D.ir_s, 31);
-  launch_residual(N, D.frowptr, D.fcol, D.fslot, D.vals, z, b, D.ir_r, st);
+  launch_residual(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, z, b, D.ir_r, st);
   scale_vec(c, N, D.scale, D.ir_r, D.ir_s);
   dev_dot(c, N, D.ir_s, D.ir_s, 30);
   launch_rel_flag(c->d_scal + 30, c->d_scal + 31, c->opt.solve_rtol, c->d_scal + 32, st);
@@ -3123,7 +3125,7 @@ sgn_status sgn_spmv(sgn_ctx c, const double* d_in, double* d_out) {
   DevSys& D = c->sys[0];
   const int64_t N = c->A.sgn.N;
   launch_gather_perm(N, D.perm, nullptr, d_in, c->d_old2, c->stream);
-  launch_spmv(N, D.frowptr, D.fcol, D.fslot, D.vals, c->d_old2, c->d_old, c->stream);
+  launch_spmv(D.row_lanes, N, D.frowptr, D.fcol, D.fslot, D.vals, c->d_old2, c->d_old, c->stream);
   launch_scatter_perm(N, D.perm, nullptr, c->d_old, d_out, c->stream);
   HIPCHK(hipStreamSynchronize(c->stream));
   return SGN_OK;

@@ -552,25 +552,25 @@ __global__ void k_fill_bytes(int64_t n16, uint4* out) {
     out[k] = z;
 }
 
-// 16 lanes per row (four rows per wavefront): lane l sums the row's entries l, l + 16, l + 32, ... in
-// ascending order, four loads in flight per pass (indices clamped to the row's first entry, products
-// masked), then a fixed butterfly over the 16 lanes
-constexpr int kRowLanes = 16;
-
+// RL lanes per row (64 / RL rows per wavefront): lane l sums the row's entries l, l + RL, l + 2 RL, ...
+// in ascending order, four loads in flight per pass (indices clamped to the row's first entry, products
+// masked), then a fixed butterfly over the RL lanes.  RL follows the matrix's mean row length, so that a
+// pass of four loads per lane covers about one row: short rows on 16 lanes left most loads idle.
+template <int RL>
 __global__ void __launch_bounds__(256) k_spmv(int64_t N, const int64_t* __restrict__ frp,
                                               const int32_t* __restrict__ fcol, const int32_t* __restrict__ fslot,
                                               const double* __restrict__ vals, const double* __restrict__ x,
                                               const double* __restrict__ b, double* __restrict__ y) {
-  const int sub = threadIdx.x & (kRowLanes - 1);
-  const int64_t row = (int64_t)blockIdx.x * (256 / kRowLanes) + (threadIdx.x / kRowLanes);
-  if (row >= N) return;  // whole 16-lane groups leave together
+  const int sub = threadIdx.x & (RL - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / RL) + (threadIdx.x / RL);
+  if (row >= N) return;  // whole RL-lane groups leave together
   const int64_t t0 = frp[row], t1 = frp[row + 1];
   double acc = 0.0;
-  for (int64_t t = t0 + sub; t < t1; t += 4 * kRowLanes) {
+  for (int64_t t = t0 + sub; t < t1; t += 4 * RL) {
     int32_t sl[4], cl[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t tt = t + q * kRowLanes, tc = tt < t1 ? tt : t0;
+      const int64_t tt = t + q * RL, tc = tt < t1 ? tt : t0;
       sl[q] = fslot[tc];
       cl[q] = fcol[tc];
     }
@@ -579,26 +579,27 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t N, const int64_t* __restri
     for (int q = 0; q < 4; ++q) pv[q] = vals[sl[q]] * x[cl[q]];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (t + q * kRowLanes < t1) acc += pv[q];
+      if (t + q * RL < t1) acc += pv[q];
   }
-  for (int off = kRowLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kRowLanes);
+  for (int off = RL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, RL);
   if (sub == 0) y[row] = b ? b[row] - acc : acc;
 }
 
-// max |K_ij| over row i, 16 lanes per row as in the SpMV (max is order-independent)
+// max |K_ij| over row i, RL lanes per row as in the SpMV (max is order-independent)
+template <int RL>
 __global__ void __launch_bounds__(256) k_row_scaling(int64_t N, const int64_t* __restrict__ frp,
                                                      const int32_t* __restrict__ fslot,
                                                      const double* __restrict__ vals, double* __restrict__ scale) {
-  const int sub = threadIdx.x & (kRowLanes - 1);
-  const int64_t row = (int64_t)blockIdx.x * (256 / kRowLanes) + (threadIdx.x / kRowLanes);
+  const int sub = threadIdx.x & (RL - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / RL) + (threadIdx.x / RL);
   if (row >= N) return;
   const int64_t t0 = frp[row], t1 = frp[row + 1];
   double m = 0.0;
-  for (int64_t t = t0 + sub; t < t1; t += 4 * kRowLanes) {
+  for (int64_t t = t0 + sub; t < t1; t += 4 * RL) {
     int32_t sl[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t tt = t + q * kRowLanes;
+      const int64_t tt = t + q * RL;
       sl[q] = fslot[tt < t1 ? tt : t0];
     }
     double av[4];
@@ -606,9 +607,9 @@ __global__ void __launch_bounds__(256) k_row_scaling(int64_t N, const int64_t* _
     for (int q = 0; q < 4; ++q) av[q] = fabs(vals[sl[q]]);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (t + q * kRowLanes < t1) m = fmax(m, av[q]);
+      if (t + q * RL < t1) m = fmax(m, av[q]);
   }
-  for (int off = kRowLanes / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, kRowLanes));
+  for (int off = RL / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, RL));
   if (sub == 0) scale[row] = m > 0.0 ? 1.0 / sqrt(m) : 1.0;
 }
 
@@ -734,19 +735,49 @@ void launch_fill_bytes(int64_t nbytes, void* out, hipStream_t s) {
   if (n16 > 0) k_fill_bytes<<<grid_for(n16, 256, 1 << 20), 256, 0, s>>>(n16, (uint4*)out);
 }
 
-void launch_spmv(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot, const double* vals,
-                 const double* x, double* y, hipStream_t s) {
-  if (N > 0) k_spmv<<<(unsigned)((N + 15) / 16), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, nullptr, y);
+int row_lanes_for(int64_t N, int64_t nnz) {
+  const int64_t mean = N > 0 ? nnz / N : 0;
+  return mean <= 20 ? 4 : mean <= 48 ? 8 : 16;
 }
 
-void launch_residual(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+namespace {
+template <int RL>
+void spmv_rl(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot, const double* vals,
+             const double* x, const double* b, double* y, hipStream_t s) {
+  constexpr int64_t rows = 256 / RL;
+  k_spmv<RL><<<(unsigned)((N + rows - 1) / rows), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, b, y);
+}
+void spmv_any(int row_lanes, int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+              const double* vals, const double* x, const double* b, double* y, hipStream_t s) {
+  if (N <= 0) return;
+  if (row_lanes == 4) spmv_rl<4>(N, frowptr, fcol, fslot, vals, x, b, y, s);
+  else if (row_lanes == 8) spmv_rl<8>(N, frowptr, fcol, fslot, vals, x, b, y, s);
+  else spmv_rl<16>(N, frowptr, fcol, fslot, vals, x, b, y, s);
+}
+template <int RL>
+void row_scaling_rl(int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals, double* scale,
+                    hipStream_t s) {
+  constexpr int64_t rows = 256 / RL;
+  k_row_scaling<RL><<<(unsigned)((N + rows - 1) / rows), 256, 0, s>>>(N, frowptr, fslot, vals, scale);
+}
+}  // namespace
+
+void launch_spmv(int row_lanes, int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+                 const double* vals, const double* x, double* y, hipStream_t s) {
+  spmv_any(row_lanes, N, frowptr, fcol, fslot, vals, x, nullptr, y, s);
+}
+
+void launch_residual(int row_lanes, int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
                      const double* vals, const double* x, const double* b, double* out, hipStream_t s) {
-  if (N > 0) k_spmv<<<(unsigned)((N + 15) / 16), 256, 0, s>>>(N, frowptr, fcol, fslot, vals, x, b, out);
+  spmv_any(row_lanes, N, frowptr, fcol, fslot, vals, x, b, out, s);
 }
 
-void launch_row_scaling(int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals, double* scale,
-                        hipStream_t s) {
-  if (N > 0) k_row_scaling<<<(unsigned)((N + 15) / 16), 256, 0, s>>>(N, frowptr, fslot, vals, scale);
+void launch_row_scaling(int row_lanes, int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals,
+                        double* scale, hipStream_t s) {
+  if (N <= 0) return;
+  if (row_lanes == 4) row_scaling_rl<4>(N, frowptr, fslot, vals, scale, s);
+  else if (row_lanes == 8) row_scaling_rl<8>(N, frowptr, fslot, vals, scale, s);
+  else row_scaling_rl<16>(N, frowptr, fslot, vals, scale, s);
 }
 
 void launch_objective_fx(int64_t nt, const int32_t* tdof, const double* tval, const double* x, double w_over_ell2,

@@ -106,11 +106,14 @@ void launch_fill_bytes(int64_t nbytes, void* out, hipStream_t s);
 void launch_rel_flag(const double* r2, const double* b2, double rtol, double* out, hipStream_t s);
 // out[0 .. n) = v (32-bit words; a kernel, so it may sit in a captured graph where memset nodes may not)
 void launch_fill_i32(int64_t n, int32_t v, void* out, hipStream_t s);
+// lanes per row (4, 8 or 16) of the row kernels below for a matrix of N rows and nnz stored entries in
+// its full CSR
+int row_lanes_for(int64_t N, int64_t nnz);
 // y = K x with the symmetric matrix stored as lower slots and addressed through the full CSR
-void launch_spmv(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+void launch_spmv(int row_lanes, int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
                  const double* vals, const double* x, double* y, hipStream_t s);
 // out = b - K x
-void launch_residual(int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
+void launch_residual(int row_lanes, int64_t N, const int64_t* frowptr, const int32_t* fcol, const int32_t* fslot,
                      const double* vals, const double* x, const double* b, double* out, hipStream_t s);
 // scale[i] = 1 / sqrt(max_j |K_ij|) over the full row (1 when the row is empty)
 // block-diagonal preconditioner: per node group (grp_ptr, new numbering) |B_i|^-1 of the diagonal block B_i
@@ -119,7 +122,7 @@ void launch_blockpc_setup(int64_t ngroups, const int32_t* grp_ptr, const int64_t
                           const double* vals, const double* scale, const int64_t* off, double* minv, hipStream_t s);
 void launch_blockpc_apply(int64_t ngroups, const int32_t* grp_ptr, const double* scale, const int64_t* off,
                           const double* minv, const double* in, double* out, hipStream_t s);
-void launch_row_scaling(int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals,
+void launch_row_scaling(int row_lanes, int64_t N, const int64_t* frowptr, const int32_t* fslot, const double* vals,
                         double* scale, hipStream_t s);
 // objective pieces on free DOFs: fx = w (x_T - t)/ell^2 on targets (else 0)
 void launch_objective_fx(int64_t nt, const int32_t* tdof, const double* tval, const double* x, double w_over_ell2,
