@@ -81,10 +81,11 @@ __global__ void __launch_bounds__(256) k_zero_fronts(const int32_t* __restrict__
   const int64_t m = f.sn_m[sn];
   T* F = front + f.sn_front_off[sn];
   if (c0 < 0) {
-    // a small front whole (c0 = -1): its m x m entries are one contiguous range, zeroed by the block
-    // with 16-byte stores (the entries above the band are written before they are read anyway)
+    // -c0 consecutive small fronts whole, from front sn on: they lie back to back, so their entries
+    // (and the padding between them) are one contiguous range, zeroed by the block with 16-byte
+    // stores (the entries above the band are written before they are read anyway)
     const int tid = threadIdx.x;
-    const int64_t n = m * m;
+    const int64_t n = f.sn_front_off[sn - c0] - f.sn_front_off[sn];
     int64_t head = (int64_t)(((16 - ((uintptr_t)F & 15)) & 15) / sizeof(T));
     if (head > n) head = n;
     if (tid < head) F[tid] = (T)0;

@@ -292,18 +292,23 @@ std::string finish_system(System& S, const std::vector<TreeNode>& tree,
   S.part_total = S.sn_part_off[nt];
   S.front_total = S.sn_front_off[nt];
   // zeroing tasks: the lower triangle and the band above the diagonal of every front, 64 columns
-  // per task, or (column -1) the whole of a front of order <= kZeroWhole
+  // per task; fronts of order <= kZeroWhole are zeroed whole, consecutive ones (adjacent in memory)
+  // together up to kZeroRun entries per task, written (first front, -count)
   S.fill_tasks.clear();
-  for (int t = 0; t < nt; ++t) {
-    if (S.sn_m[t] <= kZeroWhole) {  // one task zeroes the whole front
+  for (int t = 0; t < nt;) {
+    if (S.sn_m[t] <= kZeroWhole) {
+      int e = t + 1;
+      while (e < nt && S.sn_m[e] <= kZeroWhole && S.sn_front_off[e + 1] - S.sn_front_off[t] <= kZeroRun) ++e;
       S.fill_tasks.push_back(t);
-      S.fill_tasks.push_back(-1);
+      S.fill_tasks.push_back(-(e - t));
+      t = e;
       continue;
     }
     for (int64_t c0 = 0; c0 < S.sn_m[t]; c0 += 64) {
       S.fill_tasks.push_back(t);
       S.fill_tasks.push_back((int32_t)c0);
     }
+    ++t;
   }
   S.vec_total = S.sn_vec_off[nt];
   // relative maps child struct -> parent front index

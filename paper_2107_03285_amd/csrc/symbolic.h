@@ -17,7 +17,8 @@ constexpr int kOneMaxU = 128;     // one-panel fronts with at most this many row
 constexpr int kOneMaxM = kPanel + kOneMaxU;  // solved by one wavefront each (order <= kOneMaxM) when a
 constexpr int kOneMinFronts = 1024;          // level has at least kOneMinFronts of them
 constexpr int kSmallChild = 128;  // update blocks up to this order are added by one block per child
-constexpr int kZeroWhole = 128;   // fronts up to this order are zeroed whole by one block
+constexpr int kZeroWhole = 128;   // fronts up to this order are zeroed whole
+constexpr int64_t kZeroRun = 16384;  // entries of consecutive whole-zeroed fronts one block zeroes (>= kZeroWhole^2)
 constexpr int kOuterPanels = 4;   // panels per delayed trailing update (k = 256)
 constexpr int kTile = 64;         // update tile edge (equal to the kernels' kUpdTile)
 constexpr int kSolveKC = 256;     // k-chunk of the split-k L21 y product in the forward solve
