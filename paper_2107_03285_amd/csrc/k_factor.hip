@@ -8,7 +8,8 @@
 //   2. children's Schur complements are added in a fixed child order
 //      (extend-add, one launch per child rank, so sums are deterministic);
 //   3. per panel of <= 64 pivot columns (whole node groups):
-//        - the panel's diagonal block is factorised in LDS in FP64 with
+//        - the panel's diagonal block is factorised in LDS, in the fronts'
+//          precision (pivot tests and pivot inverses in FP64), with
 //          Bunch-Kaufman 1x1/2x2 pivots restricted to one node's group;
 //        - rows below are solved against it (TRSM, one thread per row);
 //        - trailing columns are updated with MFMA tiles; updates of columns
@@ -191,7 +192,10 @@ __global__ void __launch_bounds__(256) k_extend_add_small(const int64_t* __restr
   }
 }
 
-// Factorisation of one panel's diagonal block (w <= WM <= 64) in LDS, FP64, 64 * WAVES threads.
+// Factorisation of one panel's diagonal block (w <= WM <= 64) in LDS, 64 * WAVES threads.  The block
+// and its updates are in the fronts' precision T (an FP32 block takes half the LDS, so twice the
+// blocks share a compute unit, and half the lane reads per broadcast); the pivot search keys, the
+// Bunch-Kaufman tests and the 1x1 / 2x2 pivot inverses are in FP64.
 // WAVES = 8 shortens a lone panel's step (the update is split over eight wavefronts); WAVES = 1
 // leaves no wavefront repeating another's pivot search, which pays when a step holds enough panels
 // to fill the chip, and WM = 32 lets more of them share a compute unit's LDS.
@@ -213,6 +217,9 @@ __device__ inline double lane_bcast(double v, int src) {  // src uniform across 
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 __device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 // Maximum over the wavefront: data-parallel-primitive moves within rows of 16 lanes (swap adjacent
@@ -243,7 +250,7 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
 template <typename T, int WAVES, int WM>
 __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
                                                            T* __restrict__ front) {
-  __shared__ double A[WM][WM + 1];
+  __shared__ T A[WM][WM + 1];  // the block in the fronts' precision; pivot scalars in FP64
   __shared__ int pos[WM];
   constexpr int S = WAVES;  // column stride of a wavefront's share of an update
   const int tid = threadIdx.x, lane = tid & 63, wave = uniform_i(tid >> 6);
@@ -269,7 +276,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
     for (int t = 0; t < NL; ++t) {
       const int j = wave + WAVES * t;
       if (j < w && lane >= j && lane < w) {
-        const double v = (double)lv[t];
+        const T v = lv[t];
         A[lane][j] = v;
         A[j][lane] = v;
       }
@@ -285,27 +292,27 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
   // lanes past WM hold no row of the block (WM < 64): they read zeros
   const bool row_lane = WM == 64 || lane < WM;
   while (k < w) {
-    double v = row_lane ? A[lane][k] : 0.0;
+    T v = row_lane ? A[lane][k] : (T)0;
     const int gend = __builtin_amdgcn_readlane(gend_r, k);
-    const double cand = (lane > k && lane < gend) ? fabs(v) : 0.0;
+    const double cand = (lane > k && lane < gend) ? (double)fabs(v) : 0.0;
     const unsigned long long key =
         wave_max_u64(cand > 0.0 ? (((unsigned long long)__double_as_longlong(cand) & ~63ull) |
                                    (unsigned long long)(63 - lane))
                                 : 0ull);
     const int imax = key ? 63 - (int)(key & 63ull) : k;
-    const double colmax = key ? fabs(lane_bcast(v, imax)) : 0.0;
-    const double absakk = fabs(lane_bcast(v, k));
+    const double colmax = key ? (double)fabs(lane_bcast(v, imax)) : 0.0;
+    const double absakk = (double)fabs(lane_bcast(v, k));
     int kind = 1, p = -1, q = -1;
     bool pert = false;
     if (fmax(absakk, colmax) <= tol) {
       pert = true;
     } else if (absakk < kAlphaBK * colmax) {
-      const double u = row_lane ? A[imax][lane] : 0.0;  // row imax
-      const double c2 = (lane >= k && lane < gend && lane != imax) ? fabs(u) : 0.0;
+      const T u = row_lane ? A[imax][lane] : (T)0;  // row imax
+      const double c2 = (lane >= k && lane < gend && lane != imax) ? (double)fabs(u) : 0.0;
       const double rowmax = __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(c2)));
       if (absakk * rowmax >= kAlphaBK * colmax * colmax) {
         kind = 1;
-      } else if (fabs(lane_bcast(u, imax)) >= kAlphaBK * rowmax) {
+      } else if ((double)fabs(lane_bcast(u, imax)) >= kAlphaBK * rowmax) {
         kind = 1;
         p = k;
         q = imax;
@@ -321,13 +328,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
       if (tid < w) {
         const int t = tid;
         if (t != p && t != q) {
-          const double apt = A[p][t], aqt = A[q][t], atp = A[t][p], atq = A[t][q];
+          const T apt = A[p][t], aqt = A[q][t], atp = A[t][p], atq = A[t][q];
           A[p][t] = aqt;
           A[q][t] = apt;
           A[t][p] = atq;
           A[t][q] = atp;
         } else if (t == p) {
-          const double app = A[p][p], aqq = A[q][q], apq = A[p][q], aqp = A[q][p];
+          const T app = A[p][p], aqq = A[q][q], apq = A[p][q], aqp = A[q][p];
           A[p][p] = aqq;
           A[q][q] = app;
           A[p][q] = aqp;
@@ -338,14 +345,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
         }
       }
       __syncthreads();
-      v = row_lane ? A[lane][k] : 0.0;
+      v = row_lane ? A[lane][k] : (T)0;
     }
     // every wavefront holds the pivot columns it needs (k, and k + 1 for a 2 x 2 pivot) before any
     // wavefront overwrites them with the step's multipliers
-    const double w2 = kind == 2 && row_lane ? A[lane][k + 1] : 0.0;
+    const T w2 = kind == 2 && row_lane ? A[lane][k + 1] : (T)0;
     __syncthreads();
     if (kind == 1) {
-      double d = lane_bcast(v, k);
+      double d = (double)lane_bcast(v, k);
       if (pert) {
         d = d >= 0.0 ? tol : -tol;
         ++npert;
@@ -355,11 +362,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
       }
       const double id = 1.0 / d;
       if (lane > k && lane < w) {
-        const double li = v * id;
+        const T li = (T)((double)v * id);
         // Schur complement and X <- L_k^-1 X; the multipliers A[j][k] are lane j's copy of column k
         int j = k + 1 + wave;
         for (; j + 3 * S < w; j += 4 * S) {
-          const double a0 = A[lane][j], a1 = A[lane][j + S], a2 = A[lane][j + 2 * S], a3 = A[lane][j + 3 * S];
+          const T a0 = A[lane][j], a1 = A[lane][j + S], a2 = A[lane][j + 2 * S], a3 = A[lane][j + 3 * S];
           A[lane][j] = a0 - li * lane_bcast(v, j);
           A[lane][j + S] = a1 - li * lane_bcast(v, j + S);
           A[lane][j + 2 * S] = a2 - li * lane_bcast(v, j + 2 * S);
@@ -368,7 +375,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
         for (; j < w; j += S) A[lane][j] -= li * lane_bcast(v, j);
         j = wave;
         for (; j + 3 * S < k; j += 4 * S) {
-          const double a0 = A[j][lane], a1 = A[j + S][lane], a2 = A[j + 2 * S][lane], a3 = A[j + 3 * S][lane];
+          const T a0 = A[j][lane], a1 = A[j + S][lane], a2 = A[j + 2 * S][lane], a3 = A[j + 3 * S][lane];
           A[j][lane] = a0 - li * lane_bcast(v, j);
           A[j + S][lane] = a1 - li * lane_bcast(v, j + S);
           A[j + 2 * S][lane] = a2 - li * lane_bcast(v, j + 2 * S);
@@ -387,14 +394,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
       }
       k += 1;
     } else {
-      const double a = lane_bcast(v, k), b = lane_bcast(v, k + 1), c = lane_bcast(w2, k + 1);
+      const double a = (double)lane_bcast(v, k), b = (double)lane_bcast(v, k + 1), c = (double)lane_bcast(w2, k + 1);
       const double det = a * c - b * b;
       const double i00 = c / det, i01 = -b / det, i11 = a / det;
       if (lane > k + 1 && lane < w) {
-        const double l0 = v * i00 + w2 * i01, l1 = v * i01 + w2 * i11;
+        const T l0 = (T)((double)v * i00 + (double)w2 * i01), l1 = (T)((double)v * i01 + (double)w2 * i11);
         int j = k + 2 + wave;
         for (; j + 3 * S < w; j += 4 * S) {
-          double a4[4];
+          T a4[4];
 #pragma unroll
           for (int t = 0; t < 4; ++t) a4[t] = A[lane][j + S * t];
 #pragma unroll
@@ -404,7 +411,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
         for (; j < w; j += S) A[lane][j] -= l0 * lane_bcast(v, j) + l1 * lane_bcast(w2, j);
         j = wave;
         for (; j + 3 * S < k; j += 4 * S) {
-          double a4[4];
+          T a4[4];
 #pragma unroll
           for (int t = 0; t < 4; ++t) a4[t] = A[j + S * t][lane];
 #pragma unroll
