@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) k_extend_add_small(const int64_t* __restr
 
 // Factorisation of one panel's diagonal block (w <= WM <= 64) in LDS, 64 * WAVES threads.  The block
 // and its updates are in the fronts' precision T (an FP32 block takes half the LDS, so twice the
-// blocks share a compute unit, and half the lane reads per broadcast); the pivot search keys, the
+// blocks share a compute unit, half the lane reads per broadcast and a 32-bit pivot search key); the
 // Bunch-Kaufman tests and the 1x1 / 2x2 pivot inverses are in FP64.
 // WAVES = 8 shortens a lone panel's step (the update is split over eight wavefronts); WAVES = 1
 // leaves no wavefront repeating another's pivot search, which pays when a step holds enough panels
@@ -247,6 +247,25 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long x) {
   return ((unsigned long long)mh << 32) | ml;
 }
 
+// The lane holding the largest a >= 0 over the wavefront (-1 if all are 0): the maximum of a key made
+// of a's bits with the low 6 replaced by 63 - lane, so near-ties go to the lower row.  An FP32 block
+// takes a 32-bit key (one lane reduction), an FP64 block a 64-bit one (two).
+__device__ inline int argmax_lane(double a, int lane) {
+  const unsigned long long key =
+      wave_max_u64(a > 0.0 ? (((unsigned long long)__double_as_longlong(a) & ~63ull) | (unsigned long long)(63 - lane))
+                           : 0ull);
+  return key ? 63 - (int)(key & 63ull) : -1;
+}
+__device__ inline int argmax_lane(float a, int lane) {
+  const unsigned int key = wave_max_u32(a > 0.0f ? ((__float_as_uint(a) & ~63u) | (unsigned int)(63 - lane)) : 0u);
+  return key ? 63 - (int)(key & 63u) : -1;
+}
+// maximum of a >= 0 over the wavefront (non-negative floats order as their bit patterns)
+__device__ inline double wave_max_nonneg(double a) {
+  return __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(a)));
+}
+__device__ inline float wave_max_nonneg(float a) { return __uint_as_float(wave_max_u32(__float_as_uint(a))); }
+
 template <typename T, int WAVES, int WM>
 __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __restrict__ tasks, FrontArgs f,
                                                            T* __restrict__ front) {
@@ -294,13 +313,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
   while (k < w) {
     T v = row_lane ? A[lane][k] : (T)0;
     const int gend = __builtin_amdgcn_readlane(gend_r, k);
-    const double cand = (lane > k && lane < gend) ? (double)fabs(v) : 0.0;
-    const unsigned long long key =
-        wave_max_u64(cand > 0.0 ? (((unsigned long long)__double_as_longlong(cand) & ~63ull) |
-                                   (unsigned long long)(63 - lane))
-                                : 0ull);
-    const int imax = key ? 63 - (int)(key & 63ull) : k;
-    const double colmax = key ? (double)fabs(lane_bcast(v, imax)) : 0.0;
+    const T cand = (lane > k && lane < gend) ? (T)fabs(v) : (T)0;
+    const int am = argmax_lane(cand, lane);
+    const int imax = am >= 0 ? am : k;
+    const double colmax = am >= 0 ? (double)fabs(lane_bcast(v, imax)) : 0.0;
     const double absakk = (double)fabs(lane_bcast(v, k));
     int kind = 1, p = -1, q = -1;
     bool pert = false;
@@ -308,8 +324,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_panel_diag(const int64_t* __rest
       pert = true;
     } else if (absakk < kAlphaBK * colmax) {
       const T u = row_lane ? A[imax][lane] : (T)0;  // row imax
-      const double c2 = (lane >= k && lane < gend && lane != imax) ? (double)fabs(u) : 0.0;
-      const double rowmax = __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(c2)));
+      const T c2 = (lane >= k && lane < gend && lane != imax) ? (T)fabs(u) : (T)0;
+      const double rowmax = (double)wave_max_nonneg(c2);
       if (absakk * rowmax >= kAlphaBK * colmax * colmax) {
         kind = 1;
       } else if ((double)fabs(lane_bcast(u, imax)) >= kAlphaBK * rowmax) {
